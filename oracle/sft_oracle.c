@@ -1,0 +1,675 @@
+/*
+ * sft_oracle.c -- plain, slow, FP64 CPU oracle for the short-Fourier-transform
+ * (SFT) inner product of Tenorio & Gerosa, "Scalable data-analysis framework
+ * for long-duration gravitational waves from compact binaries using short
+ * Fourier transforms" (arXiv:2502.11823).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant generator with the GPU library; the two meet only
+ * through the seeded input generators.
+ *
+ * Every routine follows a passage of the paper, cited by section and equation
+ * label.  Where the paper is silent or garbled the reading taken is named at
+ * the routine (readings R1..R19 are listed in the design notes).
+ *
+ * Parity unpinned: none of the functions below is unpinned; each is checked by
+ * the CPU test-suite against closed forms, library routines (numpy FFT, scipy
+ * Fresnel integrals and Faddeeva function), brute-force sums or invariants.
+ *
+ * Conventions (paper Sec. III.B-III.E):
+ *   T = T_SFT, n = samples per SFT, dt = T/n, df = 1/T, f_k = k/T.
+ *   SFT of segment alpha (Eq. d_SFT):  x~_a[k] = dt * sum_j x(t_a + j dt) exp(-2 pi i j k / n).
+ *   Whitened SFT (reading R1):         d~_a[k] = 2 x~_a[k] / S_a(f_k).
+ *   Kernel in bins (Eqs. fresnel_og and the continuum form that follows it),
+ *   with x = (f_a - f_k) T and beta = fdot_a T^2:
+ *       start reference:    F(x,beta) = int_0^1      exp(i(2 pi x s + pi beta s^2)) ds
+ *       midpoint reference: F(x,beta) = int_{-1/2}^{1/2} exp(i(2 pi x s + pi beta s^2)) ds
+ *   (the midpoint form carries an extra (-1)^k on the data bins, reading R2).
+ *   Coherent sum (Eqs. with_f_1, prod_barbar, efficient, reading R9: one df):
+ *       C_a = sum_k conj(d~'_a[k]) F(kappa_a - k, beta_a),   kappa_a = f_a T
+ *       z_+ = sum_a F+_a A_a exp(i phi_a) C_a,  z_x likewise with Fx_a
+ *       ([d,h]) = A+ Re z_+ + Ax Im z_x
+ *   Norm (reading R11):  hh_+ = sum_a F+_a^2 A_a^2 T / S_a(f_a)  (hh_x likewise)
+ *   SNR  (Eq. det_short, reading R12):  rho = |A+ z_+ - i Ax z_x| / sqrt(A+^2 hh_+ + Ax^2 hh_x)
+ */
+#define _GNU_SOURCE
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846264338327950288
+#define ORC_PIL 3.14159265358979323846264338327950288L
+
+/* kernel selection */
+enum { ORC_K_DIRICHLET = 0, ORC_K_FRESNEL = 1, ORC_K_AUTO = 2, ORC_K_DISCRETE = 3, ORC_K_QUAD = 4 };
+/* waveform time reference */
+enum { ORC_REF_MID = 0, ORC_REF_START = 1 };
+/* waveform model */
+enum { ORC_WF_NEWTON = 0, ORC_WF_PN35 = 1 };
+/* per-template flags (same bit meanings as the library's public flags) */
+enum {
+  ORC_F_OUT_OF_BAND = 1u,
+  ORC_F_TAU_NONPOSITIVE = 2u,
+  ORC_F_TAYLOR_INVALID = 4u,
+  ORC_F_NONFINITE = 8u,
+  ORC_F_EMPTY = 64u
+};
+
+/* ------------------------------------------------------------------------- */
+/* Compensated (Neumaier) summation, used to bound the oracle's own rounding. */
+/* ------------------------------------------------------------------------- */
+typedef struct { double s, c, plain; } orc_sum;
+
+static void orc_sum_add(orc_sum *a, double x)
+{
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+  else a->c += (x - t) + a->s;
+  a->s = t;
+  a->plain += x;
+}
+
+static double orc_sum_get(const orc_sum *a, int compensated)
+{
+  return compensated ? a->s + a->c : a->plain;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Discrete Fourier transforms (Eq. d_SFT).                                   */
+/* ------------------------------------------------------------------------- */
+
+/* In-place forward transform X[k] = sum_j x[j] exp(-2 pi i j k / n).
+ * Radix-2 decimation in time for powers of two; a direct O(n^2) sum otherwise.
+ * Twiddles are taken from cos/sin of the exact angle (no recurrences). */
+static void orc_dft_inplace(double complex *x, long n)
+{
+  if (n <= 1) return;
+  if ((n & (n - 1)) != 0) {
+    double complex *y = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    for (long k = 0; k < n; k++) {
+      double complex s = 0;
+      for (long j = 0; j < n; j++) {
+        long m = (long)(((__int128)j * k) % n);
+        double ang = -2.0 * ORC_PI * (double)m / (double)n;
+        s += x[j] * (cos(ang) + I * sin(ang));
+      }
+      y[k] = s;
+    }
+    memcpy(x, y, sizeof(double complex) * (size_t)n);
+    free(y);
+    return;
+  }
+  /* bit reversal permutation */
+  for (long i = 1, j = 0; i < n; i++) {
+    long bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) { double complex t = x[i]; x[i] = x[j]; x[j] = t; }
+  }
+  for (long len = 2; len <= n; len <<= 1) {
+    long half = len >> 1;
+    for (long k = 0; k < half; k++) {
+      double ang = -2.0 * ORC_PI * (double)k / (double)len;
+      double complex w = cos(ang) + I * sin(ang);
+      for (long i = 0; i < n; i += len) {
+        double complex u = x[i + k], v = x[i + k + half] * w;
+        x[i + k] = u + v;
+        x[i + k + half] = u - v;
+      }
+    }
+  }
+}
+
+/* Forward transform of a real series, out[k] = sum_j x[j] exp(-2 pi i jk/n),
+ * k = 0..n/2, written as interleaved (re, im) pairs. */
+int orc_rdft(const double *x, long n, double *out)
+{
+  double complex *buf = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+  if (!buf) return -1;
+  for (long j = 0; j < n; j++) buf[j] = x[j];
+  orc_dft_inplace(buf, n);
+  for (long k = 0; k <= n / 2; k++) { out[2 * k] = creal(buf[k]); out[2 * k + 1] = cimag(buf[k]); }
+  free(buf);
+  return 0;
+}
+
+/* SFTs of consecutive disjoint segments (Sec. III.B segmentation, Eq. d_SFT):
+ * out[a][k] = dt * sum_{j<n} x[a n + j] exp(-2 pi i j k / n), k = 0..n/2. */
+int orc_make_sfts(const double *x, long n_total, long n, long n_sft, double dt, double *out)
+{
+  if (n_sft * n > n_total) return -1;
+  long nb = n / 2 + 1;
+  double *tmp = (double *)malloc(sizeof(double) * (size_t)(2 * nb));
+  if (!tmp) return -1;
+  for (long a = 0; a < n_sft; a++) {
+    orc_rdft(x + a * n, n, tmp);
+    for (long k = 0; k < 2 * nb; k++) out[a * 2 * nb + k] = dt * tmp[k];
+  }
+  free(tmp);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Fresnel integrals and the auxiliary function G.                           */
+/* ------------------------------------------------------------------------- */
+
+/* E(v) = C(v) + i S(v) = int_0^v exp(i pi t^2 / 2) dt by its Maclaurin series,
+ * summed in extended precision (used for |v| <= 2.5 only). */
+static long double complex orc_fresnel_E_series(long double v)
+{
+  long double complex r = I * (ORC_PIL / 2.0L) * v * v;
+  long double complex t = v, s = v;
+  for (int n = 1; n < 400; n++) {
+    t *= r / (long double)n;
+    long double complex add = t / (long double)(2 * n + 1);
+    s += add;
+    if (cabsl(add) < 1e-24L * (cabsl(s) + 1e-300L)) break;
+  }
+  return s;
+}
+
+/* Faddeeva function w(z) = exp(-z^2) erfc(-i z) for Im z > 0 by the classical
+ * continued fraction of erfc(u), u = -i z, Re u > 0:
+ *   erfc(u) = exp(-u^2)/sqrt(pi) * 1/(u + (1/2)/(u + 1/(u + (3/2)/(u + ...))))
+ * and exp(-z^2) exp(-u^2) = 1.  Evaluated bottom-up at a depth chosen from |u|. */
+static double complex orc_faddeeva_cf(double complex z)
+{
+  double complex u = -I * z;
+  double au = cabs(u);
+  int depth = au < 3.0 ? 2000 : au < 6.0 ? 600 : au < 20.0 ? 200 : 60;
+  double complex f = u;
+  for (int k = depth; k >= 1; k--) f = u + (0.5 * (double)k) / f;
+  return 1.0 / (sqrt(ORC_PI) * f);
+}
+
+double complex orc_faddeeva(double re, double im)
+{
+  return orc_faddeeva_cf(re + I * im);
+}
+
+/* E(v) = C(v) + i S(v) for any real v (odd function). */
+double complex orc_fresnel_E(double v)
+{
+  double av = fabs(v);
+  double complex e;
+  if (av <= 2.5) {
+    e = (double complex)orc_fresnel_E_series((long double)av);
+  } else {
+    /* E(v) = (1+i)/2 - ((1+i)/2) w(zeta) exp(i pi v^2/2), zeta = sqrt(pi)/2 (1+i) v */
+    double complex zeta = 0.5 * sqrt(ORC_PI) * (1.0 + I) * av;
+    double complex w = orc_faddeeva_cf(zeta);
+    e = 0.5 * (1.0 + I) - 0.5 * (1.0 + I) * w * cexp(I * 0.5 * ORC_PI * av * av);
+  }
+  return v < 0 ? -e : e;
+}
+
+/* Auxiliary G(v), v >= 0, defined by E(v) = (1+i)/2 - G(v) exp(i pi v^2 / 2).
+ * G(v) = ((1+i)/2) w(sqrt(pi)/2 (1+i) v); for small v it is formed from the
+ * series of E (no cancellation there since |G| ~ 1/2). */
+double complex orc_fresnel_aux(double v)
+{
+  if (v <= 2.5) {
+    long double vl = (long double)v;
+    long double complex e = orc_fresnel_E_series(vl);
+    long double complex g = (0.5L + 0.5L * I - e) * cexpl(-I * 0.5L * ORC_PIL * vl * vl);
+    return (double complex)g;
+  }
+  double complex zeta = 0.5 * sqrt(ORC_PI) * (1.0 + I) * v;
+  return 0.5 * (1.0 + I) * orc_faddeeva_cf(zeta);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Kernels: the chirp integral I(a,b;x,beta) = int_a^b exp(i(2 pi x s + pi beta s^2)) ds
+ * (Sec. III.C, continuum form of Eq. fresnel_og with s = tau / T).           */
+/* ------------------------------------------------------------------------- */
+
+/* Dirichlet limit beta = 0 (App. B): (exp(2 pi i x b) - exp(2 pi i x a)) / (2 pi i x)
+ * written as exp(i pi x (a+b)) sin(pi x (b-a)) / (pi x), whose x -> 0 limit is b-a. */
+static double complex orc_linear_integral(double a, double b, double x)
+{
+  double arg = ORC_PI * x * (b - a);
+  double s = fabs(arg) < 1e-8 ? (b - a) * (1.0 - arg * arg / 6.0) : sin(arg) / (ORC_PI * x);
+  double ph = ORC_PI * x * (a + b);
+  return s * (cos(ph) + I * sin(ph));
+}
+
+/* Closed form by completing the square (Sec. III.C):
+ *   I = exp(-i pi x^2/beta)/sqrt(2 beta) [E(v_b) - E(v_a)],  v = sqrt(2 beta)(s + x/beta).
+ * Reading R7: with E(v) = sgn(v)[(1+i)/2 - G(|v|) exp(i pi v^2/2)] and
+ * pi v^2/2 - pi x^2/beta = psi(s) = 2 pi x s + pi beta s^2, this becomes
+ *   I = [ (sgn v_b - sgn v_a)(1+i)/2 exp(-i pi x^2/beta)
+ *         - sgn(v_b) G(|v_b|) exp(i psi(b)) + sgn(v_a) G(|v_a|) exp(i psi(a)) ] / sqrt(2 beta),
+ * in which no phase larger than pi beta max(a^2,b^2) appears.  For beta < 0
+ * the integral is the conjugate of the one with (-x, -beta). */
+double complex orc_chirp_integral(double a, double b, double x, double beta)
+{
+  if (beta == 0.0) return orc_linear_integral(a, b, x);
+  if (beta < 0.0) return conj(orc_chirp_integral(a, b, -x, -beta));
+  double sq = sqrt(2.0 * beta);
+  double va = sq * (a + x / beta), vb = sq * (b + x / beta);
+  double psa = 2.0 * ORC_PI * x * a + ORC_PI * beta * a * a;
+  double psb = 2.0 * ORC_PI * x * b + ORC_PI * beta * b * b;
+  double sa = va < 0 ? -1.0 : 1.0, sb = vb < 0 ? -1.0 : 1.0;
+  double complex acc = 0;
+  if (fabs(va) <= 2.5 && fabs(vb) <= 2.5) {
+    /* both ends in the series range: difference of E directly */
+    double ph = -ORC_PI * x * x / beta;
+    return (cos(ph) + I * sin(ph)) * (orc_fresnel_E(vb) - orc_fresnel_E(va)) / sq;
+  }
+  if (sa != sb) {
+    double ph = -ORC_PI * x * x / beta;
+    acc += (sb - sa) * 0.5 * (1.0 + I) * (cos(ph) + I * sin(ph));
+  }
+  acc -= sb * orc_fresnel_aux(fabs(vb)) * (cos(psb) + I * sin(psb));
+  acc += sa * orc_fresnel_aux(fabs(va)) * (cos(psa) + I * sin(psa));
+  return acc / sq;
+}
+
+/* Gauss-Legendre nodes and weights on [-1,1] by Newton's method on P_n. */
+#define ORC_GL_N 20
+static double orc_gl_x[ORC_GL_N], orc_gl_w[ORC_GL_N];
+static int orc_gl_ready = 0;
+
+static void orc_gl_init(void)
+{
+  if (orc_gl_ready) return;
+  const int n = ORC_GL_N;
+  for (int i = 0; i < (n + 1) / 2; i++) {
+    double z = cos(ORC_PI * (i + 0.75) / (n + 0.5)), pp = 0.0;
+    for (int it = 0; it < 100; it++) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int j = 1; j <= n; j++) {
+        double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+      }
+      pp = n * (z * p1 - p2) / (z * z - 1.0);
+      double z1 = z;
+      z = z1 - p1 / pp;
+      if (fabs(z - z1) < 1e-16) {
+        /* recompute the derivative at the converged node */
+        p1 = 1.0; p2 = 0.0;
+        for (int j = 1; j <= n; j++) {
+          double p3 = p2;
+          p2 = p1;
+          p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+        }
+        pp = n * (z * p1 - p2) / (z * z - 1.0);
+        break;
+      }
+    }
+    orc_gl_x[i] = -z;
+    orc_gl_x[n - 1 - i] = z;
+    orc_gl_w[i] = orc_gl_w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+  orc_gl_ready = 1;
+}
+
+/* The same chirp integral by composite Gauss-Legendre quadrature of its
+ * definition, with panels short enough that the phase turns < pi/2 per panel. */
+double complex orc_chirp_integral_quad(double a, double b, double x, double beta)
+{
+  orc_gl_init();
+  double fmax_ = fabs(x) + fabs(beta) * fmax(fabs(a), fabs(b));
+  long P = (long)ceil((b - a) * (4.0 * fmax_ + 2.0));
+  double h = (b - a) / (double)P;
+  double complex s = 0;
+  for (long p = 0; p < P; p++) {
+    double c = a + (p + 0.5) * h;
+    double complex ps = 0;
+    for (int q = 0; q < ORC_GL_N; q++) {
+      double sg = c + 0.5 * h * orc_gl_x[q];
+      double ph = 2.0 * ORC_PI * x * sg + ORC_PI * beta * sg * sg;
+      ps += orc_gl_w[q] * (cos(ph) + I * sin(ph));
+    }
+    s += 0.5 * h * ps;
+  }
+  return s;
+}
+
+/* Discrete kernel (Eq. fresnel_og times df): (1/n) sum_{j<n} exp(i(2 pi x s_j + pi beta s_j^2)),
+ * s_j = j/n - 1/2 (midpoint) or j/n (start).  Test-only: it makes the all-bins
+ * SFT sum equal to the time-domain sum exactly. */
+double complex orc_chirp_discrete(long n, int t_ref, double x, double beta)
+{
+  double complex s = 0;
+  for (long j = 0; j < n; j++) {
+    double sg = (double)j / (double)n - (t_ref == ORC_REF_MID ? 0.5 : 0.0);
+    double ph = 2.0 * ORC_PI * x * sg + ORC_PI * beta * sg * sg;
+    s += cos(ph) + I * sin(ph);
+  }
+  return s / (double)n;
+}
+
+/* Kernel in bins for reference point t_ref. */
+double complex orc_kernel(int kernel, int t_ref, double x, double beta, double beta_switch, long n)
+{
+  double a = (t_ref == ORC_REF_MID) ? -0.5 : 0.0, b = a + 1.0;
+  switch (kernel) {
+  case ORC_K_DIRICHLET: return orc_chirp_integral(a, b, x, 0.0);
+  case ORC_K_FRESNEL: return orc_chirp_integral(a, b, x, beta);
+  case ORC_K_AUTO: return orc_chirp_integral(a, b, x, fabs(beta) <= beta_switch ? 0.0 : beta);
+  case ORC_K_DISCRETE: return orc_chirp_discrete(n, t_ref, x, beta);
+  case ORC_K_QUAD: return orc_chirp_integral_quad(a, b, x, beta);
+  default: return NAN;
+  }
+}
+
+/* Exported wrappers returning (re, im) pairs for the test-suite. */
+void orc_kernel_eval(int kernel, int t_ref, long n, double beta_switch, long count,
+                     const double *x, const double *beta, double *out)
+{
+  for (long i = 0; i < count; i++) {
+    double complex v = orc_kernel(kernel, t_ref, x[i], beta[i], beta_switch, n);
+    out[2 * i] = creal(v);
+    out[2 * i + 1] = cimag(v);
+  }
+}
+
+void orc_fresnel_E_eval(long count, const double *v, double *out)
+{
+  for (long i = 0; i < count; i++) {
+    double complex e = orc_fresnel_E(v[i]);
+    out[2 * i] = creal(e);
+    out[2 * i + 1] = cimag(e);
+  }
+}
+
+void orc_fresnel_aux_eval(long count, const double *v, double *out)
+{
+  for (long i = 0; i < count; i++) {
+    double complex g = orc_fresnel_aux(v[i]);
+    out[2 * i] = creal(g);
+    out[2 * i + 1] = cimag(g);
+  }
+}
+
+void orc_faddeeva_eval(long count, const double *z, double *out)
+{
+  for (long i = 0; i < count; i++) {
+    double complex w = orc_faddeeva_cf(z[2 * i] + I * z[2 * i + 1]);
+    out[2 * i] = creal(w);
+    out[2 * i + 1] = cimag(w);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Waveforms (Sec. II.A: h = Lambda A exp(i phi)).                            */
+/* ------------------------------------------------------------------------- */
+
+/* Leading-order (Newtonian) chirp, reading R3, with M = Mc * T_sun [s] and
+ * tau = t_c - t:
+ *   f      = 5^(3/8) / (8 pi) M^(-5/8) tau^(-3/8)
+ *   phi    = phi_c - 2 (tau / (5 M))^(5/8)
+ *   fdot   = (96/5) pi^(8/3) M^(5/3) f^(11/3)
+ *   fddot  = (11/3) fdot^2 / f
+ *   A      = (pi M f)^(2/3)
+ * out = {A, phi, f, fdot, fddot}.  Returns 0, or -1 when tau <= 0. */
+int orc_newton(double mc, double t_c, double phi_c, double t, double tsun, double *out)
+{
+  double M = mc * tsun, tau = t_c - t;
+  if (!(tau > 0.0)) return -1;
+  double f = pow(5.0, 0.375) / (8.0 * ORC_PI) * pow(M, -0.625) * pow(tau, -0.375);
+  double phi = phi_c - 2.0 * pow(tau / (5.0 * M), 0.625);
+  double fdot = 96.0 / 5.0 * pow(ORC_PI, 8.0 / 3.0) * pow(M, 5.0 / 3.0) * pow(f, 11.0 / 3.0);
+  double fddot = 11.0 / 3.0 * fdot * fdot / f;
+  out[0] = pow(ORC_PI * M * f, 2.0 / 3.0);
+  out[1] = phi;
+  out[2] = f;
+  out[3] = fdot;
+  out[4] = fddot;
+  return 0;
+}
+
+int orc_pn35(double mc, double q, double t_c, double phi_c, double t, double tsun, double *out);
+
+int orc_waveform(int wf, double mc, double q, double t_c, double phi_c, double t, double tsun, double *out)
+{
+  if (wf == ORC_WF_NEWTON) return orc_newton(mc, t_c, phi_c, t, tsun, out);
+  if (wf == ORC_WF_PN35) return orc_pn35(mc, q, t_c, phi_c, t, tsun, out);
+  return -2;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Coherent SFT sum for one template (Eqs. with_f_1, prod_barbar, efficient).  */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  long n_sft, n;       /* SFT count, samples per SFT */
+  double T;            /* T_SFT */
+  long k_lo, n_bins;   /* stored band [k_lo, k_lo + n_bins) */
+  const double *xb;    /* [n_sft][n_bins][2] raw SFT bins (Eq. d_SFT) */
+  const double *psd;   /* [n_sft][n_bins] one-sided PSD */
+  const double *fp, *fx; /* [n_sft] antenna patterns, NULL => F+ = 1, Fx = 0 */
+} orc_data;
+
+/* Whitened bin d~_a[k] = 2 x~_a[k] / S_a(f_k) (reading R1).  Indices outside
+ * [0, n/2] map through d~[-k] = conj(d~[k]) and d~[n-k] = conj(d~[k]) (the
+ * footnote of Sec. III.C).  Returns 0 when the mapped bin is outside the stored
+ * band (the bin then counts as zero), and 2 when its PSD is not positive and
+ * finite (masked bin, counts as zero). */
+static int orc_whitened_bin(const orc_data *D, long a, long k, double complex *out)
+{
+  long n = D->n;
+  long km = ((k % n) + n) % n;
+  int cj = 0;
+  if (km > n / 2) { km = n - km; cj = 1; }
+  long i = km - D->k_lo;
+  *out = 0;
+  if (i < 0 || i >= D->n_bins) return 0;
+  double S = D->psd[a * D->n_bins + i];
+  if (!(S > 0.0) || !isfinite(S)) return 2;
+  double complex v = D->xb[2 * (a * D->n_bins + i)] + I * D->xb[2 * (a * D->n_bins + i) + 1];
+  if (cj) v = conj(v);
+  *out = 2.0 * v / S;
+  return 1;
+}
+
+typedef struct {
+  int K;          /* window half-width; K < 0 => all n bins (test-only) */
+  int kernel;     /* ORC_K_* */
+  int t_ref;      /* ORC_REF_* */
+  double beta_switch;
+  double a_plus, a_cross;
+  double delta_max;  /* Taylor-validity threshold (Eq. max_tsft), <= 0 disables */
+  int compensated;
+} orc_opts;
+
+/* Per-template result: out[0..6] = Re z+, Im z+, Re zx, Im zx, hh+, hhx, rho. */
+static void orc_template_sum(const orc_data *D, const orc_opts *o,
+                             const double *A, const double *phi, const double *f,
+                             const double *fdot, const double *fddot, const unsigned char *use,
+                             double *out, uint32_t *flags, double *tie)
+{
+  orc_sum zpr = {0, 0, 0}, zpi = {0, 0, 0}, zxr = {0, 0, 0}, zxi = {0, 0, 0}, hp = {0, 0, 0}, hx = {0, 0, 0};
+  uint32_t fl = 0;
+  double tie_min = 1.0;
+  double T = D->T;
+  int used = 0;
+  for (long a = 0; a < D->n_sft; a++) {
+    if (!use[a]) continue;
+    used++;
+    double kappa = f[a] * T;          /* instantaneous frequency in bins */
+    double beta = fdot[a] * T * T;    /* drift across the SFT in bins */
+    double kc = floor(kappa + 0.5);   /* window centre, reading R5 */
+    double delta = kappa - kc;
+    double td = 0.5 - fabs(delta);
+    if (td < tie_min) tie_min = td;
+    if (fddot && o->delta_max > 0.0) {
+      /* Eq. max_tsft: frequency residual of the linear model over the segment,
+       * in bins; T/2 lever arm about the midpoint, T about the start. */
+      double lever = (o->t_ref == ORC_REF_MID) ? 0.5 * T : T;
+      double dres = 0.5 * fddot[a] * lever * lever * T;
+      if (dres > o->delta_max) fl |= ORC_F_TAYLOR_INVALID;
+    }
+    long jlo = -o->K, jhi = o->K;
+    if (o->K < 0) { jlo = -D->n / 2; jhi = D->n / 2 - 1; }
+    double complex C = 0;
+    for (long j = jlo; j <= jhi; j++) {
+      long k = (long)kc + j;
+      double complex dk;
+      int st = orc_whitened_bin(D, a, k, &dk);
+      if (st == 0) { fl |= ORC_F_OUT_OF_BAND; continue; }
+      if (st == 2) continue;
+      if (o->t_ref == ORC_REF_MID && (k & 1)) dk = -dk;   /* (-1)^k, reading R2 */
+      double complex W = orc_kernel(o->kernel, o->t_ref, kappa - (double)k, beta, o->beta_switch, D->n);
+      C += conj(dk) * W;
+    }
+    double complex term = A[a] * (cos(phi[a]) + I * sin(phi[a])) * C;
+    double fpa = D->fp ? D->fp[a] : 1.0, fxa = D->fx ? D->fx[a] : 0.0;
+    orc_sum_add(&zpr, fpa * creal(term));
+    orc_sum_add(&zpi, fpa * cimag(term));
+    orc_sum_add(&zxr, fxa * creal(term));
+    orc_sum_add(&zxi, fxa * cimag(term));
+    /* ⟨h,h⟩ per SFT (reading R11): A^2 T / S_a(f_a), S linearly interpolated. */
+    double kf = floor(kappa);
+    double w = kappa - kf;
+    long i0 = (long)kf - D->k_lo;
+    if (i0 < 0 || i0 + 1 >= D->n_bins) { fl |= ORC_F_OUT_OF_BAND; continue; }
+    double S0 = D->psd[a * D->n_bins + i0], S1 = D->psd[a * D->n_bins + i0 + 1];
+    if (!(S0 > 0.0) || !(S1 > 0.0) || !isfinite(S0) || !isfinite(S1)) { fl |= ORC_F_OUT_OF_BAND; continue; }
+    double S = (1.0 - w) * S0 + w * S1;
+    double hterm = A[a] * A[a] * T / S;
+    orc_sum_add(&hp, fpa * fpa * hterm);
+    orc_sum_add(&hx, fxa * fxa * hterm);
+  }
+  int c = o->compensated;
+  out[0] = orc_sum_get(&zpr, c);
+  out[1] = orc_sum_get(&zpi, c);
+  out[2] = orc_sum_get(&zxr, c);
+  out[3] = orc_sum_get(&zxi, c);
+  out[4] = orc_sum_get(&hp, c);
+  out[5] = orc_sum_get(&hx, c);
+  /* rho = max over phi_c of ([d,h]) / sqrt(<h,h>) (Eq. det_short, reading R12):
+   * A+ Re(e^{i phi_c} z+) + Ax Im(e^{i phi_c} zx) = Re(e^{i phi_c} (A+ z+ - i Ax zx)). */
+  double re = o->a_plus * out[0] + o->a_cross * out[3];
+  double im = o->a_plus * out[1] - o->a_cross * out[2];
+  double hh = o->a_plus * o->a_plus * out[4] + o->a_cross * o->a_cross * out[5];
+  if (used == 0 || !(hh > 0.0)) {
+    out[6] = 0.0;
+    fl |= ORC_F_EMPTY;
+  } else {
+    out[6] = sqrt(re * re + im * im) / sqrt(hh);
+  }
+  for (int i = 0; i < 7; i++)
+    if (!isfinite(out[i])) fl |= ORC_F_NONFINITE;
+  *flags = fl;
+  if (tie) *tie = tie_min;
+}
+
+/* Coherent sum for one template given its per-SFT waveform quantities at the
+ * reference time of each SFT (Sec. III.E, Eq. efficient).  use[a] != 0 selects
+ * the SFTs that enter the sum; fddot may be NULL. */
+int orc_ip_params(long n_sft, long n, double T, long k_lo, long n_bins,
+                  const double *xb, const double *psd, const double *fp, const double *fx,
+                  const double *A, const double *phi, const double *f, const double *fdot,
+                  const double *fddot, const unsigned char *use,
+                  int K, int kernel, int t_ref, double beta_switch, double a_plus, double a_cross,
+                  double delta_max, int compensated, double *out, uint32_t *flags, double *tie)
+{
+  orc_data D = {n_sft, n, T, k_lo, n_bins, xb, psd, fp, fx};
+  orc_opts o = {K, kernel, t_ref, beta_switch, a_plus, a_cross, delta_max, compensated};
+  orc_template_sum(&D, &o, A, phi, f, fdot, fddot, use, out, flags, tie);
+  return 0;
+}
+
+/* Template bank: waveform at each SFT's reference time (midpoint t_a + T/2 or
+ * start t_a, reading R2) for SFTs a_first..a_last, then the coherent sum.
+ * SFTs with tau <= 0 are skipped and flagged.  Templates run in parallel. */
+int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
+             const double *t_start, const double *xb, const double *psd,
+             const double *fp, const double *fx,
+             long n_tmpl, int wf, const double *mc, const double *q, const double *t_c,
+             const double *phi_c, const int32_t *a_first, const int32_t *a_last,
+             int K, int kernel, int t_ref, double beta_switch, double a_plus, double a_cross,
+             double tsun, double delta_max, int compensated,
+             double *out, uint32_t *flags, double *tie)
+{
+  orc_data D = {n_sft, n, T, k_lo, n_bins, xb, psd, fp, fx};
+  orc_opts o = {K, kernel, t_ref, beta_switch, a_plus, a_cross, delta_max, compensated};
+  int err = 0;
+#pragma omp parallel
+  {
+    double *buf = (double *)malloc(sizeof(double) * (size_t)(5 * n_sft));
+    unsigned char *use = (unsigned char *)malloc((size_t)n_sft);
+    if (!buf || !use) {
+#pragma omp atomic write
+      err = -1;
+    }
+#pragma omp for schedule(dynamic, 1)
+    for (long m = 0; m < n_tmpl; m++) {
+      if (!buf || !use) continue;
+      double *A = buf, *ph = buf + n_sft, *fr = buf + 2 * n_sft, *fd = buf + 3 * n_sft, *fdd = buf + 4 * n_sft;
+      uint32_t extra = 0;
+      long lo = a_first ? a_first[m] : 0, hi = a_last ? a_last[m] : n_sft - 1;
+      for (long a = 0; a < n_sft; a++) {
+        use[a] = 0;
+        if (a < lo || a > hi) continue;
+        double tref = t_start[a] + (t_ref == ORC_REF_MID ? 0.5 * T : 0.0);
+        double w[5];
+        int st = orc_waveform(wf, mc[m], q ? q[m] : 1.0, t_c[m], phi_c ? phi_c[m] : 0.0, tref, tsun, w);
+        if (st != 0) { extra |= ORC_F_TAU_NONPOSITIVE; continue; }
+        A[a] = w[0]; ph[a] = w[1]; fr[a] = w[2]; fd[a] = w[3]; fdd[a] = w[4];
+        use[a] = 1;
+      }
+      orc_template_sum(&D, &o, A, ph, fr, fd, fdd, use, out + 7 * m, flags + m, tie ? tie + m : NULL);
+      flags[m] |= extra;
+    }
+    free(buf);
+    free(use);
+  }
+  return err;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Brute-force inner products (Eqs. fd_product, td_product, whitened_data).   */
+/* ------------------------------------------------------------------------- */
+
+/* <d,h> = dt * sum_j d_j h_j (discrete Eq. td_product), Neumaier-summed. */
+double orc_td_product(const double *d, const double *h, long N, double dt)
+{
+  orc_sum s = {0, 0, 0};
+  for (long j = 0; j < N; j++) orc_sum_add(&s, d[j] * h[j]);
+  return dt * orc_sum_get(&s, 1);
+}
+
+/* <x,h> = 4 Re sum_{k=0}^{N/2} w_k conj(x~_k) h~_k / S_k df (Eq. fd_product on the
+ * full series, own FFT, x~ = dt X, df = 1/(N dt)); w_k = 1/2 at DC and Nyquist
+ * (N even) so that the one-sided sum covers the spectrum once.  S has N/2+1 entries. */
+double orc_fd_product(const double *x, const double *h, long N, double dt, const double *S)
+{
+  long nb = N / 2 + 1;
+  double *X = (double *)malloc(sizeof(double) * (size_t)(2 * nb));
+  double *H = (double *)malloc(sizeof(double) * (size_t)(2 * nb));
+  if (!X || !H) { free(X); free(H); return NAN; }
+  orc_rdft(x, N, X);
+  orc_rdft(h, N, H);
+  orc_sum s = {0, 0, 0};
+  for (long k = 0; k < nb; k++) {
+    double wk = (k == 0 || (N % 2 == 0 && k == N / 2)) ? 0.5 : 1.0;
+    double re = X[2 * k] * H[2 * k] + X[2 * k + 1] * H[2 * k + 1]; /* Re conj(X) H */
+    orc_sum_add(&s, wk * re * dt * dt / S[k]);
+  }
+  free(X);
+  free(H);
+  double df = 1.0 / ((double)N * dt);
+  return 4.0 * orc_sum_get(&s, 1) * df;
+}
+
+/* Eq. max_tsft: T_SFT(delta) = (2 delta / max fddot)^(1/3). */
+double orc_tsft_max(double delta, double fddot_max)
+{
+  return cbrt(2.0 * delta / fddot_max);
+}
+
+/* ------------------------------------------------------------------------- */
+/* 3.5PN waveform: filled in with the surrogate work; returns -2 until then.  */
+/* ------------------------------------------------------------------------- */
+int orc_pn35(double mc, double q, double t_c, double phi_c, double t, double tsun, double *out)
+{
+  (void)mc; (void)q; (void)t_c; (void)phi_c; (void)t; (void)tsun; (void)out;
+  return -2;
+}
