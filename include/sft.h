@@ -1,0 +1,195 @@
+/*
+ * sft.h -- C ABI of libsft.so: short-Fourier-transform (SFT) inner products of
+ * long-duration compact-binary gravitational-wave templates on one AMD MI355X
+ * (gfx950).  Method: Tenorio & Gerosa, arXiv:2502.11823.
+ *
+ * The library evaluates, for every template of a bank, the SFT approximation of
+ * the inner product <x,h> = 4 Re int x~* h~ / S_n df (Sec. I, Eq. fd_product):
+ *
+ *   ([d,h]) = sum_a A_a Lambda_a exp(i phi_a) C_a                (Sec. III.E, Eq. efficient)
+ *   C_a     = sum_{k = k0-K}^{k0+K} conj(d~'_a[k]) F(kappa_a - k, beta_a)   (Eq. with_f_1)
+ *
+ * with the waveform quantities {A_a, phi_a, f_a, fdot_a} taken at the midpoint of
+ * each SFT, kappa_a = f_a T_SFT, beta_a = fdot_a T_SFT^2, d~_a = 2 x~_a / S_a the
+ * per-SFT whitened data (Sec. III.B), d~'_a[k] = (-1)^k d~_a[k] (midpoint reference)
+ * and F the Fresnel kernel (Sec. III.C) or, when |beta| <= beta_switch, its
+ * Dirichlet limit sinc(x) (App. B).  Lambda_a = F+_a A+ Re + Fx_a Ax Im is the
+ * projector of Sec. II.A.  Per template the library returns
+ *
+ *   z+ = sum_a F+_a A_a exp(i phi_a) C_a,  zx = sum_a Fx_a A_a exp(i phi_a) C_a,
+ *   ([d,h]) = A+ Re z+ + Ax Im zx,
+ *   hh+ = sum_a F+_a^2 A_a^2 T / S_a(f_a),  hhx likewise (the narrow-band <h,h>),
+ *   rho = |A+ z+ - i Ax zx| / sqrt(A+^2 hh+ + Ax^2 hhx)   (phase-maximised SNR,
+ *         Sec. II.B, Eq. det_short).
+ *
+ * Every call returns sft_status: SFT_OK (0) or a negative error code; on error
+ * sft_last_error() returns a thread-local message.  Problems of one template
+ * never fail a call: they set bits of that template's flags word.
+ */
+#ifndef SFT_H
+#define SFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sft_status;
+enum {
+  SFT_OK = 0,
+  SFT_E_INVALID = -1,     /* null pointer, bad size or descriptor field */
+  SFT_E_NOMEM = -2,       /* device or host allocation failed */
+  SFT_E_DEVICE = -3,      /* a HIP runtime call or kernel launch failed */
+  SFT_E_RANGE = -4,       /* a size or option outside the supported range */
+  SFT_E_UNSUPPORTED = -5  /* an option combination the library does not implement */
+};
+
+/* device storage of the whitened SFT bins */
+enum { SFT_STORE_F64 = 0, SFT_STORE_F32 = 1, SFT_STORE_BF16 = 2 };
+/* kernel choice (Sec. III.C, App. B) */
+enum { SFT_KERNEL_DIRICHLET = 0, SFT_KERNEL_FRESNEL = 1, SFT_KERNEL_AUTO = 2 };
+/* arithmetic of the bin contraction and of the sums over SFTs; the waveform
+ * phase, its reduction mod 2 pi and the bin split are FP64 in every mode */
+enum { SFT_PREC_FP64 = 0, SFT_PREC_FP32_KAHAN = 1, SFT_PREC_FP32_NAIVE = 2 };
+/* waveform model */
+enum { SFT_WF_NEWTON = 0 };
+
+/* per-template flag bits */
+enum {
+  SFT_FLAG_OUT_OF_BAND = 1u,      /* a window bin, or a PSD bin of the norm, lies outside the stored band */
+  SFT_FLAG_TAU_NONPOSITIVE = 2u,  /* an SFT of the template's range starts its midpoint at or after t_c; skipped */
+  SFT_FLAG_TAYLOR_INVALID = 4u,   /* fddot T^3 / 8 > delta_max in some SFT (Eq. max_tsft, midpoint lever arm) */
+  SFT_FLAG_NONFINITE = 8u,        /* an output is not finite */
+  SFT_FLAG_EMPTY = 64u            /* no SFT contributed to the norm; rho is set to 0 */
+};
+
+/* Largest window half-width K supported by the scan. */
+#define SFT_K_MAX 64
+
+typedef struct sft_data sft_data; /* opaque; owns every device buffer it refers to */
+
+typedef struct {
+  int32_t n_sft;      /* SFT rows (all detectors); a data gap is an absent row */
+  int32_t n_samples;  /* samples per SFT, n (even); dt = t_sft / n */
+  double t_sft;       /* SFT duration T [s]; bin k has frequency k / T */
+  int32_t k_lo;       /* first stored bin, 0 <= k_lo <= n/2 */
+  int32_t n_bins;     /* stored bins k_lo .. k_lo + n_bins - 1, all <= n/2 */
+  int32_t storage;    /* SFT_STORE_* */
+  int32_t reserved;   /* must be 0 */
+} sft_data_desc;
+
+/*
+ * sft_load_data -- whiten and stage SFTs on the device (Sec. III.B per-SFT
+ * whitening, Eq. d_SFT normalisation).
+ *   desc     : sizes and storage precision.
+ *   t_start  : host [n_sft] start time of each SFT [s].
+ *   x_bins   : host [n_sft][n_bins][2] raw SFT bins (re, im), x~_a[k] = dt sum_j x_j e^{-2 pi i jk/n}.
+ *   psd      : host [n_sft][n_bins] one-sided noise PSD S_a(f_k); a bin whose PSD is not
+ *              positive and finite is masked (contributes zero).
+ *   fplus, fcross : host [n_sft] antenna patterns, or NULL for F+ = 1, Fx = 0.
+ *   hip_stream: hipStream_t (NULL = default stream) for the uploads and the load kernel;
+ *              the call returns after the data are ready on the device.
+ *   out      : receives the handle; release it with sft_free_data.
+ * Host arrays are only read during the call.  Bins of the stored band are
+ * mirrored through d~[-k] = conj(d~[k]) and d~[n-k] = conj(d~[k]) (footnote of
+ * Sec. III.C) when the band reaches DC or Nyquist.  Errors: SFT_E_INVALID (null
+ * pointer, n_sft < 1, odd n, band outside [0, n/2]), SFT_E_NOMEM, SFT_E_DEVICE.
+ */
+sft_status sft_load_data(const sft_data_desc* desc, const double* t_start, const double* x_bins,
+                         const double* psd, const double* fplus, const double* fcross,
+                         void* hip_stream, sft_data** out);
+
+/* Release a handle and its device memory (NULL is a no-op). */
+void sft_free_data(sft_data* data);
+
+typedef struct {
+  int32_t K;            /* window half-width: bins k0-K .. k0+K, 0 <= K <= SFT_K_MAX (Sec. III.C truncation) */
+  int32_t kernel;       /* SFT_KERNEL_* */
+  int32_t precision;    /* SFT_PREC_*: FP64 needs SFT_STORE_F64 data, the FP32 modes need F32 or BF16 data */
+  int32_t waveform;     /* SFT_WF_* */
+  double beta_switch;   /* AUTO kernel: Dirichlet when |fdot T^2| <= beta_switch (bins) */
+  double a_plus;        /* A+ of the projector, used for rho */
+  double a_cross;       /* Ax of the projector, used for rho */
+  double tsun;          /* G M_sun / c^3 [s]; M = Mc * tsun */
+  double delta_max;     /* Taylor-validity threshold in bins (Eq. max_tsft); <= 0 disables the flag */
+} sft_opts;
+
+/* Fill *opts with K = 8, AUTO kernel, FP32_KAHAN, Newtonian waveform,
+ * beta_switch = 1e-7, A+ = 1, Ax = 0, tsun = 4.925490947641267e-6 s, delta_max = 0. */
+void sft_default_opts(sft_opts* opts);
+
+/* Template bank, structure of arrays in DEVICE memory owned by the caller.
+ * Leading-order chirp (Newtonian) with chirp mass mc [Msun], coalescence time
+ * t_c [s] and phase phi_c [rad]: f = (5M/tau)^{3/8}/(8 pi M), phi = phi_c - 2 (tau/5M)^{5/8},
+ * A = (pi M f)^{2/3}, tau = t_c - t.  Template m uses SFT rows a_first[m]..a_last[m]
+ * (inclusive, clamped to the data).  q (mass ratio) is read only by waveforms that
+ * depend on it and may be NULL otherwise; phi_c, a_first, a_last may be NULL
+ * (0, 0, n_sft - 1). */
+typedef struct {
+  const double* mc;
+  const double* q;
+  const double* t_c;
+  const double* phi_c;
+  const int32_t* a_first;
+  const int32_t* a_last;
+} sft_bank;
+
+/* Outputs, DEVICE memory owned by the caller: zp, zx are [n][2] (re, im);
+ * hhp, hhx, rho are [n]; flags is [n]. */
+typedef struct {
+  double* zp;
+  double* zx;
+  double* hhp;
+  double* hhx;
+  double* rho;
+  uint32_t* flags;
+} sft_out;
+
+/*
+ * sft_template_bank_scan -- SFT inner products of n_templates templates against
+ * one data handle (Sec. V.B two-step evaluation, batched over the bank).
+ * Asynchronous on hip_stream (NULL = default stream): inputs must stay valid and
+ * outputs must not be read until the stream reaches this point.  A workspace of
+ * about 56 bytes per template and SFT chunk is taken from the stream-ordered
+ * allocator and returned on the same stream.  Results are bitwise deterministic
+ * for a given bank, data and options.  n_templates == 0 is a no-op.
+ * Errors: SFT_E_INVALID (null pointers), SFT_E_RANGE (K), SFT_E_UNSUPPORTED
+ * (precision/storage or kernel combinations), SFT_E_NOMEM, SFT_E_DEVICE.
+ */
+sft_status sft_template_bank_scan(const sft_data* data, const sft_bank* bank, int64_t n_templates,
+                                  const sft_opts* opts, sft_out* out, void* hip_stream);
+
+/*
+ * sft_inner_product -- one template, host arguments and host results; runs the
+ * bank scan with n = 1 and waits for it.  zp and zx receive (re, im).  Any of the
+ * output pointers may be NULL.  Same errors as sft_template_bank_scan.
+ */
+sft_status sft_inner_product(const sft_data* data, double mc, double q, double t_c, double phi_c,
+                             int32_t a_first, int32_t a_last, const sft_opts* opts,
+                             double zp[2], double zx[2], double* hhp, double* hhx, double* rho,
+                             uint32_t* flags);
+
+/*
+ * Kernel timing for benchmarks.  sft_kernel_timing(n) with n > 0 makes the next n
+ * calls of sft_template_bank_scan (from any thread) record a pair of HIP events on
+ * their stream around their scan kernel; n = 0 stops recording and drops the
+ * records.  sft_kernel_times waits for the recorded events and copies up to max
+ * elapsed times [ms] into ms; it returns the number of recorded scans.  Meant for a
+ * single benchmarking thread.  Errors: SFT_E_DEVICE (event creation), SFT_E_RANGE
+ * (n > 4096).
+ */
+sft_status sft_kernel_timing(int32_t n);
+int32_t sft_kernel_times(float* ms, int32_t max);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* sft_last_error(void);
+
+/* Library version string. */
+const char* sft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFT_H */

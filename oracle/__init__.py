@@ -60,6 +60,7 @@ def _load():
     lib.orc_rdft.argtypes = [P, L, P]
     lib.orc_make_sfts.argtypes = [P, L, L, L, D, P]
     lib.orc_waveform.argtypes = [Int, D, D, D, D, D, D, P]
+    lib.orc_waveform_array.argtypes = [Int, D, D, D, D, P, L, D, P]
     lib.orc_ip_params.argtypes = [L, L, D, L, L, P, P, P, P, P, P, P, P, P, P,
                                   Int, Int, Int, D, D, D, D, Int, P, P, P]
     lib.orc_scan.argtypes = [L, L, D, L, L, P, P, P, P, P,
@@ -147,16 +148,12 @@ def make_sfts(x, n, n_sft, dt):
 # --------------------------------------------------------------------------- waveform
 def waveform(mc, t_c, phi_c, t, q=1.0, wf=WF_NEWTON, tsun=T_SUN):
     """Waveform quantities (A, phi, f, fdot, fddot) at times t; NaN where tau <= 0."""
-    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
-    res = np.full((t.size, 5), np.nan)
-    buf = np.empty(5)
-    lib = _load()
-    for i, ti in enumerate(t):
-        rc = lib.orc_waveform(wf, float(mc), float(q), float(t_c), float(phi_c), float(ti), tsun, _ptr(buf))
-        if rc == -2:
-            raise NotImplementedError("waveform model %d" % wf)
-        if rc == 0:
-            res[i] = buf
+    t = np.ascontiguousarray(np.atleast_1d(np.asarray(t, dtype=np.float64)))
+    res = np.empty((t.size, 5))
+    rc = _load().orc_waveform_array(wf, float(mc), float(q), float(t_c), float(phi_c), _ptr(t), t.size,
+                                    float(tsun), _ptr(res))
+    if rc == -2:
+        raise NotImplementedError("waveform model %d" % wf)
     return res
 
 

@@ -433,6 +433,22 @@ int orc_waveform(int wf, double mc, double q, double t_c, double phi_c, double t
   return -2;
 }
 
+/* Waveform quantities at many times; rows of 5 (A, phi, f, fdot, fddot), NaN where tau <= 0. */
+int orc_waveform_array(int wf, double mc, double q, double t_c, double phi_c, const double *t, long count,
+                       double tsun, double *out)
+{
+  int rc = 0;
+  for (long i = 0; i < count; i++) {
+    int st = orc_waveform(wf, mc, q, t_c, phi_c, t[i], tsun, out + 5 * i);
+    if (st == -2) return -2;
+    if (st != 0) {
+      for (int k = 0; k < 5; k++) out[5 * i + k] = NAN;
+      rc = 1;
+    }
+  }
+  return rc;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Coherent SFT sum for one template (Eqs. with_f_1, prod_barbar, efficient).  */
 /* ------------------------------------------------------------------------- */

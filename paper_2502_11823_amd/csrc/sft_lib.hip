@@ -1,0 +1,758 @@
+// sft_lib.hip -- libsft.so: C ABI (include/sft.h) and gfx950 kernels for the
+// short-Fourier-transform inner product of Tenorio & Gerosa (arXiv:2502.11823).
+//
+// Kernels
+//   load_kernel     : per-SFT whitening d~ = 2 x~ / S (Sec. III.B), conjugation,
+//                     DC/Nyquist mirroring (footnote of Sec. III.C), conversion to the
+//                     storage precision, PSD masking.  Once per dataset.
+//   scan_kernel     : one template per lane, one SFT chunk per grid row.  For every
+//                     SFT of the chunk: FP64 chirp at the SFT midpoint, FP64 phase
+//                     reduction, FP64 bin split, 2K+1 kernel weights and the bin
+//                     contraction (Eq. with_f_1), the coherent accumulation of
+//                     Eq. efficient and of the norm, in FP64 or FP32 (Kahan or plain).
+//                     Writes one partial per (template, chunk).
+//   finalize_kernel : sums the partials of a template in chunk order (FP64), forms
+//                     rho (Eq. det_short) and the flags.
+// Reductions are in a fixed order, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <type_traits>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/sft.h"
+#include "sft_device.h"
+
+using namespace sftk;
+
+// ============================================================================ errors
+static thread_local std::string g_err;
+
+static sft_status fail(sft_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static sft_status fail(sft_status st, const char* fmt, ...)
+{
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_OR_FAIL(call)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? SFT_E_NOMEM : SFT_E_DEVICE, "%s: %s (%s:%d)", \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+extern "C" const char* sft_last_error(void) { return g_err.c_str(); }
+extern "C" const char* sft_version(void) { return "libsft 0.1.0 gfx950"; }
+
+// ============================================================================ kernel timing
+#include <mutex>
+#include <vector>
+static std::mutex g_tmu;
+static std::vector<hipEvent_t> g_ev;   // pairs: [2i] before, [2i+1] after the scan kernel of record i
+static int32_t g_tcap = 0, g_tused = 0;
+
+static void timing_drop()
+{
+  for (hipEvent_t e : g_ev) (void)hipEventDestroy(e);
+  g_ev.clear();
+  g_tcap = g_tused = 0;
+}
+
+extern "C" sft_status sft_kernel_timing(int32_t n)
+{
+  std::lock_guard<std::mutex> lk(g_tmu);
+  timing_drop();
+  if (n <= 0) return SFT_OK;
+  if (n > 4096) return fail(SFT_E_RANGE, "sft_kernel_timing: at most 4096 records");
+  g_ev.resize(2 * (size_t)n, nullptr);
+  for (auto& e : g_ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      e = nullptr;
+      timing_drop();
+      return fail(SFT_E_DEVICE, "sft_kernel_timing: hipEventCreate: %s", hipGetErrorString(r));
+    }
+  }
+  g_tcap = n;
+  return SFT_OK;
+}
+
+extern "C" int32_t sft_kernel_times(float* ms, int32_t max)
+{
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (int32_t i = 0; i < g_tused && i < max; ++i) {
+    float t = -1.f;
+    if (hipEventSynchronize(g_ev[2 * i + 1]) == hipSuccess &&
+        hipEventElapsedTime(&t, g_ev[2 * i], g_ev[2 * i + 1]) != hipSuccess)
+      t = -1.f;
+    if (ms) ms[i] = t;
+  }
+  return g_tused;
+}
+
+// returns the event pair for this scan, or nulls when not recording
+static void timing_slot(hipEvent_t* b, hipEvent_t* e)
+{
+  std::lock_guard<std::mutex> lk(g_tmu);
+  *b = *e = nullptr;
+  if (g_tused < g_tcap) {
+    *b = g_ev[2 * g_tused];
+    *e = g_ev[2 * g_tused + 1];
+    ++g_tused;
+  }
+}
+
+// ============================================================================ data handle
+struct sft_data {
+  int device;
+  int32_t n_sft, n, k_lo, n_bins, storage;
+  int32_t n_ext, k_ext_lo;  // stored rows cover bins k_ext_lo .. k_ext_lo + n_ext - 1 (mirrors included)
+  double T;
+  void* bins;     // [n_sft][n_ext] conj(2 x~ / S) in the storage type
+  void* psd;      // [n_sft][n_bins] S (double for F64 storage, float otherwise); masked -> 0
+  double* t_mid;  // [n_sft]
+  double* fp;     // [n_sft]
+  double* fx;     // [n_sft]
+};
+
+template <typename Bin> __device__ inline void store_bin(Bin* p, double re, double im);
+template <> __device__ inline void store_bin<double2>(double2* p, double re, double im) { *p = make_double2(re, im); }
+template <> __device__ inline void store_bin<float2>(float2* p, double re, double im) { *p = make_float2((float)re, (float)im); }
+template <> __device__ inline void store_bin<bf16x2>(bf16x2* p, double re, double im)
+{
+  bf16x2 v;
+  v.re = f32_to_bf16((float)re);
+  v.im = f32_to_bf16((float)im);
+  *p = v;
+}
+
+template <typename Bin, typename PS>
+__global__ __launch_bounds__(256) void load_kernel(const double* __restrict__ xb, const double* __restrict__ psd,
+                                                   int32_t n_sft, int32_t n, int32_t k_lo, int32_t n_bins,
+                                                   int32_t n_ext, int32_t k_ext_lo,
+                                                   Bin* __restrict__ bins, PS* __restrict__ psd_out)
+{
+  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = (int64_t)n_sft * n_ext;
+  if (gid >= total) return;
+  int64_t a = gid / n_ext;
+  int32_t e = (int32_t)(gid - a * n_ext);
+  int32_t k = k_ext_lo + e;
+  bool cj = false;
+  int32_t km = k;
+  if (km < 0) { km = -km; cj = true; }
+  else if (km > n / 2) { km = n - km; cj = true; }
+  int32_t i = km - k_lo;
+  double re = 0.0, im = 0.0;
+  if (i >= 0 && i < n_bins) {
+    double S = psd[a * n_bins + i];
+    if (S > 0.0 && S <= 1.79769313486231570e308) {
+      re = 2.0 * xb[2 * (a * n_bins + i)] / S;
+      im = 2.0 * xb[2 * (a * n_bins + i) + 1] / S;
+      if (cj) im = -im;
+      im = -im;  // stored operand is conj(d~)
+    }
+  }
+  store_bin<Bin>(bins + gid, re, im);
+  // the PSD rows (original band only)
+  if (!cj && k >= k_lo && k < k_lo + n_bins) {
+    double S = psd[a * n_bins + (k - k_lo)];
+    psd_out[a * n_bins + (k - k_lo)] = (S > 0.0 && S <= 1.79769313486231570e308) ? (PS)S : (PS)0;
+  }
+}
+
+__global__ void meta_kernel(const double* __restrict__ t_start, double T, int32_t n_sft, double* __restrict__ t_mid)
+{
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_sft) t_mid[i] = t_start[i] + 0.5 * T;
+}
+
+extern "C" sft_status sft_load_data(const sft_data_desc* d, const double* t_start, const double* x_bins,
+                                    const double* psd, const double* fplus, const double* fcross,
+                                    void* hip_stream, sft_data** out)
+{
+  if (!d || !t_start || !x_bins || !psd || !out) return fail(SFT_E_INVALID, "sft_load_data: null argument");
+  *out = nullptr;
+  if (d->n_sft < 1 || d->n_samples < 2 || (d->n_samples & 1) || !(d->t_sft > 0.0) || d->reserved != 0)
+    return fail(SFT_E_INVALID, "sft_load_data: bad descriptor (n_sft=%d n=%d T=%g)", d->n_sft, d->n_samples, d->t_sft);
+  if (d->k_lo < 0 || d->n_bins < 1 || d->k_lo + d->n_bins - 1 > d->n_samples / 2)
+    return fail(SFT_E_INVALID, "sft_load_data: band [%d, %d) outside [0, n/2]", d->k_lo, d->k_lo + d->n_bins);
+  if (d->storage != SFT_STORE_F64 && d->storage != SFT_STORE_F32 && d->storage != SFT_STORE_BF16)
+    return fail(SFT_E_INVALID, "sft_load_data: unknown storage %d", d->storage);
+  hipStream_t st = (hipStream_t)hip_stream;
+  sft_data* h = new sft_data();
+  std::memset(h, 0, sizeof(*h));
+  HIP_OR_FAIL(hipGetDevice(&h->device));
+  h->n_sft = d->n_sft;
+  h->n = d->n_samples;
+  h->k_lo = d->k_lo;
+  h->n_bins = d->n_bins;
+  h->storage = d->storage;
+  h->T = d->t_sft;
+  int32_t g_lo = d->k_lo == 0 ? std::min(SFT_K_MAX, d->n_bins - 1) : 0;
+  int32_t g_hi = (d->k_lo + d->n_bins - 1 == d->n_samples / 2) ? std::min(SFT_K_MAX, d->n_bins - 1) : 0;
+  h->k_ext_lo = d->k_lo - g_lo;
+  h->n_ext = d->n_bins + g_lo + g_hi;
+  size_t nb = (size_t)d->n_sft * d->n_bins;
+  size_t ne = (size_t)d->n_sft * h->n_ext;
+  size_t bin_sz = d->storage == SFT_STORE_F64 ? sizeof(double2) : d->storage == SFT_STORE_F32 ? sizeof(float2) : sizeof(bf16x2);
+  size_t ps_sz = d->storage == SFT_STORE_F64 ? sizeof(double) : sizeof(float);
+  double *dx = nullptr, *dp = nullptr, *dts = nullptr;
+  auto cleanup = [&]() {
+    if (dx) (void)hipFree(dx);
+    if (dp) (void)hipFree(dp);
+    if (dts) (void)hipFree(dts);
+  };
+  hipError_t e = hipSuccess;
+  if ((e = hipMalloc(&h->bins, ne * bin_sz)) != hipSuccess || (e = hipMalloc(&h->psd, nb * ps_sz)) != hipSuccess ||
+      (e = hipMalloc(&h->t_mid, d->n_sft * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&h->fp, d->n_sft * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&h->fx, d->n_sft * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&dx, nb * 2 * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&dp, nb * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&dts, d->n_sft * sizeof(double))) != hipSuccess) {
+    cleanup();
+    sft_free_data(h);
+    return fail(e == hipErrorOutOfMemory ? SFT_E_NOMEM : SFT_E_DEVICE, "sft_load_data: hipMalloc: %s", hipGetErrorString(e));
+  }
+  std::string err;
+  do {
+    if ((e = hipMemcpyAsync(dx, x_bins, nb * 2 * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess) break;
+    if ((e = hipMemcpyAsync(dp, psd, nb * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess) break;
+    if ((e = hipMemcpyAsync(dts, t_start, d->n_sft * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess) break;
+    if (fplus) e = hipMemcpyAsync(h->fp, fplus, d->n_sft * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) break;
+    if (fcross) e = hipMemcpyAsync(h->fx, fcross, d->n_sft * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) break;
+    if (!fplus || !fcross) {
+      // defaults F+ = 1, Fx = 0 staged from the host
+      double* tmp = new double[d->n_sft];
+      if (!fplus) {
+        for (int i = 0; i < d->n_sft; i++) tmp[i] = 1.0;
+        e = hipMemcpy(h->fp, tmp, d->n_sft * sizeof(double), hipMemcpyHostToDevice);
+      }
+      if (e == hipSuccess && !fcross) {
+        for (int i = 0; i < d->n_sft; i++) tmp[i] = 0.0;
+        e = hipMemcpy(h->fx, tmp, d->n_sft * sizeof(double), hipMemcpyHostToDevice);
+      }
+      delete[] tmp;
+      if (e != hipSuccess) break;
+    }
+    unsigned blocks = (unsigned)((ne + 255) / 256);
+    switch (d->storage) {
+    case SFT_STORE_F64:
+      hipLaunchKernelGGL((load_kernel<double2, double>), dim3(blocks), dim3(256), 0, st, dx, dp, h->n_sft, h->n, h->k_lo,
+                         h->n_bins, h->n_ext, h->k_ext_lo, (double2*)h->bins, (double*)h->psd);
+      break;
+    case SFT_STORE_F32:
+      hipLaunchKernelGGL((load_kernel<float2, float>), dim3(blocks), dim3(256), 0, st, dx, dp, h->n_sft, h->n, h->k_lo,
+                         h->n_bins, h->n_ext, h->k_ext_lo, (float2*)h->bins, (float*)h->psd);
+      break;
+    default:
+      hipLaunchKernelGGL((load_kernel<bf16x2, float>), dim3(blocks), dim3(256), 0, st, dx, dp, h->n_sft, h->n, h->k_lo,
+                         h->n_bins, h->n_ext, h->k_ext_lo, (bf16x2*)h->bins, (float*)h->psd);
+      break;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    hipLaunchKernelGGL(meta_kernel, dim3((d->n_sft + 255) / 256), dim3(256), 0, st, dts, h->T, h->n_sft, h->t_mid);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    e = hipStreamSynchronize(st);
+  } while (0);
+  cleanup();
+  if (e != hipSuccess) {
+    sft_free_data(h);
+    return fail(SFT_E_DEVICE, "sft_load_data: %s", hipGetErrorString(e));
+  }
+  *out = h;
+  return SFT_OK;
+}
+
+extern "C" void sft_free_data(sft_data* h)
+{
+  if (!h) return;
+  if (h->bins) (void)hipFree(h->bins);
+  if (h->psd) (void)hipFree(h->psd);
+  if (h->t_mid) (void)hipFree(h->t_mid);
+  if (h->fp) (void)hipFree(h->fp);
+  if (h->fx) (void)hipFree(h->fx);
+  delete h;
+}
+
+extern "C" void sft_default_opts(sft_opts* o)
+{
+  if (!o) return;
+  o->K = 8;
+  o->kernel = SFT_KERNEL_AUTO;
+  o->precision = SFT_PREC_FP32_KAHAN;
+  o->waveform = SFT_WF_NEWTON;
+  o->beta_switch = 1e-7;
+  o->a_plus = 1.0;
+  o->a_cross = 0.0;
+  o->tsun = 4.925490947641267e-6;
+  o->delta_max = 0.0;
+}
+
+// ============================================================================ scan
+struct ScanArgs {
+  const void* bins;
+  const void* psd;
+  const double* t_mid;
+  const double* fp;
+  const double* fx;
+  int32_t n_sft, n_ext, k_ext_lo, n_bins, k_lo, K;
+  double T, beta_switch, tsun, delta_max;
+  const double* mc;
+  const double* t_c;
+  const double* phi_c;
+  const int32_t* a_first;
+  const int32_t* a_last;
+  int64_t n_tmpl;
+  int32_t chunk, n_chunks;
+  double* part;      // [n_chunks][6][n_tmpl]
+  uint32_t* pflags;  // [n_chunks][n_tmpl]
+};
+
+enum { KERN_DIRICHLET = 0, KERN_FRESNEL = 1 };  // KERN_FRESNEL also applies the Dirichlet switch
+
+// accumulators
+struct AccKahan {
+  float s = 0.f, c = 0.f;
+  __device__ inline void add(float x)
+  {
+    float y = x - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ inline double get() const { return (double)s - (double)c; }
+};
+struct AccNaive {
+  float s = 0.f;
+  __device__ inline void add(float x) { s += x; }
+  __device__ inline double get() const { return (double)s; }
+};
+struct AccF64 {
+  double s = 0.0;
+  __device__ inline void add(double x) { s += x; }
+  __device__ inline double get() const { return s; }
+};
+
+template <int PREC> struct PrecTraits;
+template <> struct PrecTraits<SFT_PREC_FP64> { using R = double; using Acc = AccF64; };
+template <> struct PrecTraits<SFT_PREC_FP32_KAHAN> { using R = float; using Acc = AccKahan; };
+template <> struct PrecTraits<SFT_PREC_FP32_NAIVE> { using R = float; using Acc = AccNaive; };
+
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <typename Bin, int PREC, int KERN, int KC>
+__global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
+{
+  using R = typename PrecTraits<PREC>::R;
+  using Acc = typename PrecTraits<PREC>::Acc;
+  using PS = typename std::conditional<PREC == SFT_PREC_FP64, double, float>::type;
+
+  __shared__ float2 tab[SFT_G_NINT * (SFT_G_DEG + 1)];
+  if (KERN == KERN_FRESNEL) {
+    for (int i = threadIdx.x; i < SFT_G_NINT * (SFT_G_DEG + 1); i += blockDim.x)
+      tab[i] = make_float2(sft_g_coef[i / (SFT_G_DEG + 1)][i % (SFT_G_DEG + 1)][0],
+                           sft_g_coef[i / (SFT_G_DEG + 1)][i % (SFT_G_DEG + 1)][1]);
+    __syncthreads();
+  }
+
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.n_tmpl) return;
+  const int K = KC >= 0 ? KC : a.K;
+  const int c = blockIdx.y;
+  const int a0 = c * a.chunk;
+  const int a1 = min(a0 + a.chunk, a.n_sft) - 1;
+  const int lo = a.a_first ? max((int)a.a_first[m], a0) : a0;
+  const int hi = a.a_last ? min((int)a.a_last[m], a1) : a1;
+
+  const double T = a.T;
+  const double M = a.mc[m] * a.tsun;
+  const double inv5M = 1.0 / (5.0 * M);
+  const double cf = T / (8.0 * kPi * M);
+  const double tc = a.t_c[m];
+  const double phic = a.phi_c ? a.phi_c[m] : 0.0;
+  const Bin* __restrict__ bins = (const Bin*)a.bins;
+  const PS* __restrict__ psd = (const PS*)a.psd;
+
+  Acc zpr, zpi, zxr, zxi, hp, hx;
+  uint32_t fl = 0;
+
+  for (int al = a0; al <= a1; ++al) {
+    if (al < lo || al > hi) continue;
+    const double tau = tc - a.t_mid[al];
+    if (!(tau > 0.0)) {
+      fl |= kFlagTau;
+      continue;
+    }
+    const Chirp ch = newton_chirp(tau, inv5M, cf, phic, T);
+    if (a.delta_max > 0.0 && ch.dres > a.delta_max) fl |= kFlagTaylor;
+    if (!(ch.kappa < 1.0e9)) {
+      // frequency far above any stored band: no window bin and no norm bin exists
+      fl |= kFlagOOB;
+      continue;
+    }
+    const double kr = floor(ch.kappa + 0.5);
+    const double delta = ch.kappa - kr;
+    const int k0 = (int)kr;
+    const double ph = reduce_2pi(ch.phase);
+    const int i0 = k0 - K - a.k_ext_lo;
+    const bool inband = (i0 >= 0) && (i0 + 2 * K < a.n_ext);
+    const Bin* row = bins + (int64_t)al * a.n_ext;
+
+    R cre = 0, cim = 0;
+    bool dir = true;
+    if constexpr (KERN == KERN_FRESNEL) dir = fabs(ch.beta) <= a.beta_switch;
+    if (dir) {
+      // H_j = sin(pi delta) / (pi (delta - j))
+      const R dl = (R)delta;
+      const R sp = (PREC == SFT_PREC_FP64) ? (R)(sin(kPi * delta) / kPi) : (R)(sinf(kPiF * (float)dl) * kInvPiF);
+#pragma unroll 4
+      for (int j = -K; j <= K; ++j) {
+        const int idx = i0 + j + K;
+        R bre, bim;
+        if (inband || (idx >= 0 && idx < a.n_ext)) {
+          BinIO<Bin>::load(row + idx, bre, bim);
+        } else {
+          fl |= kFlagOOB;
+          continue;
+        }
+        const R x = dl - (R)j;
+        R h;
+        if (PREC == SFT_PREC_FP64) h = (x == (R)0) ? (R)1 : sp / x;
+        else h = (x == (R)0) ? (R)1 : (R)(sp * fast_rcp((float)x));
+        cre = fma(bre, h, cre);
+        cim = fma(bim, h, cim);
+      }
+    } else if constexpr (KERN == KERN_FRESNEL) {
+      // Fresnel weights; beta < 0 through F(x, beta) = conj F(-x, -beta)
+      const bool neg = ch.beta < 0.0;
+      const double bpos = fabs(ch.beta);
+      const double ds64 = neg ? -delta : delta;
+      const float bp = (float)bpos;
+      const float ds = (float)ds64;
+      const float rsb = rsqrtf(bp);
+      const float sq2ob = 1.41421356237309505f * rsb;   // sqrt(2 / beta)
+      const float isq2b = 0.70710678118654752f * rsb;   // 1 / sqrt(2 beta)
+      // E-+ = exp(i(-+pi delta + pi beta / 4)), pi beta / 4 reduced in FP64
+      const float th = (float)reduce_2pi(0.25 * kPi * bpos);
+      float st, ct, sd, cd;
+      sincosf(th, &st, &ct);
+      sincosf(kPiF * ds, &sd, &cd);
+      const float epr = cd * ct - sd * st, epi = sd * ct + cd * st;   // E+
+      const float emr = cd * ct + sd * st, emi = cd * st - sd * ct;   // E-
+      // 1 / beta in FP64 for the stationary phase: FP32 estimate + two Newton steps
+      double ib = (double)(1.0f / bp);
+      ib = ib * fma(-bpos, ib, 2.0);
+      ib = ib * fma(-bpos, ib, 2.0);
+#pragma unroll 2
+      for (int j = -K; j <= K; ++j) {
+        const int idx = i0 + j + K;
+        float bre, bim;
+        if (inband || (idx >= 0 && idx < a.n_ext)) {
+          BinIO<Bin>::load(row + idx, bre, bim);
+        } else {
+          fl |= kFlagOOB;
+          continue;
+        }
+        const int jj = neg ? -j : j;
+        const float x = ds - (float)jj;
+        const float pm = x - 0.5f * bp, pp = x + 0.5f * bp;
+        const float2 em = fres_endpoint(pm, bp, sq2ob, isq2b, tab);
+        const float2 ep = fres_endpoint(pp, bp, sq2ob, isq2b, tab);
+        float hre = (em.x * emr - em.y * emi) - (ep.x * epr - ep.y * epi);
+        float him = (em.x * emi + em.y * emr) - (ep.x * epi + ep.y * epr);
+        if (pm < 0.0f && pp >= 0.0f) {
+          // stationary point inside the SFT: (-1)^j (1+i) exp(-i pi x^2 / beta) / sqrt(2 beta)
+          const double x64 = ds64 - (double)jj;
+          const double hq = x64 * x64 * ib;
+          const float r = (float)(hq - 2.0 * rint(0.5 * hq));
+          float sr, cr;
+          sincosf(kPiF * r, &sr, &cr);
+          const float sg = (jj & 1) ? -isq2b : isq2b;
+          hre = fmaf(sg, cr + sr, hre);
+          him = fmaf(sg, cr - sr, him);
+        }
+        if (neg) him = -him;
+        cre = fmaf(bre, hre, fmaf(-bim, him, cre));
+        cim = fmaf(bre, him, fmaf(bim, hre, cim));
+      }
+    }
+    // term = (-1)^{k0} A exp(i phi) C
+    R pc, ps;
+    if (PREC == SFT_PREC_FP64) {
+      double s_, c_;
+      sincos(ph, &s_, &c_);
+      ps = (R)s_;
+      pc = (R)c_;
+    } else {
+      float s_, c_;
+      sincosf((float)ph, &s_, &c_);
+      ps = (R)s_;
+      pc = (R)c_;
+    }
+    const R amp = (R)ch.amp;
+    const R as = (k0 & 1) ? -amp : amp;
+    const R tre = as * (pc * cre - ps * cim);
+    const R tim = as * (pc * cim + ps * cre);
+    const R fpa = (R)a.fp[al];
+    const R fxa = (R)a.fx[al];
+    zpr.add(fpa * tre);
+    zpi.add(fpa * tim);
+    zxr.add(fxa * tre);
+    zxi.add(fxa * tim);
+    // norm term A^2 T / S(f), S linear between bins floor(kappa) and floor(kappa) + 1
+    const double kfl = floor(ch.kappa);
+    const int ip = (int)kfl - a.k_lo;
+    if (ip < 0 || ip + 1 >= a.n_bins) {
+      fl |= kFlagOOB;
+      continue;
+    }
+    const R S0 = (R)psd[(int64_t)al * a.n_bins + ip];
+    const R S1 = (R)psd[(int64_t)al * a.n_bins + ip + 1];
+    if (!(S0 > (R)0) || !(S1 > (R)0)) {
+      fl |= kFlagOOB;
+      continue;
+    }
+    const R w = (R)(ch.kappa - kfl);
+    const R S = ((R)1 - w) * S0 + w * S1;
+    R hterm;
+    if (PREC == SFT_PREC_FP64) hterm = amp * amp * (R)T / S;
+    else hterm = amp * amp * (R)T * (R)fast_rcp((float)S);
+    hp.add(fpa * fpa * hterm);
+    hx.add(fxa * fxa * hterm);
+  }
+
+  const int64_t n = a.n_tmpl;
+  double* p = a.part + (int64_t)c * 6 * n + m;
+  p[0] = zpr.get();
+  p[n] = zpi.get();
+  p[2 * n] = zxr.get();
+  p[3 * n] = zxi.get();
+  p[4 * n] = hp.get();
+  p[5 * n] = hx.get();
+  a.pflags[(int64_t)c * n + m] = fl;
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ part, const uint32_t* __restrict__ pflags,
+                                                       int64_t n, int32_t n_chunks, double a_plus, double a_cross,
+                                                       double* __restrict__ zp, double* __restrict__ zx,
+                                                       double* __restrict__ hhp, double* __restrict__ hhx,
+                                                       double* __restrict__ rho, uint32_t* __restrict__ flags)
+{
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  uint32_t fl = 0;
+  for (int c = 0; c < n_chunks; ++c) {
+    const double* p = part + (int64_t)c * 6 * n + m;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v[q] += p[q * n];
+    fl |= pflags[(int64_t)c * n + m];
+  }
+  const double re = a_plus * v[0] + a_cross * v[3];
+  const double im = a_plus * v[1] - a_cross * v[2];
+  const double hh = a_plus * a_plus * v[4] + a_cross * a_cross * v[5];
+  double r;
+  if (!(hh > 0.0)) {
+    r = 0.0;
+    fl |= kFlagEmpty;
+  } else {
+    r = sqrt(re * re + im * im) / sqrt(hh);
+  }
+  bool fin = isfinite(r);
+  for (int q = 0; q < 6; ++q) fin = fin && isfinite(v[q]);
+  if (!fin) fl |= kFlagNonfinite;
+  zp[2 * m] = v[0];
+  zp[2 * m + 1] = v[1];
+  zx[2 * m] = v[2];
+  zx[2 * m + 1] = v[3];
+  hhp[m] = v[4];
+  hhx[m] = v[5];
+  rho[m] = r;
+  flags[m] = fl;
+}
+
+// ---------------------------------------------------------------------------- dispatch
+template <typename Bin, int PREC, int KERN>
+static hipError_t launch_k(const ScanArgs& a, dim3 grid, hipStream_t st)
+{
+  switch (a.K) {
+  case 4: hipLaunchKernelGGL((scan_kernel<Bin, PREC, KERN, 4>), grid, dim3(256), 0, st, a); break;
+  case 8: hipLaunchKernelGGL((scan_kernel<Bin, PREC, KERN, 8>), grid, dim3(256), 0, st, a); break;
+  case 32: hipLaunchKernelGGL((scan_kernel<Bin, PREC, KERN, 32>), grid, dim3(256), 0, st, a); break;
+  default: hipLaunchKernelGGL((scan_kernel<Bin, PREC, KERN, -1>), grid, dim3(256), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename Bin, int PREC>
+static hipError_t launch_kern(const ScanArgs& a, int kern, dim3 grid, hipStream_t st)
+{
+  if (kern == KERN_DIRICHLET) return launch_k<Bin, PREC, KERN_DIRICHLET>(a, grid, st);
+  return launch_k<Bin, PREC, KERN_FRESNEL>(a, grid, st);
+}
+
+static int choose_chunks(int64_t n, int32_t n_sft)
+{
+  // enough template-waves x chunks to keep ~16 waves resident per CU on 256 CUs
+  const int64_t target_waves = 256 * 16;
+  int64_t tw = (n + 63) / 64;
+  int64_t nc = (target_waves + tw - 1) / tw;
+  int64_t max_nc = std::max<int64_t>(1, n_sft / 8);
+  nc = std::min<int64_t>(std::max<int64_t>(nc, 1), max_nc);
+  return (int)nc;
+}
+
+static sft_status validate_scan(const sft_data* d, const sft_opts* o)
+{
+  if (!d || !o) return fail(SFT_E_INVALID, "scan: null data or options");
+  if (o->K < 0 || o->K > SFT_K_MAX) return fail(SFT_E_RANGE, "scan: K=%d outside [0, %d]", o->K, SFT_K_MAX);
+  if (o->kernel != SFT_KERNEL_DIRICHLET && o->kernel != SFT_KERNEL_FRESNEL && o->kernel != SFT_KERNEL_AUTO)
+    return fail(SFT_E_INVALID, "scan: unknown kernel %d", o->kernel);
+  if (o->waveform != SFT_WF_NEWTON) return fail(SFT_E_UNSUPPORTED, "scan: waveform %d not available", o->waveform);
+  if (!(o->tsun > 0.0)) return fail(SFT_E_INVALID, "scan: tsun must be positive");
+  if (o->precision == SFT_PREC_FP64) {
+    if (d->storage != SFT_STORE_F64) return fail(SFT_E_UNSUPPORTED, "scan: FP64 precision needs F64 storage");
+    if (o->kernel != SFT_KERNEL_DIRICHLET) return fail(SFT_E_UNSUPPORTED, "scan: FP64 precision supports the Dirichlet kernel only");
+  } else if (o->precision == SFT_PREC_FP32_KAHAN || o->precision == SFT_PREC_FP32_NAIVE) {
+    if (d->storage == SFT_STORE_F64) return fail(SFT_E_UNSUPPORTED, "scan: FP32 precision needs F32 or BF16 storage");
+  } else {
+    return fail(SFT_E_INVALID, "scan: unknown precision %d", o->precision);
+  }
+  return SFT_OK;
+}
+
+extern "C" sft_status sft_template_bank_scan(const sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o,
+                                             sft_out* out, void* hip_stream)
+{
+  sft_status s = validate_scan(d, o);
+  if (s != SFT_OK) return s;
+  if (!bank || !out) return fail(SFT_E_INVALID, "scan: null bank or output");
+  if (n < 0) return fail(SFT_E_INVALID, "scan: negative template count");
+  if (n == 0) return SFT_OK;
+  if (!bank->mc || !bank->t_c) return fail(SFT_E_INVALID, "scan: bank.mc and bank.t_c are required");
+  if (!out->zp || !out->zx || !out->hhp || !out->hhx || !out->rho || !out->flags)
+    return fail(SFT_E_INVALID, "scan: every output array is required");
+  if (n > (int64_t)INT32_MAX * 256) return fail(SFT_E_RANGE, "scan: too many templates");
+  hipStream_t st = (hipStream_t)hip_stream;
+
+  ScanArgs a;
+  a.bins = d->bins;
+  a.psd = d->psd;
+  a.t_mid = d->t_mid;
+  a.fp = d->fp;
+  a.fx = d->fx;
+  a.n_sft = d->n_sft;
+  a.n_ext = d->n_ext;
+  a.k_ext_lo = d->k_ext_lo;
+  a.n_bins = d->n_bins;
+  a.k_lo = d->k_lo;
+  a.K = o->K;
+  a.T = d->T;
+  // the FRESNEL kernel uses the Dirichlet limit only at beta == 0
+  a.beta_switch = o->kernel == SFT_KERNEL_AUTO ? o->beta_switch : 0.0;
+  a.tsun = o->tsun;
+  a.delta_max = o->delta_max;
+  a.mc = bank->mc;
+  a.t_c = bank->t_c;
+  a.phi_c = bank->phi_c;
+  a.a_first = bank->a_first;
+  a.a_last = bank->a_last;
+  a.n_tmpl = n;
+  a.n_chunks = choose_chunks(n, d->n_sft);
+  a.chunk = (d->n_sft + a.n_chunks - 1) / a.n_chunks;
+  a.n_chunks = (d->n_sft + a.chunk - 1) / a.chunk;
+
+  size_t part_bytes = (size_t)a.n_chunks * 6 * n * sizeof(double);
+  size_t flag_bytes = (size_t)a.n_chunks * n * sizeof(uint32_t);
+  void* ws = nullptr;
+  HIP_OR_FAIL(hipMallocAsync(&ws, part_bytes + flag_bytes, st));
+  a.part = (double*)ws;
+  a.pflags = (uint32_t*)((char*)ws + part_bytes);
+
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)a.n_chunks);
+  const int kern = o->kernel == SFT_KERNEL_DIRICHLET ? KERN_DIRICHLET : KERN_FRESNEL;
+  hipEvent_t ev_b, ev_e;
+  timing_slot(&ev_b, &ev_e);
+  if (ev_b) (void)hipEventRecord(ev_b, st);
+  hipError_t e;
+  if (o->precision == SFT_PREC_FP64) {
+    e = launch_k<double2, SFT_PREC_FP64, KERN_DIRICHLET>(a, grid, st);
+  } else if (d->storage == SFT_STORE_F32) {
+    e = o->precision == SFT_PREC_FP32_KAHAN ? launch_kern<float2, SFT_PREC_FP32_KAHAN>(a, kern, grid, st)
+                                            : launch_kern<float2, SFT_PREC_FP32_NAIVE>(a, kern, grid, st);
+  } else {
+    e = o->precision == SFT_PREC_FP32_KAHAN ? launch_kern<bf16x2, SFT_PREC_FP32_KAHAN>(a, kern, grid, st)
+                                            : launch_kern<bf16x2, SFT_PREC_FP32_NAIVE>(a, kern, grid, st);
+  }
+  if (ev_e) (void)hipEventRecord(ev_e, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.part, a.pflags, n,
+                       a.n_chunks, o->a_plus, o->a_cross, out->zp, out->zx, out->hhp, out->hhx, out->rho, out->flags);
+    e = hipGetLastError();
+  }
+  hipError_t e2 = hipFreeAsync(ws, st);
+  if (e != hipSuccess) return fail(SFT_E_DEVICE, "scan: launch failed: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(SFT_E_DEVICE, "scan: hipFreeAsync: %s", hipGetErrorString(e2));
+  return SFT_OK;
+}
+
+extern "C" sft_status sft_inner_product(const sft_data* d, double mc, double q, double t_c, double phi_c,
+                                        int32_t a_first, int32_t a_last, const sft_opts* o, double zp[2],
+                                        double zx[2], double* hhp, double* hhx, double* rho, uint32_t* flags)
+{
+  sft_status s = validate_scan(d, o);
+  if (s != SFT_OK) return s;
+  // one device block: 4 doubles in + 2 ints in, 7 doubles + 1 flag out
+  struct Blk {
+    double mc, q, tc, phic;
+    int32_t af, al;
+    double zp[2], zx[2], hhp, hhx, rho;
+    uint32_t fl;
+  };
+  Blk h{};
+  h.mc = mc;
+  h.q = q;
+  h.tc = t_c;
+  h.phic = phi_c;
+  h.af = a_first;
+  h.al = a_last;
+  Blk* dv = nullptr;
+  HIP_OR_FAIL(hipMalloc(&dv, sizeof(Blk)));
+  hipError_t e = hipMemcpy(dv, &h, sizeof(Blk), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dv);
+    return fail(SFT_E_DEVICE, "sft_inner_product: %s", hipGetErrorString(e));
+  }
+  sft_bank b{&dv->mc, &dv->q, &dv->tc, &dv->phic, &dv->af, &dv->al};
+  sft_out ou{dv->zp, dv->zx, &dv->hhp, &dv->hhx, &dv->rho, &dv->fl};
+  s = sft_template_bank_scan(d, &b, 1, o, &ou, nullptr);
+  if (s == SFT_OK) {
+    e = hipMemcpy(&h, dv, sizeof(Blk), hipMemcpyDeviceToHost);  // waits for the default stream
+    if (e != hipSuccess) s = fail(SFT_E_DEVICE, "sft_inner_product: %s", hipGetErrorString(e));
+  }
+  (void)hipFree(dv);
+  if (s != SFT_OK) return s;
+  if (zp) { zp[0] = h.zp[0]; zp[1] = h.zp[1]; }
+  if (zx) { zx[0] = h.zx[0]; zx[1] = h.zx[1]; }
+  if (hhp) *hhp = h.hhp;
+  if (hhx) *hhx = h.hhx;
+  if (rho) *rho = h.rho;
+  if (flags) *flags = h.fl;
+  return SFT_OK;
+}

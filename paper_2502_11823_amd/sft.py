@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libsft.so (C ABI in include/sft.h).
+
+Argument marshalling only: every step of the SFT inner product runs in the HIP
+kernels of libsft.so.  PyTorch provides device memory and streams.  If the
+library has not been built, ``lib()`` raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsft.so")
+
+SFT_OK = 0
+STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
+KERNEL = {"dirichlet": 0, "fresnel": 1, "auto": 2}
+PRECISION = {"fp64": 0, "fp32_kahan": 1, "fp32_naive": 2}
+WAVEFORM = {"newton": 0}
+FLAG_OUT_OF_BAND, FLAG_TAU_NONPOSITIVE, FLAG_TAYLOR_INVALID, FLAG_NONFINITE, FLAG_EMPTY = 1, 2, 4, 8, 64
+K_MAX = 64
+T_SUN = 4.925490947641267e-6
+
+
+class SFTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("libsft status %d: %s" % (status, msg))
+        self.status = status
+
+
+class DataDesc(ctypes.Structure):
+    _fields_ = [("n_sft", ctypes.c_int32), ("n_samples", ctypes.c_int32), ("t_sft", ctypes.c_double),
+                ("k_lo", ctypes.c_int32), ("n_bins", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("waveform", ctypes.c_int32), ("beta_switch", ctypes.c_double), ("a_plus", ctypes.c_double),
+                ("a_cross", ctypes.c_double), ("tsun", ctypes.c_double), ("delta_max", ctypes.c_double)]
+
+
+class Bank(ctypes.Structure):
+    _fields_ = [("mc", ctypes.c_void_p), ("q", ctypes.c_void_p), ("t_c", ctypes.c_void_p),
+                ("phi_c", ctypes.c_void_p), ("a_first", ctypes.c_void_p), ("a_last", ctypes.c_void_p)]
+
+
+class Out(ctypes.Structure):
+    _fields_ = [("zp", ctypes.c_void_p), ("zx", ctypes.c_void_p), ("hhp", ctypes.c_void_p),
+                ("hhx", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
+EXPORTS = ["sft_load_data", "sft_free_data", "sft_default_opts", "sft_template_bank_scan",
+           "sft_inner_product", "sft_last_error", "sft_version", "sft_kernel_timing", "sft_kernel_times"]
+
+_lib = None
+
+
+def lib():
+    """Load libsft.so (raises if it is missing: build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsft.so not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    L.sft_load_data.argtypes = [ctypes.POINTER(DataDesc), P, P, P, P, P, P, ctypes.POINTER(P)]
+    L.sft_load_data.restype = ctypes.c_int32
+    L.sft_free_data.argtypes = [P]
+    L.sft_free_data.restype = None
+    L.sft_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.sft_default_opts.restype = None
+    L.sft_template_bank_scan.argtypes = [P, ctypes.POINTER(Bank), ctypes.c_int64, ctypes.POINTER(Opts),
+                                         ctypes.POINTER(Out), P]
+    L.sft_template_bank_scan.restype = ctypes.c_int32
+    D = ctypes.c_double
+    L.sft_inner_product.argtypes = [P, D, D, D, D, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Opts),
+                                    P, P, P, P, P, P]
+    L.sft_inner_product.restype = ctypes.c_int32
+    L.sft_last_error.argtypes = []
+    L.sft_last_error.restype = ctypes.c_char_p
+    L.sft_version.argtypes = []
+    L.sft_version.restype = ctypes.c_char_p
+    L.sft_kernel_timing.argtypes = [ctypes.c_int32]
+    L.sft_kernel_timing.restype = ctypes.c_int32
+    L.sft_kernel_times.argtypes = [P, ctypes.c_int32]
+    L.sft_kernel_times.restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().sft_last_error().decode()
+
+
+def _check(status: int):
+    if status != SFT_OK:
+        raise SFTError(status, last_error())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def make_opts(K=8, kernel="auto", precision="fp32_kahan", waveform="newton", beta_switch=1e-7,
+              a_plus=1.0, a_cross=0.0, tsun=T_SUN, delta_max=0.0) -> Opts:
+    o = Opts()
+    lib().sft_default_opts(ctypes.byref(o))
+    o.K = int(K)
+    o.kernel = KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
+    o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    o.waveform = WAVEFORM[waveform] if isinstance(waveform, str) else int(waveform)
+    o.beta_switch = float(beta_switch)
+    o.a_plus = float(a_plus)
+    o.a_cross = float(a_cross)
+    o.tsun = float(tsun)
+    o.delta_max = float(delta_max)
+    return o
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class SFTData:
+    """Device-resident whitened SFTs (owns an sft_data handle)."""
+
+    def __init__(self, t_start, n_samples, t_sft, k_lo, x_bins, psd, fplus=None, fcross=None,
+                 storage="f32", stream=None):
+        xb = np.asarray(x_bins)
+        if np.iscomplexobj(xb):
+            xb = np.stack([xb.real, xb.imag], axis=-1)
+        xb = np.ascontiguousarray(xb, dtype=np.float64)
+        n_sft, n_bins = xb.shape[0], xb.shape[1]
+        psd = np.ascontiguousarray(np.broadcast_to(psd, (n_sft, n_bins)), dtype=np.float64)
+        self._keep = (_f64(t_start), xb, psd, _f64(fplus), _f64(fcross))
+        desc = DataDesc(n_sft, int(n_samples), float(t_sft), int(k_lo), n_bins, STORAGE[storage], 0)
+        h = ctypes.c_void_p()
+        st = _stream_ptr(stream) if stream is not None else None
+        _check(lib().sft_load_data(ctypes.byref(desc), _p(self._keep[0]), _p(xb), _p(psd),
+                                   _p(self._keep[3]), _p(self._keep[4]), st, ctypes.byref(h)))
+        self.handle = h
+        self.n_sft, self.n_bins, self.storage = n_sft, n_bins, storage
+        self.t_sft, self.n_samples, self.k_lo = float(t_sft), int(n_samples), int(k_lo)
+        self._keep = None
+
+    @classmethod
+    def from_workload(cls, w, storage="f32", stream=None):
+        return cls(w.t_start, w.n_samples, w.t_sft, w.k_lo, w.x_bins, w.psd, w.fplus, w.fcross,
+                   storage=storage, stream=stream)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().sft_free_data(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bank_to_device(bank: Dict[str, np.ndarray], device="cuda"):
+    import torch
+    out = {}
+    for k in ("mc", "q", "t_c", "phi_c"):
+        if k in bank and bank[k] is not None:
+            out[k] = torch.as_tensor(np.ascontiguousarray(bank[k], dtype=np.float64), device=device)
+    for k in ("a_first", "a_last"):
+        if k in bank and bank[k] is not None:
+            out[k] = torch.as_tensor(np.ascontiguousarray(bank[k], dtype=np.int32), device=device)
+    return out
+
+
+def alloc_out(n: int, device="cuda"):
+    import torch
+    return {"zp": torch.empty((n, 2), dtype=torch.float64, device=device),
+            "zx": torch.empty((n, 2), dtype=torch.float64, device=device),
+            "hhp": torch.empty(n, dtype=torch.float64, device=device),
+            "hhx": torch.empty(n, dtype=torch.float64, device=device),
+            "rho": torch.empty(n, dtype=torch.float64, device=device),
+            "flags": torch.empty(n, dtype=torch.int32, device=device)}
+
+
+def _tp(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _bank_struct(bank_t):
+    for k, t in bank_t.items():
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("bank array %s must be a contiguous device tensor" % k)
+    return Bank(_tp(bank_t.get("mc")), _tp(bank_t.get("q")), _tp(bank_t.get("t_c")),
+                _tp(bank_t.get("phi_c")), _tp(bank_t.get("a_first")), _tp(bank_t.get("a_last")))
+
+
+def _out_struct(out):
+    return Out(_tp(out["zp"]), _tp(out["zx"]), _tp(out["hhp"]), _tp(out["hhx"]), _tp(out["rho"]),
+               _tp(out["flags"]))
+
+
+def template_bank_scan(data: SFTData, bank_t, opts: Opts, out=None, stream=None, n=None):
+    """Asynchronous bank scan on ``stream`` (default: torch's current stream)."""
+    n = int(bank_t["mc"].numel()) if n is None else int(n)
+    if out is None:
+        out = alloc_out(n, device=bank_t["mc"].device)
+    b = _bank_struct(bank_t)
+    o = _out_struct(out)
+    _check(lib().sft_template_bank_scan(data.handle, ctypes.byref(b), n, ctypes.byref(opts),
+                                        ctypes.byref(o), _stream_ptr(stream)))
+    return out
+
+
+def inner_product(data: SFTData, mc, t_c, phi_c=0.0, q=1.0, a_first=0, a_last=None, opts: Opts = None):
+    """One template, host in / host out (synchronous)."""
+    opts = make_opts() if opts is None else opts
+    a_last = data.n_sft - 1 if a_last is None else a_last
+    zp = (ctypes.c_double * 2)()
+    zx = (ctypes.c_double * 2)()
+    hhp, hhx, rho = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    fl = ctypes.c_uint32()
+    _check(lib().sft_inner_product(data.handle, float(mc), float(q), float(t_c), float(phi_c),
+                                   int(a_first), int(a_last), ctypes.byref(opts),
+                                   ctypes.cast(zp, ctypes.c_void_p), ctypes.cast(zx, ctypes.c_void_p),
+                                   ctypes.cast(ctypes.pointer(hhp), ctypes.c_void_p),
+                                   ctypes.cast(ctypes.pointer(hhx), ctypes.c_void_p),
+                                   ctypes.cast(ctypes.pointer(rho), ctypes.c_void_p),
+                                   ctypes.cast(ctypes.pointer(fl), ctypes.c_void_p)))
+    return {"zp": zp[0] + 1j * zp[1], "zx": zx[0] + 1j * zx[1], "hhp": hhp.value, "hhx": hhx.value,
+            "rho": rho.value, "flags": fl.value}
+
+
+def kernel_timing(n: int):
+    """Record HIP events around the scan kernel of the next n bank scans (0 stops)."""
+    _check(lib().sft_kernel_timing(int(n)))
+
+
+def kernel_times(max_records: int = 4096):
+    """Elapsed milliseconds of the recorded scan kernels (waits for them)."""
+    buf = (ctypes.c_float * max_records)()
+    n = lib().sft_kernel_times(ctypes.cast(buf, ctypes.c_void_p), max_records)
+    return [buf[i] for i in range(min(n, max_records))]

@@ -1,0 +1,228 @@
+"""GPU parity: the HIP bank scan against the FP64 oracle, element by element.
+
+Metric (per template, per polarisation): e = |z_gpu - z_orc| / max(|z_orc|, sqrt(hh_orc)),
+the error in units of the noise standard deviation of <n,h> when |z| is small and
+relative otherwise.  Bars: e <= 1e-6 on z (spec bound for <x,h>), relative
+error <= 1e-5 on rho, <= 1e-6 on hh, flags bit-exact.  Templates whose window
+centre sits within 1e-9 bins of a rounding tie (both sides decide k0 in FP64 but
+by different formulae) are excluded from the flag/z comparison and counted.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_11823_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2502_11823_amd import sft  # noqa: E402
+
+KERN = {"dirichlet": oracle.K_DIRICHLET, "fresnel": oracle.K_FRESNEL, "auto": oracle.K_AUTO}
+
+
+def gpu_scan(data, bank, **kw):
+    opts = sft.make_opts(**kw)
+    res = sft.template_bank_scan(data, sft.bank_to_device(bank), opts)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in res.items()}
+    out["zp"] = out["zp"][:, 0] + 1j * out["zp"][:, 1]
+    out["zx"] = out["zx"][:, 0] + 1j * out["zx"][:, 1]
+    out["flags"] = out["flags"].astype(np.uint32)
+    return out
+
+
+def orc_scan(w, bank, x_bins=None, psd=None, **kw):
+    od = oracle.SFTData(w.t_start, w.n_samples, w.t_sft, w.k_lo, w.x_bins if x_bins is None else x_bins,
+                        w.psd if psd is None else psd, w.fplus, w.fcross)
+    kw = dict(kw)
+    kw.pop("precision", None)
+    kw["kernel"] = KERN[kw.get("kernel", "auto")]
+    return oracle.scan(od, bank["mc"], bank["t_c"], phi_c=bank["phi_c"], a_first=bank["a_first"],
+                       a_last=bank["a_last"], **kw)
+
+
+def compare(g, o, idx=None, tol_z=1e-6, tol_rho=1e-5, tol_hh=1e-6, label=""):
+    if idx is not None:
+        g = {k: v[idx] for k, v in g.items()}
+    ok = o["tie"] > 1e-9
+    n_tie = int(np.sum(~ok))
+    assert n_tie <= max(1, len(ok) // 1000), "too many rounding ties: %d" % n_tie
+    hh = np.maximum(o["hhp"], 1e-300)
+    hx = np.maximum(o["hhx"], 1e-300)
+    ep = np.abs(g["zp"] - o["zp"]) / np.maximum(np.abs(o["zp"]), np.sqrt(hh))
+    ex = np.where(o["hhx"] > 0, np.abs(g["zx"] - o["zx"]) / np.maximum(np.abs(o["zx"]), np.sqrt(hx)), 0.0)
+    eh = np.abs(g["hhp"] - o["hhp"]) / hh
+    er = np.where(o["rho"] > 0, np.abs(g["rho"] - o["rho"]) / np.maximum(o["rho"], 1e-300), np.abs(g["rho"]))
+    print("%s: n=%d max e(z+)=%.3e e(zx)=%.3e e(hh)=%.3e e(rho)=%.3e ties=%d"
+          % (label, len(ok), ep[ok].max(), ex[ok].max(), eh[ok].max(), er[ok].max(), n_tie))
+    assert np.array_equal(g["flags"][ok], o["flags"][ok]), (g["flags"][ok], o["flags"][ok])
+    assert ep[ok].max() <= tol_z
+    assert ex[ok].max() <= tol_z
+    assert eh[ok].max() <= tol_hh
+    assert er[ok].max() <= tol_rho
+    return ep[ok].max()
+
+
+# ----------------------------------------------------------------------------- fixtures
+@pytest.fixture(scope="module")
+def tiny():
+    """The tiny workload with a Newtonian injection at SNR 20 (Mc = 1.2, t_c = 16984 s)."""
+    w = synth.tiny(seed=1)
+    dt = w.t_sft / w.n_samples
+    t = np.arange(w.n_sft * w.n_samples) * dt
+    wf = oracle.waveform(1.2, 16984.0, 0.0, t)
+    h = wf[:, 0] * np.cos(wf[:, 1])
+    h *= 20.0 / np.sqrt(np.sum(h**2) / w.sigma**2)
+    w.x_bins = synth.sfts_from_series(w.series + h, w.n_samples, w.n_sft, dt)
+    return w
+
+
+@pytest.fixture(scope="module")
+def ground_small():
+    return synth.ground(seed=6, n_templates=777, n_slots=96, n_det=3, k_lo=40, k_hi=470,
+                        t_end_pad=300.0)
+
+
+# ----------------------------------------------------------------------------- tiny workload
+def test_tiny_fp64_dirichlet_full_bank(tiny):
+    data = sft.SFTData.from_workload(tiny, storage="f64")
+    kw = dict(K=4, kernel="dirichlet", precision="fp64")
+    g = gpu_scan(data, tiny.bank, **kw)
+    o = orc_scan(tiny, tiny.bank, **kw)
+    e = compare(g, o, label="tiny fp64")
+    assert e < 1e-9                       # FP64 throughout: far inside the bar
+    # the loudest template sits at the injected chirp mass (the K = 4 Dirichlet window
+    # loses part of the SNR-20 injection in the late, fast-drifting SFTs)
+    m = int(np.argmax(g["rho"]))
+    assert abs(tiny.bank["mc"][m] - 1.2) < 1e-3 and g["rho"][m] > 8
+
+
+@pytest.mark.parametrize("precision", ["fp32_kahan", "fp32_naive"])
+def test_tiny_fp32_dirichlet_full_bank(tiny, precision):
+    data = sft.SFTData.from_workload(tiny, storage="f32")
+    kw = dict(K=4, kernel="dirichlet", precision=precision)
+    compare(gpu_scan(data, tiny.bank, **kw), orc_scan(tiny, tiny.bank, **kw), label="tiny " + precision)
+
+
+def test_tiny_bf16_storage_is_reported_not_exact(tiny):
+    """BF16 data bins carry ~3e-3 relative rounding: the error is measured, not hidden."""
+    data = sft.SFTData.from_workload(tiny, storage="bf16")
+    kw = dict(K=4, kernel="dirichlet", precision="fp32_kahan")
+    g = gpu_scan(data, tiny.bank, **kw)
+    o = orc_scan(tiny, tiny.bank, **kw)
+    e = np.abs(g["zp"] - o["zp"]) / np.maximum(np.abs(o["zp"]), np.sqrt(o["hhp"]))
+    print("tiny bf16: max e = %.3e" % e.max())
+    assert 1e-5 < e.max() < 3e-2
+    assert np.array_equal(g["flags"], o["flags"])
+
+
+# ----------------------------------------------------------------------------- Fresnel / multi-detector
+@pytest.mark.parametrize("K,kernel", [(8, "auto"), (5, "auto"), (8, "fresnel"), (4, "dirichlet")])
+def test_ground_small_multidetector(ground_small, K, kernel):
+    """3 detectors, gaps, coloured non-stationary PSD, antenna patterns; 777 templates
+    (three 256-lane tiles and a ragged tail), compile-time and run-time K."""
+    w = ground_small
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=K, kernel=kernel, precision="fp32_kahan", a_plus=1.0, a_cross=1.0)
+    compare(gpu_scan(data, w.bank, **kw), orc_scan(w, w.bank, **kw), label="ground-small K=%d %s" % (K, kernel))
+
+
+def test_fresnel_large_drift():
+    """Templates close to merger: beta = fdot T^2 up to tens of bins, K = 32."""
+    w = synth.ground(seed=8, n_templates=300, n_slots=40, n_det=1, k_lo=20, k_hi=1500,
+                     t_end_pad=15.0, mc_lo=1.3, mc_hi=1.5)
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=32, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=0.0)
+    o = orc_scan(w, w.bank, **kw)
+    compare(gpu_scan(data, w.bank, **kw), o, label="large drift")
+
+
+# ----------------------------------------------------------------------------- edge cases
+def test_edges_tau_band_ragged_empty():
+    """t_c inside the data (tau <= 0 SFTs), windows leaving the band, ragged and empty
+    SFT ranges, a masked PSD bin and a single template."""
+    w = synth.ground(seed=9, n_templates=333, n_slots=50, n_det=2, k_lo=100, k_hi=300,
+                     t_end_pad=-400.0, mc_lo=1.0, mc_hi=1.5)
+    g0 = np.random.default_rng(1)
+    w.bank["a_first"] = g0.integers(0, w.n_sft // 2, w.n_templates).astype(np.int32)
+    w.bank["a_last"] = (w.bank["a_first"] + g0.integers(-3, w.n_sft, w.n_templates)).astype(np.int32)
+    w.psd[5, 17] = 0.0
+    w.psd[6, 30] = np.inf
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=8, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0, delta_max=1e-3)
+    g = gpu_scan(data, w.bank, **kw)
+    o = orc_scan(w, w.bank, **kw)
+    assert np.any(o["flags"] & oracle.F_TAU_NONPOSITIVE)
+    assert np.any(o["flags"] & oracle.F_OUT_OF_BAND)
+    assert np.any(o["flags"] & oracle.F_EMPTY)
+    assert np.any(o["flags"] & oracle.F_TAYLOR_INVALID)
+    compare(g, o, label="edges")
+    one = {k: v[:1] for k, v in w.bank.items()}
+    compare(gpu_scan(data, one, **kw), orc_scan(w, one, **kw), label="single template")
+
+
+def test_dc_mirror_and_nonfinite():
+    """A band starting at DC: windows reaching k < 0 use conj(d~[-k]); NaN data -> NONFINITE."""
+    w = synth.tiny(seed=4, n_templates=64, n_sft=16)
+    w.bank["t_c"][:] = 1.4e9                 # f ~ 0.05 Hz: kappa ~ 3 bins at T = 64 s
+    w.bank["mc"][:] = np.linspace(1.0, 1.6, 64)
+    kw = dict(K=6, kernel="dirichlet", precision="fp64")
+    data = sft.SFTData.from_workload(w, storage="f64")
+    compare(gpu_scan(data, w.bank, **kw), orc_scan(w, w.bank, **kw), label="dc mirror")
+    xb = w.x_bins.copy()
+    xb[3, :] = np.nan
+    w2 = synth.tiny(seed=4, n_templates=64, n_sft=16)
+    w2.x_bins = xb
+    w2.bank = w.bank
+    d2 = sft.SFTData.from_workload(w2, storage="f64")
+    g = gpu_scan(d2, w.bank, **kw)
+    o = orc_scan(w2, w.bank, **kw)
+    assert np.all(g["flags"] & oracle.F_NONFINITE) and np.array_equal(g["flags"], o["flags"])
+
+
+def test_zero_templates_and_determinism(ground_small):
+    w = ground_small
+    data = sft.SFTData.from_workload(w, storage="f32")
+    opts = sft.make_opts(K=8, kernel="auto", a_plus=1.0, a_cross=1.0)
+    bt = sft.bank_to_device(w.bank)
+    out = sft.alloc_out(1)
+    sft.template_bank_scan(data, bt, opts, out=out, n=0)       # no-op
+    r1 = sft.template_bank_scan(data, bt, opts)
+    r2 = sft.template_bank_scan(data, bt, opts)
+    torch.cuda.synchronize()
+    for k in r1:
+        assert torch.equal(r1[k], r2[k]), k
+
+
+def test_inner_product_single_call(ground_small):
+    w = ground_small
+    data = sft.SFTData.from_workload(w, storage="f32")
+    opts = sft.make_opts(K=8, kernel="auto", a_plus=1.0, a_cross=1.0)
+    m = 123
+    r = sft.inner_product(data, w.bank["mc"][m], w.bank["t_c"][m], opts=opts)
+    one = {k: v[m:m + 1] for k, v in w.bank.items()}
+    o = orc_scan(w, one, K=8, kernel="auto", a_plus=1.0, a_cross=1.0)
+    e = abs(r["zp"] - o["zp"][0]) / max(abs(o["zp"][0]), np.sqrt(o["hhp"][0]))
+    assert e < 1e-6 and r["flags"] == o["flags"][0]
+    assert abs(r["rho"] / o["rho"][0] - 1) < 1e-5
+
+
+# ----------------------------------------------------------------------------- full ground workload
+@pytest.mark.slow
+def test_ground_full_size_sampled():
+    """The full ground-based workload (3 x 3891 SFTs, 1e5 templates, K = 8, automatic
+    kernel, FP32 compensated) in the bench's launch configuration, checked on a seeded
+    sample of templates the oracle computes one by one."""
+    w = synth.ground(seed=2)
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=8, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0)
+    g = gpu_scan(data, w.bank, **kw)
+    idx = np.sort(np.random.default_rng(0).choice(w.n_templates, 24, replace=False))
+    idx = np.concatenate([[0, w.n_templates - 1], idx])
+    o = orc_scan(w, w.subset(idx), **kw)
+    compare(g, o, idx=idx, label="ground full (sampled)")
+    assert np.all(np.isfinite(g["rho"])) and np.all(g["flags"] == 0)
