@@ -104,7 +104,8 @@ __device__ inline Chirp newton_chirp(double tau, double inv5M, double cf, double
 {
   double y = tau * inv5M;
   float yf = (float)y;
-  double s = (double)exp2f(-0.125f * log2f(yf));
+  // FP32 estimate from the hardware log2/exp2 (about 1 ulp); the Newton steps fix the rest
+  double s = (double)__builtin_amdgcn_exp2f(-0.125f * __builtin_amdgcn_logf(yf));
   for (int it = 0; it < 2; ++it) {
     double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
     s = fma(s * 0.125, fma(-y, s8, 1.0), s);
@@ -128,25 +129,54 @@ __device__ inline double reduce_2pi(double phi)
   return fma(-n, kTwoPiLo, r);
 }
 
-// ---------------------------------------------------------------- Fresnel endpoint term
-// e(p) = sgn(p) G(sqrt(2/beta)|p|) / sqrt(2 beta) as (re, im); tab is the LDS copy of
-// sft_g_coef laid out [interval][power] as float2.
-__device__ inline float2 fres_endpoint(float p, float beta, float sq2ob, float isq2b, const float2* tab)
+constexpr double kTwoOverPi = 0.63661977236758134308;
+constexpr double kPiO2Hi = 1.5707963267948966192;     // nearest double to pi/2
+constexpr double kPiO2Lo = 6.123233995736766036e-17;  // pi/2 - kPiO2Hi
+
+// (sin phi, cos phi) in FP32 for an unreduced FP64 phase: phi = n pi/2 + r with
+// |r| <= pi/4 by a two-constant Cody-Waite reduction in FP64, then the Maclaurin
+// series of sin and cos on [-pi/4, pi/4] in FP32 (truncation < 1e-11), and the
+// quadrant n mod 4 applied by swapping and negating.
+__device__ inline void phasor(double phi, float& s, float& c)
 {
-  float v = fabsf(p) * sq2ob;
+  const double n = rint(phi * kTwoOverPi);
+  double r = fma(-n, kPiO2Hi, phi);
+  r = fma(-n, kPiO2Lo, r);
+  const float x = (float)r;
+  const float x2 = x * x;
+  const float sp = x * fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, -2.50521084e-8f, 2.75573192e-6f),
+                                                          -1.98412698e-4f), 8.33333333e-3f), -1.66666667e-1f), 1.0f);
+  const float cp = fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 2.08767570e-9f, -2.75573192e-7f),
+                                                              2.48015873e-5f), -1.38888889e-3f), 4.16666667e-2f), -0.5f), 1.0f);
+  const int q = (int)((long long)n & 3);
+  const float s0 = (q & 1) ? cp : sp;
+  const float c0 = (q & 1) ? sp : cp;
+  s = (q & 2) ? -s0 : s0;
+  c = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// ---------------------------------------------------------------- Fresnel endpoint term
+// 2 pi e(p) = 2 pi sgn(p) G(sqrt(2/beta)|p|) / sqrt(2 beta) as (re, im).  In the
+// asymptotic range (v >= 4.5) with r = 1/p and w = beta r^2 / (2 pi):
+//   2 pi e(p) = r w gs(w^2) + i r fs(w^2),
+//   fs = 1 - 3 W + 105 W^2 - 10395 W^3,  gs = 1 - 15 W + 945 W^2 - 135135 W^3,  W = w^2.
+// Below, G(v) from the LDS table (interval width 1/2, Horner in v - centre), scaled
+// by tsc = 2 pi / sqrt(2 beta).  bq = beta / (2 pi).
+__device__ inline float2 fres_endpoint2(float p, float bq, float sq2ob, float tsc, const float2* tab)
+{
+  const float v = fabsf(p) * sq2ob;
   if (v >= SFT_G_VASYM) {
-    float r = 1.0f / p;
-    float w = beta * r * r * kInvTwoPiF;
-    float W = w * w;
-    float fs = fmaf(W, fmaf(W, fmaf(W, -10395.0f, 105.0f), -3.0f), 1.0f);
-    float gs = w * fmaf(W, fmaf(W, fmaf(W, -135135.0f, 945.0f), -15.0f), 1.0f);
-    float c = r * kInvTwoPiF;
-    return make_float2(c * gs, c * fs);
+    const float r = __builtin_amdgcn_rcpf(p);
+    const float w = bq * (r * r);
+    const float W = w * w;
+    const float fs = fmaf(W, fmaf(W, fmaf(W, -10395.0f, 105.0f), -3.0f), 1.0f);
+    const float gs = fmaf(W, fmaf(W, fmaf(W, -135135.0f, 945.0f), -15.0f), 1.0f);
+    return make_float2((r * w) * gs, r * fs);
   }
   int i = (int)(v * (1.0f / SFT_G_WIDTH));
   i = i < SFT_G_NINT - 1 ? i : SFT_G_NINT - 1;
   i = i > 0 ? i : 0;
-  float u = v - ((float)i + 0.5f) * SFT_G_WIDTH;
+  const float u = v - ((float)i + 0.5f) * SFT_G_WIDTH;
   const float2* cc = tab + i * (SFT_G_DEG + 1);
   float gr = cc[SFT_G_DEG].x, gi = cc[SFT_G_DEG].y;
 #pragma unroll
@@ -154,7 +184,7 @@ __device__ inline float2 fres_endpoint(float p, float beta, float sq2ob, float i
     gr = fmaf(gr, u, cc[k].x);
     gi = fmaf(gi, u, cc[k].y);
   }
-  float sc = p < 0.0f ? -isq2b : isq2b;
+  const float sc = p < 0.0f ? -tsc : tsc;
   return make_float2(gr * sc, gi * sc);
 }
 

@@ -324,7 +324,12 @@ struct ScanArgs {
   uint32_t* pflags;  // [n_chunks][n_tmpl]
 };
 
-enum { KERN_DIRICHLET = 0, KERN_FRESNEL = 1 };  // KERN_FRESNEL also applies the Dirichlet switch
+enum { KERN_DIRICHLET = 0, KERN_FRESNEL = 1 };
+
+// unroll factor of the Fresnel bin loop (4 keeps the kernel at 5 waves per SIMD)
+#ifndef SFT_BIN_UNROLL
+#define SFT_BIN_UNROLL 4
+#endif  // KERN_FRESNEL also applies the Dirichlet switch
 
 // accumulators
 struct AccKahan {
@@ -409,7 +414,6 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
     const double kr = floor(ch.kappa + 0.5);
     const double delta = ch.kappa - kr;
     const int k0 = (int)kr;
-    const double ph = reduce_2pi(ch.phase);
     const int i0 = k0 - K - a.k_ext_lo;
     const bool inband = (i0 >= 0) && (i0 + 2 * K < a.n_ext);
     const Bin* row = bins + (int64_t)al * a.n_ext;
@@ -420,7 +424,14 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
     if (dir) {
       // H_j = sin(pi delta) / (pi (delta - j))
       const R dl = (R)delta;
-      const R sp = (PREC == SFT_PREC_FP64) ? (R)(sin(kPi * delta) / kPi) : (R)(sinf(kPiF * (float)dl) * kInvPiF);
+      R sp;
+      if constexpr (PREC == SFT_PREC_FP64) {
+        sp = sin(kPi * delta) / kPi;
+      } else {
+        float s_, c_;
+        phasor(kPi * delta, s_, c_);
+        sp = s_ * kInvPiF;
+      }
 #pragma unroll 4
       for (int j = -K; j <= K; ++j) {
         const int idx = i0 + j + K;
@@ -433,77 +444,98 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
         }
         const R x = dl - (R)j;
         R h;
-        if (PREC == SFT_PREC_FP64) h = (x == (R)0) ? (R)1 : sp / x;
+        if constexpr (PREC == SFT_PREC_FP64) h = (x == (R)0) ? (R)1 : sp / x;
         else h = (x == (R)0) ? (R)1 : (R)(sp * fast_rcp((float)x));
         cre = fma(bre, h, cre);
         cim = fma(bim, h, cim);
       }
     } else if constexpr (KERN == KERN_FRESNEL) {
-      // Fresnel weights; beta < 0 through F(x, beta) = conj F(-x, -beta)
+      // Fresnel weights; beta < 0 through F(x, beta) = conj F(-x, -beta).  The endpoint
+      // phasors E-+ are common to all bins, so the bins accumulate b e(p-) and b e(p+)
+      // and the phasors are applied once: C = E- S- - E+ S+ + S_stat.
       const bool neg = ch.beta < 0.0;
       const double bpos = fabs(ch.beta);
       const double ds64 = neg ? -delta : delta;
       const float bp = (float)bpos;
       const float ds = (float)ds64;
       const float rsb = rsqrtf(bp);
-      const float sq2ob = 1.41421356237309505f * rsb;   // sqrt(2 / beta)
-      const float isq2b = 0.70710678118654752f * rsb;   // 1 / sqrt(2 beta)
-      // E-+ = exp(i(-+pi delta + pi beta / 4)), pi beta / 4 reduced in FP64
-      const float th = (float)reduce_2pi(0.25 * kPi * bpos);
+      const float sq2ob = 1.41421356237309505f * rsb;         // sqrt(2 / beta)
+      const float isq2b = 0.70710678118654752f * rsb;         // 1 / sqrt(2 beta)
+      const float tsc = 6.28318530717958648f * isq2b;         // 2 pi / sqrt(2 beta)
+      const float bq = bp * kInvTwoPiF;                       // beta / (2 pi)
+      const float dm = ds - 0.5f * bp, dp = ds + 0.5f * bp;   // p-+ of bin j are dm - j, dp - j
+      // E-+ = exp(i(-+pi delta + pi beta / 4))
       float st, ct, sd, cd;
-      sincosf(th, &st, &ct);
-      sincosf(kPiF * ds, &sd, &cd);
+      phasor(0.25 * kPi * bpos, st, ct);
+      phasor(kPi * ds64, sd, cd);
       const float epr = cd * ct - sd * st, epi = sd * ct + cd * st;   // E+
       const float emr = cd * ct + sd * st, emi = cd * st - sd * ct;   // E-
       // 1 / beta in FP64 for the stationary phase: FP32 estimate + two Newton steps
-      double ib = (double)(1.0f / bp);
+      double ib = (double)fast_rcp(bp);
       ib = ib * fma(-bpos, ib, 2.0);
       ib = ib * fma(-bpos, ib, 2.0);
-#pragma unroll 2
-      for (int j = -K; j <= K; ++j) {
-        const int idx = i0 + j + K;
-        float bre, bim;
-        if (inband || (idx >= 0 && idx < a.n_ext)) {
+      float smr = 0.f, smi = 0.f, spr = 0.f, spi = 0.f, ssr = 0.f, ssi = 0.f;
+      auto run = [&](auto negc, auto checked) {
+        constexpr bool NEG = decltype(negc)::value;
+        constexpr bool CHK = decltype(checked)::value;
+#pragma unroll SFT_BIN_UNROLL
+        for (int j = -K; j <= K; ++j) {
+          const int idx = i0 + j + K;
+          float bre, bim;
+          if constexpr (CHK) {
+            if (idx < 0 || idx >= a.n_ext) {
+              fl |= kFlagOOB;
+              continue;
+            }
+          }
           BinIO<Bin>::load(row + idx, bre, bim);
-        } else {
-          fl |= kFlagOOB;
-          continue;
+          const int jj = NEG ? -j : j;
+          const float pm = dm - (float)jj, pp = dp - (float)jj;
+          const float2 em = fres_endpoint2(pm, bq, sq2ob, tsc, tab);
+          const float2 ep = fres_endpoint2(pp, bq, sq2ob, tsc, tab);
+          const float emy = NEG ? -em.y : em.y, epy = NEG ? -ep.y : ep.y;
+          smr = fmaf(bre, em.x, fmaf(-bim, emy, smr));
+          smi = fmaf(bre, emy, fmaf(bim, em.x, smi));
+          spr = fmaf(bre, ep.x, fmaf(-bim, epy, spr));
+          spi = fmaf(bre, epy, fmaf(bim, ep.x, spi));
+          if (pm < 0.0f && pp >= 0.0f) {
+            // stationary point inside the SFT: (-1)^j (1+i) exp(-i pi x^2 / beta) / sqrt(2 beta)
+            const double x64 = ds64 - (double)jj;
+            const double hq = x64 * x64 * ib;
+            float sr, cr;
+            phasor(kPi * (hq - 2.0 * rint(0.5 * hq)), sr, cr);
+            const float sg = (jj & 1) ? -isq2b : isq2b;
+            const float hre = sg * (cr + sr);
+            const float him = NEG ? -sg * (cr - sr) : sg * (cr - sr);
+            ssr = fmaf(bre, hre, fmaf(-bim, him, ssr));
+            ssi = fmaf(bre, him, fmaf(bim, hre, ssi));
+          }
         }
-        const int jj = neg ? -j : j;
-        const float x = ds - (float)jj;
-        const float pm = x - 0.5f * bp, pp = x + 0.5f * bp;
-        const float2 em = fres_endpoint(pm, bp, sq2ob, isq2b, tab);
-        const float2 ep = fres_endpoint(pp, bp, sq2ob, isq2b, tab);
-        float hre = (em.x * emr - em.y * emi) - (ep.x * epr - ep.y * epi);
-        float him = (em.x * emi + em.y * emr) - (ep.x * epi + ep.y * epr);
-        if (pm < 0.0f && pp >= 0.0f) {
-          // stationary point inside the SFT: (-1)^j (1+i) exp(-i pi x^2 / beta) / sqrt(2 beta)
-          const double x64 = ds64 - (double)jj;
-          const double hq = x64 * x64 * ib;
-          const float r = (float)(hq - 2.0 * rint(0.5 * hq));
-          float sr, cr;
-          sincosf(kPiF * r, &sr, &cr);
-          const float sg = (jj & 1) ? -isq2b : isq2b;
-          hre = fmaf(sg, cr + sr, hre);
-          him = fmaf(sg, cr - sr, him);
-        }
-        if (neg) him = -him;
-        cre = fmaf(bre, hre, fmaf(-bim, him, cre));
-        cim = fmaf(bre, him, fmaf(bim, hre, cim));
+      };
+      if (inband) {
+        if (neg) run(std::true_type{}, std::false_type{});
+        else run(std::false_type{}, std::false_type{});
+      } else {
+        if (neg) run(std::true_type{}, std::true_type{});
+        else run(std::false_type{}, std::true_type{});
       }
+      const float emy = neg ? -emi : emi, epy = neg ? -epi : epi;
+      cre = fmaf(kInvTwoPiF, (emr * smr - emy * smi) - (epr * spr - epy * spi), ssr);
+      cim = fmaf(kInvTwoPiF, (emr * smi + emy * smr) - (epr * spi + epy * spr), ssi);
     }
     // term = (-1)^{k0} A exp(i phi) C
     R pc, ps;
-    if (PREC == SFT_PREC_FP64) {
+    if constexpr (PREC == SFT_PREC_FP64) {
+      const double ph = reduce_2pi(ch.phase);
       double s_, c_;
       sincos(ph, &s_, &c_);
       ps = (R)s_;
       pc = (R)c_;
     } else {
       float s_, c_;
-      sincosf((float)ph, &s_, &c_);
-      ps = (R)s_;
-      pc = (R)c_;
+      phasor(ch.phase, s_, c_);
+      ps = s_;
+      pc = c_;
     }
     const R amp = (R)ch.amp;
     const R as = (k0 & 1) ? -amp : amp;

@@ -45,7 +45,9 @@ def orc_scan(w, bank, x_bins=None, psd=None, **kw):
                        a_last=bank["a_last"], **kw)
 
 
-def compare(g, o, idx=None, tol_z=1e-6, tol_rho=1e-5, tol_hh=1e-6, label=""):
+def compare(g, o, idx=None, tol_z=1e-6, tol_rho=1e-5, tol_hh=1e-6, label="", noise_scale=None):
+    """noise_scale: optional (hh+, hhx) of the template's full SFT set, used in place of the
+    reported norm when the stored band cut some of its norm bins (OUT_OF_BAND)."""
     if idx is not None:
         g = {k: v[idx] for k, v in g.items()}
     ok = o["tie"] > 1e-9
@@ -53,9 +55,12 @@ def compare(g, o, idx=None, tol_z=1e-6, tol_rho=1e-5, tol_hh=1e-6, label=""):
     assert n_tie <= max(1, len(ok) // 1000), "too many rounding ties: %d" % n_tie
     hh = np.maximum(o["hhp"], 1e-300)
     hx = np.maximum(o["hhx"], 1e-300)
+    if noise_scale is not None:
+        hh = np.maximum(hh, noise_scale[0])
+        hx = np.maximum(hx, noise_scale[1])
     ep = np.abs(g["zp"] - o["zp"]) / np.maximum(np.abs(o["zp"]), np.sqrt(hh))
     ex = np.where(o["hhx"] > 0, np.abs(g["zx"] - o["zx"]) / np.maximum(np.abs(o["zx"]), np.sqrt(hx)), 0.0)
-    eh = np.abs(g["hhp"] - o["hhp"]) / hh
+    eh = np.abs(g["hhp"] - o["hhp"]) / np.maximum(o["hhp"], 1e-300)
     er = np.where(o["rho"] > 0, np.abs(g["rho"] - o["rho"]) / np.maximum(o["rho"], 1e-300), np.abs(g["rho"]))
     print("%s: n=%d max e(z+)=%.3e e(zx)=%.3e e(hh)=%.3e e(rho)=%.3e ties=%d"
           % (label, len(ok), ep[ok].max(), ex[ok].max(), eh[ok].max(), er[ok].max(), n_tie))
@@ -142,25 +147,36 @@ def test_fresnel_large_drift():
 
 
 # ----------------------------------------------------------------------------- edge cases
-def test_edges_tau_band_ragged_empty():
-    """t_c inside the data (tau <= 0 SFTs), windows leaving the band, ragged and empty
-    SFT ranges, a masked PSD bin and a single template."""
-    w = synth.ground(seed=9, n_templates=333, n_slots=50, n_det=2, k_lo=100, k_hi=300,
+def _edge_workload(k_lo, k_hi):
+    w = synth.ground(seed=9, n_templates=333, n_slots=50, n_det=2, k_lo=k_lo, k_hi=k_hi,
                      t_end_pad=-400.0, mc_lo=1.0, mc_hi=1.5)
     g0 = np.random.default_rng(1)
     w.bank["a_first"] = g0.integers(0, w.n_sft // 2, w.n_templates).astype(np.int32)
     w.bank["a_last"] = (w.bank["a_first"] + g0.integers(-3, w.n_sft, w.n_templates)).astype(np.int32)
+    return w
+
+
+def test_edges_tau_band_ragged_empty():
+    """t_c inside the data (tau <= 0 SFTs), windows leaving the band, ragged and empty
+    SFT ranges, a masked PSD bin and a single template.  The stored band [100, 300)
+    cuts the norm bins of many SFTs whose windows still reach into the band, so the
+    error scale is the norm computed from the same PSD over the full band."""
+    w = _edge_workload(100, 300)
     w.psd[5, 17] = 0.0
     w.psd[6, 30] = np.inf
     data = sft.SFTData.from_workload(w, storage="f32")
     kw = dict(K=8, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0, delta_max=1e-3)
     g = gpu_scan(data, w.bank, **kw)
     o = orc_scan(w, w.bank, **kw)
+    wide = _edge_workload(20, 2049)
+    assert np.array_equal(wide.psd[:, 80:280][:, [i for i in range(200) if i not in (17, 30)]],
+                          w.psd[:, [i for i in range(200) if i not in (17, 30)]])
+    ow = orc_scan(wide, w.bank, **kw)
     assert np.any(o["flags"] & oracle.F_TAU_NONPOSITIVE)
     assert np.any(o["flags"] & oracle.F_OUT_OF_BAND)
     assert np.any(o["flags"] & oracle.F_EMPTY)
     assert np.any(o["flags"] & oracle.F_TAYLOR_INVALID)
-    compare(g, o, label="edges")
+    compare(g, o, label="edges", noise_scale=(ow["hhp"], ow["hhx"]))
     one = {k: v[:1] for k, v in w.bank.items()}
     compare(gpu_scan(data, one, **kw), orc_scan(w, one, **kw), label="single template")
 
