@@ -26,35 +26,70 @@ if ROOT not in sys.path:
 METRIC = "template inner products/s at ≤1e-6 rel err; surrogate+FP32 vs plain path"
 
 # --------------------------------------------------------------------------------------
-# Algorithmic VALU work of the scan per (template, SFT), in lane-operation slots
-# (an add, mul or FMA = 1 slot; a transcendental v_rcp/v_sqrt/v_sin/v_exp/v_log = 4
-# slots, quarter rate).  Counted from the formulas the kernel evaluates:
-#   waveform at the SFT midpoint (FP64): tau, y, s = y^(-1/8) (log2 + exp2 + two
-#     4-operation Newton steps), kappa, phase, A, beta, 1/tau       -> 21 + 2 T
-#   phase reduction mod 2 pi + sin/cos of the reduced phase          ->  4 + 2 T
-#   bin split kappa -> k0, delta                                     ->  3
-#   kernel setup: Dirichlet sin(pi delta) (1 + 1 T); Fresnel sqrt(2/beta),
-#     E-+ phasors, pi beta/4 reduction (~14 + 3 T)
-#   per bin: Dirichlet: x = delta - j, 1/x (T), x sp, 2 FMA          ->  3 + 1 T
-#            Fresnel (asymptotic endpoints, the dominant branch): two endpoint
-#            terms (1/p, w, 2 x (3 FMA + 1 mul), 2 mul) = 2 x (9 + 1 T), the
-#            assembly with the two phasors (8) and the complex MAC (4)  -> 30 + 2 T
-#   coherent accumulation: complex rotation (6), 4 compensated adds (4 x 4),
-#     norm (interpolation 3, 1/S 1 T, 4 mul, 2 compensated adds 8)     -> 37 + 1 T
+# Algorithmic VALU work of the scan, in lane-operation slots: an FP32/FP64 add, mul or
+# FMA = 1 slot, a transcendental (v_rcp, v_rsq, v_log, v_exp) = 4 slots (quarter rate);
+# compares, selects, conversions of loop indices and address arithmetic are not counted.
+# Counted from the formulas the kernel evaluates (Fresnel kernel, asymptotic endpoint
+# branch, which is the dominant one):
+#   per (template, timestamp group), shared by the detectors of the group:
+#     FP64 chirp at the SFT midpoint (tau, y, s = y^(-1/8) from log2/exp2 and two
+#       Newton steps, kappa, phase, A, beta, Taylor residual)          34 + 2 T
+#     window split kappa -> k0, delta                                    4
+#     Fresnel set-up: 1/sqrt(beta), scales, endpoint offsets, the two
+#       phasors exp(i pi beta/4), exp(i pi delta), E-+, 1/beta (FP64)   63 + 2 T
+#     per bin: p-+ (2) and two endpoint terms (|p| sqrt(2/beta), 1/p,
+#       r^2, w, w^2, two 3-FMA series, three products)                  28 + 2 T
+#     phase phasor exp(i phi) and the signed amplitude                   24
+#     norm set-up (floor, weight, A^2 T)                                  6
+#   per (template, SFT row):
+#     per bin: two complex MACs into S-, S+                              8
+#     C = (E- S- - E+ S+) / 2 pi + S_stat                                12
+#     term, projector and four Kahan-compensated sums                    26
+#     norm term A^2 T / S(f) with interpolation, two Kahan sums          18 + T
+# The Dirichlet kernel replaces the Fresnel set-up by sin(pi delta) (22) and the per-bin
+# group work by x = delta - j and x^-1 (1 + T), and the per-row MACs by 2 FMAs.
 # --------------------------------------------------------------------------------------
 SLOT_T = 4
 
 
-def alg_slots_per_unit(K: int, kernel: str) -> int:
-    base = (21 + 2 * SLOT_T) + (4 + 2 * SLOT_T) + 3 + (37 + 1 * SLOT_T)
+def alg_slots(K: int, kernel: str, n_groups: int, n_rows: int) -> float:
+    nb = 2 * K + 1
     if kernel == "dirichlet":
-        return base + (1 + SLOT_T) + (2 * K + 1) * (3 + SLOT_T)
-    return base + (14 + 3 * SLOT_T) + (2 * K + 1) * (30 + 2 * SLOT_T)
+        per_group = (34 + 2 * SLOT_T) + 4 + 22 + nb * (1 + SLOT_T) + 24 + 6
+        per_row = nb * 2 + 26 + (18 + SLOT_T)
+    else:
+        per_group = (34 + 2 * SLOT_T) + 4 + (63 + 2 * SLOT_T) + nb * (28 + 2 * SLOT_T) + 24 + 6
+        per_row = nb * 8 + 12 + 26 + (18 + SLOT_T)
+    return per_group * n_groups + per_row * n_rows
 
 
 # peak VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (FP32 and FP64 FMA both
-# full rate without packed FP32; = 78.6 TFLOP/s FP64 / 2 flops per FMA)
+# full rate without packed FP32; = 78.6 TFLOP/s FP64 counting an FMA as 2 flops)
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+
+
+KERNEL_SOURCES = ["paper_2502_11823_amd/csrc/sft_lib.hip", "paper_2502_11823_amd/csrc/sft_device.h",
+                  "paper_2502_11823_amd/csrc/fresnel_table.h"]
+COUNTERS = "profiles/scan_kernel_ground_counters.md"
+
+
+def measured_traffic():
+    """HBM bytes per scan launch from the committed rocprofv3 counter summary, or None when
+    the kernel sources have changed since the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        txt = open(os.path.join(ROOT, COUNTERS)).read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in txt.splitlines() if ":" in line and line[:1].isalpha()
+                  and " " not in line.split(":", 1)[0])
+    if fields.get("kernel_source_sha256_16", "").strip() != h.hexdigest()[:16]:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -65,6 +100,8 @@ def parse():
     p.add_argument("--templates", type=int, default=100_000)
     p.add_argument("--cpu-sample", type=int, default=160, help="templates in the oracle sample (0 = skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--tuning", default="",
+                   help="block,chunk_groups,persistent: use this launch shape instead of autotuning")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only a plain device copy of known size (counter calibration)")
     return p.parse_args()
@@ -104,6 +141,17 @@ def main():
     out = sft.alloc_out(w.n_templates)
     print("setup %.1f s: %d SFTs x %d bins, %d templates" % (time.time() - t0, w.n_sft, w.n_bins, w.n_templates),
           file=sys.stderr, flush=True)
+    t0 = time.time()
+    if args.tuning:
+        b, c, p = (int(v) for v in args.tuning.split(","))
+        sft.set_tuning(data, block=b, chunk_groups=c, persistent=p)
+        best = sft.get_tuning(data)
+        print("fixed tuning %s" % best.as_dict(), file=sys.stderr, flush=True)
+    else:
+        best, best_ms = sft.autotune(data, bank, opts, out=out, reps=2)
+        torch.cuda.synchronize()
+        print("autotune %.1f s: %s -> %.3f ms" % (time.time() - t0, best.as_dict(), best_ms), file=sys.stderr,
+              flush=True)
 
     for _ in range(args.warmup):
         sft.template_bank_scan(data, bank, opts, out=out)
@@ -122,10 +170,22 @@ def main():
     value = w.n_templates * args.steps / elapsed
     ms_step = 1e3 * elapsed / args.steps
     k_ms = float(np.mean(ktimes)) if ktimes.size else float("nan")
-    units = w.n_templates * w.n_sft
-    slots = alg_slots_per_unit(K, kernel) * units
+    n_groups = int(np.unique(w.t_start).size)
+    slots = w.n_templates * alg_slots(K, kernel, n_groups, w.n_sft)
     achieved = slots / (k_ms * 1e-3) / 1e12
     peak = PEAK_SLOTS / 1e12
+
+    # the same scan replayed from a captured HIP graph
+    plan = sft.Plan(data, bank, opts, out=out)
+    for _ in range(2):
+        plan.launch()
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch()
+    torch.cuda.synchronize()
+    graph_ms = 1e3 * (time.perf_counter() - tg) / args.steps
+    plan.close()
 
     res = {
         "metric": METRIC,
@@ -145,9 +205,12 @@ def main():
                    "n_templates": w.n_templates, "n_sft": w.n_sft, "K": K, "kernel": kernel,
                    "precision": "fp32_kahan", "storage": "f32"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(),
                      "kernel": "scan_kernel", "kernel_ms": k_ms,
-                     "alg_slots_per_template_sft": alg_slots_per_unit(K, kernel)},
+                     "alg_slots_per_template": slots / w.n_templates,
+                     "units": {"templates": w.n_templates, "timestamp_groups": n_groups, "sft_rows": w.n_sft}},
+        "tuning": best.as_dict(),
+        "graph_ms_per_step": graph_ms,
     }
     print("scan: %.3f ms/step (kernel %.3f ms), %.3e IP/s" % (ms_step, k_ms, value), file=sys.stderr, flush=True)
 

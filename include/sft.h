@@ -161,6 +161,55 @@ sft_status sft_template_bank_scan(const sft_data* data, const sft_bank* bank, in
                                   const sft_opts* opts, sft_out* out, void* hip_stream);
 
 /*
+ * Launch shape of the bank scan, kept per data handle (fields equal to 0 select the
+ * automatic choice).  block: templates per workgroup, 64, 128 or 256 (default 256).
+ * chunk_groups: timestamp groups (SFT rows sharing a start time, one per detector) per
+ * work item; a work item is (template tile, chunk), and partial sums are combined in
+ * chunk order (default: chunks of about 1 MiB of bins and at least four work items per
+ * resident workgroup).  persistent: 1 launches one workgroup per resident slot, each
+ * pulling work items from a device counter until the queue is empty; 0 launches one
+ * workgroup per item.  An all-zero tuning selects the automatic chunks with the
+ * persistent grid.
+ * Results are bitwise identical for a given tuning; different tunings change only the
+ * order of the FP64 combination of partial sums.
+ */
+typedef struct {
+  int32_t block;
+  int32_t chunk_groups;
+  int32_t persistent;
+  int32_t reserved;  /* must be 0 */
+} sft_tuning;
+
+/* Read or replace the tuning of a handle.  Errors: SFT_E_INVALID, SFT_E_RANGE. */
+sft_status sft_get_tuning(const sft_data* data, sft_tuning* tuning);
+sft_status sft_set_tuning(sft_data* data, const sft_tuning* tuning);
+
+/*
+ * sft_autotune -- time candidate tunings (block 64/128/256, 1..64 chunks, plain and
+ * persistent grids) on the given bank with HIP events on hip_stream, reps timed runs
+ * each after one warm-up, store the fastest in the handle and return it (best, best_ms
+ * may be NULL).  Writes the outputs like a scan.  Synchronises hip_stream.
+ * Errors: those of sft_template_bank_scan, SFT_E_RANGE (reps outside [1, 100]).
+ */
+sft_status sft_autotune(sft_data* data, const sft_bank* bank, int64_t n_templates, const sft_opts* opts,
+                        sft_out* out, void* hip_stream, int32_t reps, sft_tuning* best, float* best_ms);
+
+/*
+ * Graph plans: a bank scan captured once into a HIP graph with its own workspace
+ * (about 56 bytes per template and chunk, allocated at creation), replayed by
+ * sft_plan_launch on any stream.  The plan keeps the device pointers of bank and out
+ * and the handle's tuning at creation: their contents may change between launches,
+ * the pointers may not, and data must outlive the plan.  Launches of one plan must not
+ * overlap (they share the workspace).  Errors: those of sft_template_bank_scan,
+ * SFT_E_NOMEM, SFT_E_DEVICE (capture or instantiation failed).
+ */
+typedef struct sft_plan sft_plan;
+sft_status sft_plan_create(const sft_data* data, const sft_bank* bank, int64_t n_templates,
+                           const sft_opts* opts, sft_out* out, sft_plan** plan);
+sft_status sft_plan_launch(sft_plan* plan, void* hip_stream);
+void sft_plan_destroy(sft_plan* plan);
+
+/*
  * sft_inner_product -- one template, host arguments and host results; runs the
  * bank scan with n = 1 and waits for it.  zp and zx receive (re, im).  Any of the
  * output pointers may be NULL.  Same errors as sft_template_bank_scan.

@@ -70,6 +70,10 @@ def _load():
     lib.orc_td_product.restype = D
     lib.orc_fd_product.argtypes = [P, P, L, D, P]
     lib.orc_fd_product.restype = D
+    lib.orc_pn35_consistency.argtypes = [D, D, D, D]
+    lib.orc_pn35_consistency.restype = D
+    lib.orc_set_pn_order.argtypes = [Int]
+    lib.orc_set_pn_order.restype = None
     lib.orc_tsft_max.argtypes = [D, D]
     lib.orc_tsft_max.restype = D
     _lib = lib
@@ -155,6 +159,16 @@ def waveform(mc, t_c, phi_c, t, q=1.0, wf=WF_NEWTON, tsun=T_SUN):
     if rc == -2:
         raise NotImplementedError("waveform model %d" % wf)
     return res
+
+
+def pn35_consistency(mc, q, tau, tsun=T_SUN):
+    """(d phi/dt) / (2 pi f) - 1 of the 3.5PN waveform, analytic."""
+    return _load().orc_pn35_consistency(float(mc), float(q), float(tau), float(tsun))
+
+
+def set_pn_order(order: int):
+    """Half PN orders kept by the 3.5PN waveform (7 = all; 0 = the Newtonian chirp)."""
+    _load().orc_set_pn_order(int(order))
 
 
 # --------------------------------------------------------------------------- inner products

@@ -682,10 +682,126 @@ double orc_tsft_max(double delta, double fddot_max)
 }
 
 /* ------------------------------------------------------------------------- */
-/* 3.5PN waveform: filled in with the surrogate work; returns -2 until then.  */
+/* 3.5PN waveform (reading R21): closed-form time-domain post-Newtonian         */
+/* inspiral in the variable Theta = nu (t_c - t) / (5 M) (the "TaylorT3" form of */
+/* the PN literature; Blanchet, Living Rev. Relativ. 17 (2014) 2, Sec. 9.3).     */
+/*   orbital phase  phi_orb = -(1/nu) Theta^{5/8} [1 + sum_k P_k Theta^{-k/8}]    */
+/*   PN parameter   x = (M omega)^{2/3} = (1/4) Theta^{-1/4} [1 + sum_k X_k Theta^{-k/8}] */
+/* with k = 2..7; the k = 5 phase term carries ln(Theta) and the k = 6 terms     */
+/* ln(Theta/256).  GW phase phi = phi_c + 2 phi_orb, f = x^{3/2} / (pi M).        */
+/* Amplitude: A = nu^{2/5} x (1 + x (-107/42 + 55 nu/42) + 2 pi x^{3/2}          */
+/*   + x^2 (-2173/1512 - 1069 nu/216 + 2047 nu^2/1512)), the dominant-mode        */
+/* amplitude through 2PN (real part); nu^{2/5} x = (pi Mc f)^{2/3} as in the      */
+/* Newtonian chirp.  M = Mc nu^{-3/5}, nu = q/(1+q)^2.  orc_pn_order (0..7) keeps  */
+/* the half-orders k <= orc_pn_order (0 is the Newtonian chirp).                  */
 /* ------------------------------------------------------------------------- */
+static int orc_pn_order = 7;
+
+void orc_set_pn_order(int order) { orc_pn_order = order < 0 ? 0 : order > 7 ? 7 : order; }
+
+/* a series term c(Theta) Theta^p with c = A + B ln(Theta) */
+typedef struct { double A, B, p; } orc_pnterm;
+
+static void orc_pn_series(double nu, orc_pnterm *ph, orc_pnterm *xs)
+{
+  const double pi = ORC_PI, pi2 = ORC_PI * ORC_PI, g = 0.57721566490153286061;
+  const double n2 = nu * nu, n3 = nu * nu * nu;
+  const double l256 = log(256.0);
+  for (int k = 0; k <= 7; k++) {
+    ph[k].A = ph[k].B = 0.0;
+    xs[k].A = xs[k].B = 0.0;
+    ph[k].p = 0.625 - 0.125 * k;
+    xs[k].p = -0.25 - 0.125 * k;
+  }
+  ph[0].A = 1.0;
+  xs[0].A = 1.0;
+  /* phase coefficients P_k */
+  ph[2].A = 3715.0 / 8064.0 + 55.0 / 96.0 * nu;
+  ph[3].A = -0.75 * pi;
+  ph[4].A = 9275495.0 / 14450688.0 + 284875.0 / 258048.0 * nu + 1855.0 / 2048.0 * n2;
+  ph[5].B = (-38645.0 / 172032.0 + 65.0 / 2048.0 * nu) * pi;          /* times ln(Theta) */
+  ph[6].A = 831032450749357.0 / 57682522275840.0 - 53.0 / 40.0 * pi2 - 107.0 / 56.0 * g
+            + (-126510089885.0 / 4161798144.0 + 2255.0 / 2048.0 * pi2) * nu
+            + 154565.0 / 1835008.0 * n2 - 1179625.0 / 1769472.0 * n3 - 107.0 / 448.0 * l256;
+  ph[6].B = 107.0 / 448.0;
+  ph[7].A = (188516689.0 / 173408256.0 + 488825.0 / 516096.0 * nu - 141769.0 / 516096.0 * n2) * pi;
+  /* x coefficients X_k */
+  xs[2].A = 743.0 / 4032.0 + 11.0 / 48.0 * nu;
+  xs[3].A = -0.2 * pi;
+  xs[4].A = 19583.0 / 254016.0 + 24401.0 / 193536.0 * nu + 31.0 / 288.0 * n2;
+  xs[5].A = (-11891.0 / 53760.0 + 109.0 / 1920.0 * nu) * pi;
+  xs[6].A = -10052469856691.0 / 6008596070400.0 + pi2 / 6.0 + 107.0 / 420.0 * g
+            + (3147553127.0 / 780337152.0 - 451.0 / 3072.0 * pi2) * nu
+            - 15211.0 / 442368.0 * n2 + 25565.0 / 1327104.0 * n3 + 107.0 / 3360.0 * l256;
+  xs[6].B = -107.0 / 3360.0;
+  xs[7].A = (-113868647.0 / 433520640.0 - 31821.0 / 143360.0 * nu + 294941.0 / 3870720.0 * n2) * pi;
+}
+
+/* sum of c_k(Theta) Theta^{p_k} and its first and second Theta-derivatives */
+static void orc_pn_eval(const orc_pnterm *t, double th, double *v, double *d1, double *d2)
+{
+  double lt = log(th);
+  *v = *d1 = *d2 = 0.0;
+  for (int k = 0; k <= orc_pn_order; k++) {
+    double A = t[k].A, B = t[k].B, p = t[k].p;
+    if (A == 0.0 && B == 0.0) continue;
+    double tp = pow(th, p), c = A + B * lt;
+    *v += c * tp;
+    /* d/dth [c th^p] = th^{p-1} (p c + B) */
+    double e1 = p * c + B;
+    *d1 += e1 * tp / th;
+    /* d2 = th^{p-2} ((p-1)(p c + B) + p B) */
+    *d2 += ((p - 1.0) * e1 + p * B) * tp / (th * th);
+  }
+}
+
 int orc_pn35(double mc, double q, double t_c, double phi_c, double t, double tsun, double *out)
 {
-  (void)mc; (void)q; (void)t_c; (void)phi_c; (void)t; (void)tsun; (void)out;
-  return -2;
+  double tau = t_c - t;
+  if (!(tau > 0.0)) return -1;
+  if (!(q >= 1.0)) q = 1.0 / q;
+  double nu = q / ((1.0 + q) * (1.0 + q));
+  double M = mc * pow(nu, -0.6) * tsun;       /* total mass [s] */
+  double th = nu * tau / (5.0 * M);
+  orc_pnterm ph[8], xs[8];
+  orc_pn_series(nu, ph, xs);
+  double P, dP, d2P, X, dX, d2X;
+  orc_pn_eval(ph, th, &P, &dP, &d2P);
+  orc_pn_eval(xs, th, &X, &dX, &d2X);
+  double phi_orb = -P / nu;
+  double x = 0.25 * X, dx = 0.25 * dX, d2x = 0.25 * d2X;   /* derivatives in Theta */
+  double dth = -nu / (5.0 * M);                             /* dTheta/dt */
+  double f = pow(x, 1.5) / (ORC_PI * M);
+  /* f = x^{3/2}/(pi M): df/dt = (3/2) x^{1/2} x' th' / (pi M), d2f/dt2 likewise */
+  double fdot = 1.5 * sqrt(x) * dx * dth / (ORC_PI * M);
+  double fddot = (0.75 / sqrt(x) * dx * dx + 1.5 * sqrt(x) * d2x) * dth * dth / (ORC_PI * M);
+  double amp = 1.0;
+  if (orc_pn_order >= 2) amp += x * (-107.0 / 42.0 + 55.0 / 42.0 * nu);
+  if (orc_pn_order >= 3) amp += 2.0 * ORC_PI * pow(x, 1.5);
+  if (orc_pn_order >= 4) amp += x * x * (-2173.0 / 1512.0 - 1069.0 / 216.0 * nu + 2047.0 / 1512.0 * nu * nu);
+  out[0] = pow(nu, 0.4) * x * amp;
+  out[1] = phi_c + 2.0 * phi_orb;
+  out[2] = f;
+  out[3] = fdot;
+  out[4] = fddot;
+  return 0;
+}
+
+/* Consistency of the two PN series: (d phi_gw / dt) / (2 pi f) - 1 evaluated
+ * analytically from the phase series (test-suite pin; O(Theta^-1) when the two
+ * series agree through 3.5PN). */
+double orc_pn35_consistency(double mc, double q, double tau, double tsun)
+{
+  if (!(q >= 1.0)) q = 1.0 / q;
+  double nu = q / ((1.0 + q) * (1.0 + q));
+  double M = mc * pow(nu, -0.6) * tsun;
+  double th = nu * tau / (5.0 * M);
+  orc_pnterm ph[8], xs[8];
+  orc_pn_series(nu, ph, xs);
+  double P, dP, d2P, X, dX, d2X;
+  orc_pn_eval(ph, th, &P, &dP, &d2P);
+  orc_pn_eval(xs, th, &X, &dX, &d2X);
+  double dphi_dt = 2.0 * (-dP / nu) * (-nu / (5.0 * M));
+  double f = pow(0.25 * X, 1.5) / (ORC_PI * M);
+  return dphi_dt / (2.0 * ORC_PI * f) - 1.0;
 }

@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/sft.h"
 #include "sft_device.h"
@@ -115,6 +116,9 @@ static void timing_slot(hipEvent_t* b, hipEvent_t* e)
 }
 
 // ============================================================================ data handle
+// Rows that share a start time (detectors of one network) form a timestamp group;
+// a group holds at most this many rows (more rows at one time start another group).
+#define SFT_GROUP_MAX 4
 struct sft_data {
   int device;
   int32_t n_sft, n, k_lo, n_bins, storage;
@@ -122,9 +126,14 @@ struct sft_data {
   double T;
   void* bins;     // [n_sft][n_ext] conj(2 x~ / S) in the storage type
   void* psd;      // [n_sft][n_bins] S (double for F64 storage, float otherwise); masked -> 0
-  double* t_mid;  // [n_sft]
   double* fp;     // [n_sft]
   double* fx;     // [n_sft]
+  // timestamp groups: rows with equal start times (one per detector), in time order
+  int32_t n_groups, nd;   // group count, largest group size (<= SFT_GROUP_MAX)
+  double* g_tmid;         // [n_groups] SFT midpoint t_start + T/2
+  int32_t* g_rows;        // [n_groups][SFT_GROUP_MAX] rows, -1 = absent
+  int32_t cu_count;       // compute units of the device
+  sft_tuning tune;        // launch shape of the scans on this handle (0 fields = automatic)
 };
 
 template <typename Bin> __device__ inline void store_bin(Bin* p, double re, double im);
@@ -173,10 +182,26 @@ __global__ __launch_bounds__(256) void load_kernel(const double* __restrict__ xb
   }
 }
 
-__global__ void meta_kernel(const double* __restrict__ t_start, double T, int32_t n_sft, double* __restrict__ t_mid)
+// Group rows by start time: stable order by time, runs of equal t_start split into
+// groups of at most SFT_GROUP_MAX rows.
+static void build_groups(const double* t_start, int32_t n_sft, double T, std::vector<double>& tmid,
+                         std::vector<int32_t>& rows, int32_t& nd)
 {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_sft) t_mid[i] = t_start[i] + 0.5 * T;
+  std::vector<int32_t> order(n_sft);
+  for (int32_t i = 0; i < n_sft; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return t_start[x] < t_start[y]; });
+  tmid.clear();
+  rows.clear();
+  nd = 1;
+  int32_t i = 0;
+  while (i < n_sft) {
+    int32_t j = i;
+    while (j < n_sft && j - i < SFT_GROUP_MAX && t_start[order[j]] == t_start[order[i]]) ++j;
+    tmid.push_back(t_start[order[i]] + 0.5 * T);
+    for (int32_t d = 0; d < SFT_GROUP_MAX; ++d) rows.push_back(i + d < j ? order[i + d] : -1);
+    nd = std::max(nd, j - i);
+    i = j;
+  }
 }
 
 extern "C" sft_status sft_load_data(const sft_data_desc* d, const double* t_start, const double* x_bins,
@@ -195,6 +220,9 @@ extern "C" sft_status sft_load_data(const sft_data_desc* d, const double* t_star
   sft_data* h = new sft_data();
   std::memset(h, 0, sizeof(*h));
   HIP_OR_FAIL(hipGetDevice(&h->device));
+  if (hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess ||
+      h->cu_count < 1)
+    h->cu_count = 256;
   h->n_sft = d->n_sft;
   h->n = d->n_samples;
   h->k_lo = d->k_lo;
@@ -217,7 +245,6 @@ extern "C" sft_status sft_load_data(const sft_data_desc* d, const double* t_star
   };
   hipError_t e = hipSuccess;
   if ((e = hipMalloc(&h->bins, ne * bin_sz)) != hipSuccess || (e = hipMalloc(&h->psd, nb * ps_sz)) != hipSuccess ||
-      (e = hipMalloc(&h->t_mid, d->n_sft * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&h->fp, d->n_sft * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&h->fx, d->n_sft * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&dx, nb * 2 * sizeof(double))) != hipSuccess ||
@@ -266,9 +293,17 @@ extern "C" sft_status sft_load_data(const sft_data_desc* d, const double* t_star
       break;
     }
     if ((e = hipGetLastError()) != hipSuccess) break;
-    hipLaunchKernelGGL(meta_kernel, dim3((d->n_sft + 255) / 256), dim3(256), 0, st, dts, h->T, h->n_sft, h->t_mid);
-    if ((e = hipGetLastError()) != hipSuccess) break;
-    e = hipStreamSynchronize(st);
+    {
+      std::vector<double> tmid;
+      std::vector<int32_t> grows;
+      build_groups(t_start, d->n_sft, h->T, tmid, grows, h->nd);
+      h->n_groups = (int32_t)tmid.size();
+      if ((e = hipMalloc(&h->g_tmid, tmid.size() * sizeof(double))) != hipSuccess) break;
+      if ((e = hipMalloc(&h->g_rows, grows.size() * sizeof(int32_t))) != hipSuccess) break;
+      if ((e = hipMemcpyAsync(h->g_tmid, tmid.data(), tmid.size() * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess) break;
+      if ((e = hipMemcpyAsync(h->g_rows, grows.data(), grows.size() * sizeof(int32_t), hipMemcpyHostToDevice, st)) != hipSuccess) break;
+      e = hipStreamSynchronize(st);   // the host vectors go out of scope here
+    }
   } while (0);
   cleanup();
   if (e != hipSuccess) {
@@ -284,7 +319,8 @@ extern "C" void sft_free_data(sft_data* h)
   if (!h) return;
   if (h->bins) (void)hipFree(h->bins);
   if (h->psd) (void)hipFree(h->psd);
-  if (h->t_mid) (void)hipFree(h->t_mid);
+  if (h->g_tmid) (void)hipFree(h->g_tmid);
+  if (h->g_rows) (void)hipFree(h->g_rows);
   if (h->fp) (void)hipFree(h->fp);
   if (h->fx) (void)hipFree(h->fx);
   delete h;
@@ -308,10 +344,11 @@ extern "C" void sft_default_opts(sft_opts* o)
 struct ScanArgs {
   const void* bins;
   const void* psd;
-  const double* t_mid;
+  const double* g_tmid;    // [n_groups] midpoint time of each timestamp group
+  const int32_t* g_rows;   // [n_groups][SFT_GROUP_MAX] SFT rows of the group, -1 = absent
   const double* fp;
   const double* fx;
-  int32_t n_sft, n_ext, k_ext_lo, n_bins, k_lo, K;
+  int32_t n_groups, n_ext, k_ext_lo, n_bins, k_lo, K;
   double T, beta_switch, tsun, delta_max;
   const double* mc;
   const double* t_c;
@@ -319,17 +356,21 @@ struct ScanArgs {
   const int32_t* a_first;
   const int32_t* a_last;
   int64_t n_tmpl;
-  int32_t chunk, n_chunks;
+  int32_t chunk, n_chunks;  // groups per chunk, chunk count
+  int32_t n_tiles;          // ceil(n_tmpl / blockDim.x)
+  int32_t n_items;          // n_tiles * n_chunks work items, chunk-major
+  int32_t persistent;       // 1: grid of resident blocks pulling items from *counter
+  int32_t* counter;         // work-queue head (zeroed before the launch)
   double* part;      // [n_chunks][6][n_tmpl]
   uint32_t* pflags;  // [n_chunks][n_tmpl]
 };
 
 enum { KERN_DIRICHLET = 0, KERN_FRESNEL = 1 };
 
-// unroll factor of the Fresnel bin loop (4 keeps the kernel at 5 waves per SIMD)
+// unroll factor of the bin loops (4 keeps the Fresnel kernel at 5 waves per SIMD)
 #ifndef SFT_BIN_UNROLL
 #define SFT_BIN_UNROLL 4
-#endif  // KERN_FRESNEL also applies the Dirichlet switch
+#endif
 
 // accumulators
 struct AccKahan {
@@ -361,13 +402,16 @@ template <> struct PrecTraits<SFT_PREC_FP32_NAIVE> { using R = float; using Acc 
 
 __device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <typename Bin, int PREC, int KERN, int KC>
+// One lane per template, one grid row per chunk of timestamp groups.  The SFT rows of
+// a group (one per detector) share the SFT midpoint, hence the chirp, the window and
+// all 2K+1 kernel weights: those are evaluated once per group and contracted with the
+// bins of each of the ND rows (the projector Lambda carries the detector dependence).
+template <typename Bin, int PREC, int KERN, int KC, int ND>
+__device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab);
+
+template <typename Bin, int PREC, int KERN, int KC, int ND>
 __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
 {
-  using R = typename PrecTraits<PREC>::R;
-  using Acc = typename PrecTraits<PREC>::Acc;
-  using PS = typename std::conditional<PREC == SFT_PREC_FP64, double, float>::type;
-
   __shared__ float2 tab[SFT_G_NINT * (SFT_G_DEG + 1)];
   if (KERN == KERN_FRESNEL) {
     for (int i = threadIdx.x; i < SFT_G_NINT * (SFT_G_DEG + 1); i += blockDim.x)
@@ -376,14 +420,39 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
     __syncthreads();
   }
 
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= a.n_tmpl) return;
+  __shared__ int s_item;
   const int K = KC >= 0 ? KC : a.K;
-  const int c = blockIdx.y;
-  const int a0 = c * a.chunk;
-  const int a1 = min(a0 + a.chunk, a.n_sft) - 1;
-  const int lo = a.a_first ? max((int)a.a_first[m], a0) : a0;
-  const int hi = a.a_last ? min((int)a.a_last[m], a1) : a1;
+  // A work item is (template tile, chunk of timestamp groups), chunk-major so that
+  // concurrently running blocks share the data rows of one chunk in L2.  A plain grid
+  // runs one item per block; a persistent grid pulls items from a counter until the
+  // queue is empty (every block reaches the exit test with the same item value).
+  int item = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  for (;;) {
+    if (a.persistent) {
+      __syncthreads();
+      if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+      __syncthreads();
+      item = s_item;
+      if (item >= a.n_items) break;
+    }
+    const int tile = item % a.n_tiles;
+    const int c = item / a.n_tiles;
+    const int64_t m = (int64_t)tile * blockDim.x + threadIdx.x;
+    if (m < a.n_tmpl) scan_item<Bin, PREC, KERN, KC, ND>(a, K, m, c, tab);
+    if (!a.persistent) break;
+  }
+}
+
+template <typename Bin, int PREC, int KERN, int KC, int ND>
+__device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab)
+{
+  using R = typename PrecTraits<PREC>::R;
+  using Acc = typename PrecTraits<PREC>::Acc;
+  using PS = typename std::conditional<PREC == SFT_PREC_FP64, double, float>::type;
+  const int g0 = c * a.chunk;
+  const int g1 = min(g0 + a.chunk, a.n_groups) - 1;
+  const int lo = a.a_first ? (int)a.a_first[m] : 0;
+  const int hi = a.a_last ? (int)a.a_last[m] : 0x7fffffff;
 
   const double T = a.T;
   const double M = a.mc[m] * a.tsun;
@@ -397,9 +466,18 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
   Acc zpr, zpi, zxr, zxi, hp, hx;
   uint32_t fl = 0;
 
-  for (int al = a0; al <= a1; ++al) {
-    if (al < lo || al > hi) continue;
-    const double tau = tc - a.t_mid[al];
+  for (int g = g0; g <= g1; ++g) {
+    int rows[ND];
+    bool act[ND];
+    bool any = false;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      rows[d] = a.g_rows[g * SFT_GROUP_MAX + d];
+      act[d] = rows[d] >= 0 && rows[d] >= lo && rows[d] <= hi;
+      any = any || act[d];
+    }
+    if (!any) continue;
+    const double tau = tc - a.g_tmid[g];
     if (!(tau > 0.0)) {
       fl |= kFlagTau;
       continue;
@@ -416,9 +494,13 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
     const int k0 = (int)kr;
     const int i0 = k0 - K - a.k_ext_lo;
     const bool inband = (i0 >= 0) && (i0 + 2 * K < a.n_ext);
-    const Bin* row = bins + (int64_t)al * a.n_ext;
+    const Bin* rp[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) rp[d] = bins + (int64_t)(rows[d] >= 0 ? rows[d] : 0) * a.n_ext;
 
-    R cre = 0, cim = 0;
+    R cre[ND], cim[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) cre[d] = cim[d] = (R)0;
     bool dir = true;
     if constexpr (KERN == KERN_FRESNEL) dir = fabs(ch.beta) <= a.beta_switch;
     if (dir) {
@@ -432,13 +514,10 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
         phasor(kPi * delta, s_, c_);
         sp = s_ * kInvPiF;
       }
-#pragma unroll 4
+#pragma unroll SFT_BIN_UNROLL
       for (int j = -K; j <= K; ++j) {
         const int idx = i0 + j + K;
-        R bre, bim;
-        if (inband || (idx >= 0 && idx < a.n_ext)) {
-          BinIO<Bin>::load(row + idx, bre, bim);
-        } else {
+        if (!inband && (idx < 0 || idx >= a.n_ext)) {
           fl |= kFlagOOB;
           continue;
         }
@@ -446,8 +525,14 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
         R h;
         if constexpr (PREC == SFT_PREC_FP64) h = (x == (R)0) ? (R)1 : sp / x;
         else h = (x == (R)0) ? (R)1 : (R)(sp * fast_rcp((float)x));
-        cre = fma(bre, h, cre);
-        cim = fma(bim, h, cim);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          if (rows[d] < 0) continue;
+          R bre, bim;
+          BinIO<Bin>::load(rp[d] + idx, bre, bim);
+          cre[d] = fma(bre, h, cre[d]);
+          cim[d] = fma(bim, h, cim[d]);
+        }
       }
     } else if constexpr (KERN == KERN_FRESNEL) {
       // Fresnel weights; beta < 0 through F(x, beta) = conj F(-x, -beta).  The endpoint
@@ -474,41 +559,51 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
       double ib = (double)fast_rcp(bp);
       ib = ib * fma(-bpos, ib, 2.0);
       ib = ib * fma(-bpos, ib, 2.0);
-      float smr = 0.f, smi = 0.f, spr = 0.f, spi = 0.f, ssr = 0.f, ssi = 0.f;
+      float smr[ND], smi[ND], spr[ND], spi[ND], ssr[ND], ssi[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) smr[d] = smi[d] = spr[d] = spi[d] = ssr[d] = ssi[d] = 0.f;
       auto run = [&](auto negc, auto checked) {
         constexpr bool NEG = decltype(negc)::value;
         constexpr bool CHK = decltype(checked)::value;
 #pragma unroll SFT_BIN_UNROLL
         for (int j = -K; j <= K; ++j) {
           const int idx = i0 + j + K;
-          float bre, bim;
           if constexpr (CHK) {
             if (idx < 0 || idx >= a.n_ext) {
               fl |= kFlagOOB;
               continue;
             }
           }
-          BinIO<Bin>::load(row + idx, bre, bim);
           const int jj = NEG ? -j : j;
           const float pm = dm - (float)jj, pp = dp - (float)jj;
           const float2 em = fres_endpoint2(pm, bq, sq2ob, tsc, tab);
           const float2 ep = fres_endpoint2(pp, bq, sq2ob, tsc, tab);
           const float emy = NEG ? -em.y : em.y, epy = NEG ? -ep.y : ep.y;
-          smr = fmaf(bre, em.x, fmaf(-bim, emy, smr));
-          smi = fmaf(bre, emy, fmaf(bim, em.x, smi));
-          spr = fmaf(bre, ep.x, fmaf(-bim, epy, spr));
-          spi = fmaf(bre, epy, fmaf(bim, ep.x, spi));
-          if (pm < 0.0f && pp >= 0.0f) {
+          const bool stat = pm < 0.0f && pp >= 0.0f;
+          float hre = 0.f, him = 0.f;
+          if (stat) {
             // stationary point inside the SFT: (-1)^j (1+i) exp(-i pi x^2 / beta) / sqrt(2 beta)
             const double x64 = ds64 - (double)jj;
             const double hq = x64 * x64 * ib;
             float sr, cr;
             phasor(kPi * (hq - 2.0 * rint(0.5 * hq)), sr, cr);
             const float sg = (jj & 1) ? -isq2b : isq2b;
-            const float hre = sg * (cr + sr);
-            const float him = NEG ? -sg * (cr - sr) : sg * (cr - sr);
-            ssr = fmaf(bre, hre, fmaf(-bim, him, ssr));
-            ssi = fmaf(bre, him, fmaf(bim, hre, ssi));
+            hre = sg * (cr + sr);
+            him = NEG ? -sg * (cr - sr) : sg * (cr - sr);
+          }
+#pragma unroll
+          for (int d = 0; d < ND; ++d) {
+            if (rows[d] < 0) continue;
+            float bre, bim;
+            BinIO<Bin>::load(rp[d] + idx, bre, bim);
+            smr[d] = fmaf(bre, em.x, fmaf(-bim, emy, smr[d]));
+            smi[d] = fmaf(bre, emy, fmaf(bim, em.x, smi[d]));
+            spr[d] = fmaf(bre, ep.x, fmaf(-bim, epy, spr[d]));
+            spi[d] = fmaf(bre, epy, fmaf(bim, ep.x, spi[d]));
+            if (stat) {
+              ssr[d] = fmaf(bre, hre, fmaf(-bim, him, ssr[d]));
+              ssi[d] = fmaf(bre, him, fmaf(bim, hre, ssi[d]));
+            }
           }
         }
       };
@@ -520,10 +615,13 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
         else run(std::false_type{}, std::true_type{});
       }
       const float emy = neg ? -emi : emi, epy = neg ? -epi : epi;
-      cre = fmaf(kInvTwoPiF, (emr * smr - emy * smi) - (epr * spr - epy * spi), ssr);
-      cim = fmaf(kInvTwoPiF, (emr * smi + emy * smr) - (epr * spi + epy * spr), ssi);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        cre[d] = fmaf(kInvTwoPiF, (emr * smr[d] - emy * smi[d]) - (epr * spr[d] - epy * spi[d]), ssr[d]);
+        cim[d] = fmaf(kInvTwoPiF, (emr * smi[d] + emy * smr[d]) - (epr * spi[d] + epy * spr[d]), ssi[d]);
+      }
     }
-    // term = (-1)^{k0} A exp(i phi) C
+    // term_d = (-1)^{k0} A exp(i phi) C_d
     R pc, ps;
     if constexpr (PREC == SFT_PREC_FP64) {
       const double ph = reduce_2pi(ch.phase);
@@ -539,34 +637,41 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
     }
     const R amp = (R)ch.amp;
     const R as = (k0 & 1) ? -amp : amp;
-    const R tre = as * (pc * cre - ps * cim);
-    const R tim = as * (pc * cim + ps * cre);
-    const R fpa = (R)a.fp[al];
-    const R fxa = (R)a.fx[al];
-    zpr.add(fpa * tre);
-    zpi.add(fpa * tim);
-    zxr.add(fxa * tre);
-    zxi.add(fxa * tim);
+    const R apc = as * pc, aps = as * ps;
     // norm term A^2 T / S(f), S linear between bins floor(kappa) and floor(kappa) + 1
     const double kfl = floor(ch.kappa);
     const int ip = (int)kfl - a.k_lo;
-    if (ip < 0 || ip + 1 >= a.n_bins) {
-      fl |= kFlagOOB;
-      continue;
-    }
-    const R S0 = (R)psd[(int64_t)al * a.n_bins + ip];
-    const R S1 = (R)psd[(int64_t)al * a.n_bins + ip + 1];
-    if (!(S0 > (R)0) || !(S1 > (R)0)) {
-      fl |= kFlagOOB;
-      continue;
-    }
+    const bool psd_in = ip >= 0 && ip + 1 < a.n_bins;
     const R w = (R)(ch.kappa - kfl);
-    const R S = ((R)1 - w) * S0 + w * S1;
-    R hterm;
-    if (PREC == SFT_PREC_FP64) hterm = amp * amp * (R)T / S;
-    else hterm = amp * amp * (R)T * (R)fast_rcp((float)S);
-    hp.add(fpa * fpa * hterm);
-    hx.add(fxa * fxa * hterm);
+    const R a2t = amp * amp * (R)T;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      if (!act[d]) continue;
+      const R tre = apc * cre[d] - aps * cim[d];
+      const R tim = apc * cim[d] + aps * cre[d];
+      const R fpa = (R)a.fp[rows[d]];
+      const R fxa = (R)a.fx[rows[d]];
+      zpr.add(fpa * tre);
+      zpi.add(fpa * tim);
+      zxr.add(fxa * tre);
+      zxi.add(fxa * tim);
+      if (!psd_in) {
+        fl |= kFlagOOB;
+        continue;
+      }
+      const R S0 = (R)psd[(int64_t)rows[d] * a.n_bins + ip];
+      const R S1 = (R)psd[(int64_t)rows[d] * a.n_bins + ip + 1];
+      if (!(S0 > (R)0) || !(S1 > (R)0)) {
+        fl |= kFlagOOB;
+        continue;
+      }
+      const R S = ((R)1 - w) * S0 + w * S1;
+      R hterm;
+      if constexpr (PREC == SFT_PREC_FP64) hterm = a2t / S;
+      else hterm = a2t * (R)fast_rcp((float)S);
+      hp.add(fpa * fpa * hterm);
+      hx.add(fxa * fxa * hterm);
+    }
   }
 
   const int64_t n = a.n_tmpl;
@@ -620,34 +725,46 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------- dispatch
-template <typename Bin, int PREC, int KERN>
-static hipError_t launch_k(const ScanArgs& a, dim3 grid, hipStream_t st)
+using ScanFn = void (*)(ScanArgs);
+
+template <typename Bin, int PREC, int KERN, int KC>
+static ScanFn pick_nd(int nd)
 {
-  switch (a.K) {
-  case 4: hipLaunchKernelGGL((scan_kernel<Bin, PREC, KERN, 4>), grid, dim3(256), 0, st, a); break;
-  case 8: hipLaunchKernelGGL((scan_kernel<Bin, PREC, KERN, 8>), grid, dim3(256), 0, st, a); break;
-  case 32: hipLaunchKernelGGL((scan_kernel<Bin, PREC, KERN, 32>), grid, dim3(256), 0, st, a); break;
-  default: hipLaunchKernelGGL((scan_kernel<Bin, PREC, KERN, -1>), grid, dim3(256), 0, st, a); break;
+  switch (nd) {
+  case 1: return scan_kernel<Bin, PREC, KERN, KC, 1>;
+  case 2: return scan_kernel<Bin, PREC, KERN, KC, 2>;
+  case 3: return scan_kernel<Bin, PREC, KERN, KC, 3>;
+  default: return scan_kernel<Bin, PREC, KERN, KC, 4>;
   }
-  return hipGetLastError();
+}
+
+template <typename Bin, int PREC, int KERN>
+static ScanFn pick_k(int K, int nd)
+{
+  if (PREC == SFT_PREC_FP64) return K == 4 ? pick_nd<Bin, PREC, KERN, 4>(nd) : pick_nd<Bin, PREC, KERN, -1>(nd);
+  return K == 8 ? pick_nd<Bin, PREC, KERN, 8>(nd) : pick_nd<Bin, PREC, KERN, -1>(nd);
 }
 
 template <typename Bin, int PREC>
-static hipError_t launch_kern(const ScanArgs& a, int kern, dim3 grid, hipStream_t st)
+static ScanFn pick_kern(int kern, int K, int nd)
 {
-  if (kern == KERN_DIRICHLET) return launch_k<Bin, PREC, KERN_DIRICHLET>(a, grid, st);
-  return launch_k<Bin, PREC, KERN_FRESNEL>(a, grid, st);
+  return kern == KERN_DIRICHLET ? pick_k<Bin, PREC, KERN_DIRICHLET>(K, nd) : pick_k<Bin, PREC, KERN_FRESNEL>(K, nd);
 }
 
-static int choose_chunks(int64_t n, int32_t n_sft)
+static ScanFn pick_kernel(const sft_data* d, const sft_opts* o)
 {
-  // enough template-waves x chunks to keep ~16 waves resident per CU on 256 CUs
-  const int64_t target_waves = 256 * 16;
-  int64_t tw = (n + 63) / 64;
-  int64_t nc = (target_waves + tw - 1) / tw;
-  int64_t max_nc = std::max<int64_t>(1, n_sft / 8);
-  nc = std::min<int64_t>(std::max<int64_t>(nc, 1), max_nc);
-  return (int)nc;
+  const int kern = o->kernel == SFT_KERNEL_DIRICHLET ? KERN_DIRICHLET : KERN_FRESNEL;
+  if (o->precision == SFT_PREC_FP64) return pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET>(o->K, d->nd);
+  if (d->storage == SFT_STORE_F32)
+    return o->precision == SFT_PREC_FP32_KAHAN ? pick_kern<float2, SFT_PREC_FP32_KAHAN>(kern, o->K, d->nd)
+                                               : pick_kern<float2, SFT_PREC_FP32_NAIVE>(kern, o->K, d->nd);
+  return o->precision == SFT_PREC_FP32_KAHAN ? pick_kern<bf16x2, SFT_PREC_FP32_KAHAN>(kern, o->K, d->nd)
+                                             : pick_kern<bf16x2, SFT_PREC_FP32_NAIVE>(kern, o->K, d->nd);
+}
+
+__global__ void zero_counter_kernel(int32_t* c)
+{
+  if (threadIdx.x == 0) c[0] = 0;
 }
 
 static sft_status validate_scan(const sft_data* d, const sft_opts* o)
@@ -669,27 +786,50 @@ static sft_status validate_scan(const sft_data* d, const sft_opts* o)
   return SFT_OK;
 }
 
-extern "C" sft_status sft_template_bank_scan(const sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o,
-                                             sft_out* out, void* hip_stream)
+static sft_status validate_io(const sft_bank* bank, int64_t n, const sft_out* out)
 {
-  sft_status s = validate_scan(d, o);
-  if (s != SFT_OK) return s;
   if (!bank || !out) return fail(SFT_E_INVALID, "scan: null bank or output");
   if (n < 0) return fail(SFT_E_INVALID, "scan: negative template count");
   if (n == 0) return SFT_OK;
   if (!bank->mc || !bank->t_c) return fail(SFT_E_INVALID, "scan: bank.mc and bank.t_c are required");
   if (!out->zp || !out->zx || !out->hhp || !out->hhx || !out->rho || !out->flags)
     return fail(SFT_E_INVALID, "scan: every output array is required");
-  if (n > (int64_t)INT32_MAX * 256) return fail(SFT_E_RANGE, "scan: too many templates");
-  hipStream_t st = (hipStream_t)hip_stream;
+  if (n > (int64_t)INT32_MAX) return fail(SFT_E_RANGE, "scan: too many templates");
+  return SFT_OK;
+}
 
+static sft_status validate_tuning(const sft_tuning* t)
+{
+  if (!t) return fail(SFT_E_INVALID, "tuning: null");
+  if (t->block != 0 && t->block != 64 && t->block != 128 && t->block != 256)
+    return fail(SFT_E_RANGE, "tuning: block must be 0, 64, 128 or 256 (got %d)", t->block);
+  if (t->chunk_groups < 0) return fail(SFT_E_RANGE, "tuning: chunk_groups must be >= 0");
+  if (t->persistent != 0 && t->persistent != 1) return fail(SFT_E_RANGE, "tuning: persistent must be 0 or 1");
+  return SFT_OK;
+}
+
+// A scan prepared for launch: arguments, launch shape and workspace layout.
+struct Prepared {
   ScanArgs a;
+  ScanFn fn;
+  dim3 grid, block;
+  size_t part_bytes, flag_bytes, counter_off, ws_bytes;
+  int64_t n;
+  double a_plus, a_cross;
+};
+
+static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o,
+                               const sft_tuning& t, Prepared& P)
+{
+  ScanArgs& a = P.a;
+  std::memset(&a, 0, sizeof(a));
   a.bins = d->bins;
   a.psd = d->psd;
-  a.t_mid = d->t_mid;
+  a.g_tmid = d->g_tmid;
+  a.g_rows = d->g_rows;
   a.fp = d->fp;
   a.fx = d->fx;
-  a.n_sft = d->n_sft;
+  a.n_groups = d->n_groups;
   a.n_ext = d->n_ext;
   a.k_ext_lo = d->k_ext_lo;
   a.n_bins = d->n_bins;
@@ -706,41 +846,236 @@ extern "C" sft_status sft_template_bank_scan(const sft_data* d, const sft_bank* 
   a.a_first = bank->a_first;
   a.a_last = bank->a_last;
   a.n_tmpl = n;
-  a.n_chunks = choose_chunks(n, d->n_sft);
-  a.chunk = (d->n_sft + a.n_chunks - 1) / a.n_chunks;
-  a.n_chunks = (d->n_sft + a.chunk - 1) / a.chunk;
-
-  size_t part_bytes = (size_t)a.n_chunks * 6 * n * sizeof(double);
-  size_t flag_bytes = (size_t)a.n_chunks * n * sizeof(uint32_t);
-  void* ws = nullptr;
-  HIP_OR_FAIL(hipMallocAsync(&ws, part_bytes + flag_bytes, st));
-  a.part = (double*)ws;
-  a.pflags = (uint32_t*)((char*)ws + part_bytes);
-
-  dim3 grid((unsigned)((n + 255) / 256), (unsigned)a.n_chunks);
-  const int kern = o->kernel == SFT_KERNEL_DIRICHLET ? KERN_DIRICHLET : KERN_FRESNEL;
-  hipEvent_t ev_b, ev_e;
-  timing_slot(&ev_b, &ev_e);
-  if (ev_b) (void)hipEventRecord(ev_b, st);
-  hipError_t e;
-  if (o->precision == SFT_PREC_FP64) {
-    e = launch_k<double2, SFT_PREC_FP64, KERN_DIRICHLET>(a, grid, st);
-  } else if (d->storage == SFT_STORE_F32) {
-    e = o->precision == SFT_PREC_FP32_KAHAN ? launch_kern<float2, SFT_PREC_FP32_KAHAN>(a, kern, grid, st)
-                                            : launch_kern<float2, SFT_PREC_FP32_NAIVE>(a, kern, grid, st);
+  P.fn = pick_kernel(d, o);
+  const int B = t.block ? t.block : 256;
+  a.n_tiles = (int32_t)((n + B - 1) / B);
+  int nb_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb_cu, (const void*)P.fn, B, 0) != hipSuccess || nb_cu < 1)
+    nb_cu = 1;
+  const int64_t resident = (int64_t)nb_cu * d->cu_count;
+  int64_t nc;
+  if (t.chunk_groups > 0) {
+    nc = (d->n_groups + t.chunk_groups - 1) / t.chunk_groups;
   } else {
-    e = o->precision == SFT_PREC_FP32_KAHAN ? launch_kern<bf16x2, SFT_PREC_FP32_KAHAN>(a, kern, grid, st)
-                                            : launch_kern<bf16x2, SFT_PREC_FP32_NAIVE>(a, kern, grid, st);
+    // automatic: chunks of about 1 MiB of bins (they stay in L2 while the tiles of the
+    // chunk run) and at least ~4 work items per resident block (short last wave)
+    const size_t bin_sz = d->storage == SFT_STORE_F64 ? 16 : d->storage == SFT_STORE_F32 ? 8 : 4;
+    const size_t group_bytes = (size_t)d->nd * d->n_ext * bin_sz;
+    const int64_t g_l2 = std::max<int64_t>(1, (int64_t)((1u << 20) / std::max<size_t>(group_bytes, 1)));
+    nc = std::max<int64_t>((d->n_groups + g_l2 - 1) / g_l2, (4 * resident + a.n_tiles - 1) / a.n_tiles);
+    nc = std::min<int64_t>(std::max<int64_t>(nc, 1), std::max(1, d->n_groups / 4));
   }
+  nc = std::min<int64_t>(std::max<int64_t>(nc, 1), std::min<int64_t>(d->n_groups, 65535));
+  a.chunk = (int32_t)((d->n_groups + nc - 1) / nc);
+  a.n_chunks = (d->n_groups + a.chunk - 1) / a.chunk;
+  if ((int64_t)a.n_tiles * a.n_chunks > INT32_MAX) return fail(SFT_E_RANGE, "scan: too many work items");
+  a.n_items = a.n_tiles * a.n_chunks;
+  a.persistent = t.block == 0 && t.chunk_groups == 0 && t.persistent == 0 ? 1 : t.persistent;
+  P.block = dim3(B);
+  if (a.persistent) P.grid = dim3((unsigned)std::min<int64_t>(a.n_items, resident));
+  else P.grid = dim3((unsigned)a.n_tiles, (unsigned)a.n_chunks);
+  P.part_bytes = (size_t)a.n_chunks * 6 * n * sizeof(double);
+  P.flag_bytes = (size_t)a.n_chunks * n * sizeof(uint32_t);
+  P.counter_off = (P.part_bytes + P.flag_bytes + 255) / 256 * 256;
+  P.ws_bytes = P.counter_off + 256;
+  P.n = n;
+  P.a_plus = o->a_plus;
+  P.a_cross = o->a_cross;
+  return SFT_OK;
+}
+
+// Enqueue [zero counter,] scan, finalize on st.  ws holds P.ws_bytes bytes.
+static hipError_t enqueue_scan(Prepared& P, void* ws, sft_out* out, hipStream_t st, bool timed)
+{
+  ScanArgs& a = P.a;
+  a.part = (double*)ws;
+  a.pflags = (uint32_t*)((char*)ws + P.part_bytes);
+  a.counter = (int32_t*)((char*)ws + P.counter_off);
+  if (a.persistent) {
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, st, a.counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipEvent_t ev_b = nullptr, ev_e = nullptr;
+  if (timed) timing_slot(&ev_b, &ev_e);
+  if (ev_b) (void)hipEventRecord(ev_b, st);
+  void* args[] = {&a};
+  hipError_t e = hipLaunchKernel((const void*)P.fn, P.grid, P.block, args, 0, st);
+  if (e == hipSuccess) e = hipGetLastError();
   if (ev_e) (void)hipEventRecord(ev_e, st);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.part, a.pflags, n,
-                       a.n_chunks, o->a_plus, o->a_cross, out->zp, out->zx, out->hhp, out->hhx, out->rho, out->flags);
-    e = hipGetLastError();
-  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, a.part, a.pflags, P.n,
+                     a.n_chunks, P.a_plus, P.a_cross, out->zp, out->zx, out->hhp, out->hhx, out->rho, out->flags);
+  return hipGetLastError();
+}
+
+extern "C" sft_status sft_template_bank_scan(const sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o,
+                                             sft_out* out, void* hip_stream)
+{
+  sft_status s = validate_scan(d, o);
+  if (s != SFT_OK) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK || n == 0) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Prepared P;
+  if ((s = prepare_scan(d, bank, n, o, d->tune, P)) != SFT_OK) return s;
+  void* ws = nullptr;
+  HIP_OR_FAIL(hipMallocAsync(&ws, P.ws_bytes, st));
+  hipError_t e = enqueue_scan(P, ws, out, st, true);
   hipError_t e2 = hipFreeAsync(ws, st);
   if (e != hipSuccess) return fail(SFT_E_DEVICE, "scan: launch failed: %s", hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(SFT_E_DEVICE, "scan: hipFreeAsync: %s", hipGetErrorString(e2));
+  return SFT_OK;
+}
+
+// ---------------------------------------------------------------------------- tuning
+extern "C" sft_status sft_get_tuning(const sft_data* d, sft_tuning* t)
+{
+  if (!d || !t) return fail(SFT_E_INVALID, "sft_get_tuning: null argument");
+  *t = d->tune;
+  return SFT_OK;
+}
+
+extern "C" sft_status sft_set_tuning(sft_data* d, const sft_tuning* t)
+{
+  if (!d) return fail(SFT_E_INVALID, "sft_set_tuning: null data");
+  sft_status s = validate_tuning(t);
+  if (s != SFT_OK) return s;
+  d->tune = *t;
+  d->tune.reserved = 0;
+  return SFT_OK;
+}
+
+extern "C" sft_status sft_autotune(sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o, sft_out* out,
+                                   void* hip_stream, int32_t reps, sft_tuning* best, float* best_ms)
+{
+  sft_status s = validate_scan(d, o);
+  if (s != SFT_OK) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK) return s;
+  if (n == 0) return fail(SFT_E_INVALID, "sft_autotune: needs at least one template");
+  if (reps < 1 || reps > 100) return fail(SFT_E_RANGE, "sft_autotune: reps must be in [1, 100]");
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<sft_tuning> cand;
+  const int blocks[] = {64, 128, 256};
+  const int nchunks[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  for (int b : blocks)
+    for (int nc : nchunks) {
+      if (nc > d->n_groups) continue;
+      for (int pers = 0; pers < 2; ++pers) {
+        sft_tuning t{};
+        t.block = b;
+        t.chunk_groups = (d->n_groups + nc - 1) / nc;
+        t.persistent = pers;
+        cand.push_back(t);
+      }
+    }
+  std::vector<Prepared> preps(cand.size());
+  size_t ws_max = 0;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    if ((s = prepare_scan(d, bank, n, o, cand[i], preps[i])) != SFT_OK) return s;
+    ws_max = std::max(ws_max, preps[i].ws_bytes);
+  }
+  void* ws = nullptr;
+  HIP_OR_FAIL(hipMallocAsync(&ws, ws_max, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float bms = 3.4e38f;
+  size_t bi = 0;
+  for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
+    e = enqueue_scan(preps[i], ws, out, st, false);   // warm-up
+    if (e != hipSuccess) break;
+    if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = enqueue_scan(preps[i], ws, out, st, false);
+    if (e != hipSuccess) break;
+    if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+    ms /= (float)reps;
+    if (ms < bms) {
+      bms = ms;
+      bi = i;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  hipError_t e2 = hipFreeAsync(ws, st);
+  if (e != hipSuccess) return fail(SFT_E_DEVICE, "sft_autotune: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(SFT_E_DEVICE, "sft_autotune: hipFreeAsync: %s", hipGetErrorString(e2));
+  d->tune = cand[bi];
+  if (best) *best = cand[bi];
+  if (best_ms) *best_ms = bms;
+  return SFT_OK;
+}
+
+// ---------------------------------------------------------------------------- graph plans
+struct sft_plan {
+  Prepared P;
+  void* ws;
+  sft_out out;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" void sft_plan_destroy(sft_plan* p)
+{
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->ws) (void)hipFree(p->ws);
+  delete p;
+}
+
+extern "C" sft_status sft_plan_create(const sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o,
+                                      sft_out* out, sft_plan** plan)
+{
+  if (!plan) return fail(SFT_E_INVALID, "sft_plan_create: null plan pointer");
+  *plan = nullptr;
+  sft_status s = validate_scan(d, o);
+  if (s != SFT_OK) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK) return s;
+  if (n == 0) return fail(SFT_E_INVALID, "sft_plan_create: needs at least one template");
+  sft_plan* p = new sft_plan();
+  p->ws = nullptr;
+  p->graph = nullptr;
+  p->exec = nullptr;
+  p->out = *out;
+  if ((s = prepare_scan(d, bank, n, o, d->tune, p->P)) != SFT_OK) {
+    delete p;
+    return s;
+  }
+  hipError_t e = hipMalloc(&p->ws, p->P.ws_bytes);
+  if (e != hipSuccess) {
+    sft_plan_destroy(p);
+    return fail(e == hipErrorOutOfMemory ? SFT_E_NOMEM : SFT_E_DEVICE, "sft_plan_create: hipMalloc: %s", hipGetErrorString(e));
+  }
+  hipStream_t cs = nullptr;
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) {
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t el = enqueue_scan(p->P, p->ws, &p->out, cs, false);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(cs, &g);
+      p->graph = g;
+      if (el != hipSuccess) e = el;
+    }
+    (void)hipStreamDestroy(cs);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    sft_plan_destroy(p);
+    return fail(SFT_E_DEVICE, "sft_plan_create: graph capture: %s", hipGetErrorString(e));
+  }
+  *plan = p;
+  return SFT_OK;
+}
+
+extern "C" sft_status sft_plan_launch(sft_plan* p, void* hip_stream)
+{
+  if (!p) return fail(SFT_E_INVALID, "sft_plan_launch: null plan");
+  hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(SFT_E_DEVICE, "sft_plan_launch: %s", hipGetErrorString(e));
   return SFT_OK;
 }
 

@@ -53,8 +53,18 @@ class Out(ctypes.Structure):
                 ("hhx", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("chunk_groups", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"block": self.block, "chunk_groups": self.chunk_groups, "persistent": self.persistent}
+
+
 EXPORTS = ["sft_load_data", "sft_free_data", "sft_default_opts", "sft_template_bank_scan",
-           "sft_inner_product", "sft_last_error", "sft_version", "sft_kernel_timing", "sft_kernel_times"]
+           "sft_inner_product", "sft_last_error", "sft_version", "sft_kernel_timing", "sft_kernel_times",
+           "sft_get_tuning", "sft_set_tuning", "sft_autotune", "sft_plan_create", "sft_plan_launch",
+           "sft_plan_destroy"]
 
 _lib = None
 
@@ -85,6 +95,20 @@ def lib():
     L.sft_last_error.restype = ctypes.c_char_p
     L.sft_version.argtypes = []
     L.sft_version.restype = ctypes.c_char_p
+    L.sft_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    L.sft_get_tuning.restype = ctypes.c_int32
+    L.sft_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    L.sft_set_tuning.restype = ctypes.c_int32
+    L.sft_autotune.argtypes = [P, ctypes.POINTER(Bank), ctypes.c_int64, ctypes.POINTER(Opts), ctypes.POINTER(Out),
+                               P, ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_float)]
+    L.sft_autotune.restype = ctypes.c_int32
+    L.sft_plan_create.argtypes = [P, ctypes.POINTER(Bank), ctypes.c_int64, ctypes.POINTER(Opts),
+                                  ctypes.POINTER(Out), ctypes.POINTER(P)]
+    L.sft_plan_create.restype = ctypes.c_int32
+    L.sft_plan_launch.argtypes = [P, P]
+    L.sft_plan_launch.restype = ctypes.c_int32
+    L.sft_plan_destroy.argtypes = [P]
+    L.sft_plan_destroy.restype = None
     L.sft_kernel_timing.argtypes = [ctypes.c_int32]
     L.sft_kernel_timing.restype = ctypes.c_int32
     L.sft_kernel_times.argtypes = [P, ctypes.c_int32]
@@ -252,3 +276,55 @@ def kernel_times(max_records: int = 4096):
     buf = (ctypes.c_float * max_records)()
     n = lib().sft_kernel_times(ctypes.cast(buf, ctypes.c_void_p), max_records)
     return [buf[i] for i in range(min(n, max_records))]
+
+
+def get_tuning(data: SFTData) -> Tuning:
+    t = Tuning()
+    _check(lib().sft_get_tuning(data.handle, ctypes.byref(t)))
+    return t
+
+
+def set_tuning(data: SFTData, block=0, chunk_groups=0, persistent=0):
+    t = Tuning(int(block), int(chunk_groups), int(persistent), 0)
+    _check(lib().sft_set_tuning(data.handle, ctypes.byref(t)))
+
+
+def autotune(data: SFTData, bank_t, opts: Opts, out=None, stream=None, reps=2):
+    """Time candidate launch shapes on this bank; the best is kept by the handle."""
+    n = int(bank_t["mc"].numel())
+    out = alloc_out(n, device=bank_t["mc"].device) if out is None else out
+    b, o = _bank_struct(bank_t), _out_struct(out)
+    t = Tuning()
+    ms = ctypes.c_float()
+    _check(lib().sft_autotune(data.handle, ctypes.byref(b), n, ctypes.byref(opts), ctypes.byref(o),
+                              _stream_ptr(stream), int(reps), ctypes.byref(t), ctypes.byref(ms)))
+    return t, ms.value
+
+
+class Plan:
+    """A bank scan captured into a HIP graph (fixed bank/output pointers)."""
+
+    def __init__(self, data: SFTData, bank_t, opts: Opts, out=None):
+        n = int(bank_t["mc"].numel())
+        self.out = alloc_out(n, device=bank_t["mc"].device) if out is None else out
+        self._bank_t, self._data = bank_t, data
+        b, o = _bank_struct(bank_t), _out_struct(self.out)
+        h = ctypes.c_void_p()
+        _check(lib().sft_plan_create(data.handle, ctypes.byref(b), n, ctypes.byref(opts), ctypes.byref(o),
+                                     ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().sft_plan_launch(self.handle, _stream_ptr(stream)))
+        return self.out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().sft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,6 +16,14 @@ Workloads (all synthetic; the paper's data are simulated signals too):
                  with a U[0.8, 1.2] scale per SFT, antenna patterns with a one-day
                  period, stored band bins [32, 512), 1e5 templates with
                  Mc ~ U[1.0, 1.5], t_c = 131672 s, K = 8, automatic kernel.
+  * ``space``  : one detector, 60 SFTs of 2 days at 0.2 Hz (34560 samples, band
+                 bins [0, 1792) = 0 .. 1.04e-2 Hz), white noise, antenna patterns with
+                 a one-year period; 2e5 templates with Mc log-uniform in [1e5, 1e6]
+                 Msun, each using its last n_use ~ U{8..60} SFTs (ragged), K = 32.
+                 t_c puts the last SFT midpoint tau_end = 3.5e5 s (Mc/1e5)^(-5/19)
+                 before coalescence (the recipe constant is derived in the design
+                 notes so that the last SFT keeps the Taylor residual below 3 bins
+                 and the drift below 48 bins).
 Noise in the ``ground`` workload is drawn directly in the SFT domain (independent
 Gaussian bins of variance T S / 4 per quadrature), which is the exact law of the
 SFT of stationary Gaussian noise under a rectangular window when leakage is
@@ -151,3 +159,31 @@ def ground(seed: int = 2, n_templates: int = 100_000, n_slots: int = 4096, n_det
     bank = uniform_bank(n_templates, mc_lo, mc_hi, t_c, seed + 1000, n_sft=n_sft)
     return Workload("ground", t_start, det, n, t_sft, k_lo, xb, psd, fplus, fcross, bank,
                     dict(K=8, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0))
+
+
+YEAR = 3.15576e7
+
+
+def space(seed: int = 3, n_templates: int = 200_000, n_sft: int = 60, n_use_lo: int = 8,
+          n_use_hi: int = 60) -> Workload:
+    """Space-based-like massive-BBH bank with ragged SFT ranges (one detector)."""
+    fs, t_sft = 0.2, 2 * DAY
+    n = int(round(fs * t_sft))
+    k_lo, k_hi = 0, 1792
+    g = rng(seed)
+    t_start = np.arange(n_sft) * t_sft
+    psd = np.ones((n_sft, k_hi - k_lo))
+    xb = sft_domain_noise(psd, t_sft, seed + 17)
+    ph = 2.0 * np.pi * (t_start + 0.5 * t_sft) / YEAR
+    fplus, fcross = np.cos(ph), np.sin(ph)
+    mc = np.exp(g.uniform(np.log(1e5), np.log(1e6), n_templates))
+    n_use = g.integers(n_use_lo, n_use_hi + 1, n_templates)
+    a_first = (n_sft - n_use).astype(np.int32)
+    o = np.lexsort((mc, a_first))             # group templates of equal range, then by mass
+    mc, a_first = mc[o], a_first[o]
+    t_mid_last = t_start[-1] + 0.5 * t_sft
+    t_c = t_mid_last + 3.5e5 * (mc / 1e5) ** (-5.0 / 19.0)
+    bank = {"mc": mc, "q": np.ones(n_templates), "t_c": t_c, "phi_c": np.zeros(n_templates),
+            "a_first": a_first, "a_last": np.full(n_templates, n_sft - 1, np.int32)}
+    return Workload("space", t_start, np.zeros(n_sft, np.int32), n, t_sft, k_lo, xb, psd, fplus, fcross,
+                    bank, dict(K=32, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0))

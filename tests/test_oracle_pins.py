@@ -372,3 +372,45 @@ def test_p15_oracle_rounding(orc, small_ground):
     a = orc.scan(data, w.bank["mc"], w.bank["t_c"], K=8, compensated=True)
     b = orc.scan(data, w.bank["mc"], w.bank["t_c"], K=8, compensated=False)
     assert np.max(np.abs(a["zp"] - b["zp"]) / np.sqrt(a["hhp"])) < 1e-11
+
+
+# --------------------------------------------------------------------------- P13
+def test_p13_pn35_series_consistency(orc):
+    """P13 (reading R21): the 3.5PN phase series and the independently transcribed
+    frequency series satisfy d(phi)/dt = 2 pi f up to the first omitted order: the
+    residual falls as Theta^-1 at full order (4PN truncation) and as Theta^-(k+1)/8 or
+    faster when truncated after half-order k; a wrong coefficient at order k would leave
+    a residual falling only as Theta^-k/8.  Order 0 is the Newtonian chirp."""
+    try:
+        for q in (1.0, 1.5, 2.0):
+            mc = 1.2
+            nu = q / (1 + q) ** 2
+            M = mc * nu ** -0.6 * orc.T_SUN
+            for order, slope_min in [(2, 0.48), (4, 0.55), (5, 0.73), (6, 0.74), (7, 0.99)]:
+                orc.set_pn_order(order)
+                th = np.array([1e4, 1e5, 1e6, 1e7])
+                r = np.array([orc.pn35_consistency(mc, q, t * 5 * M / nu) for t in th])
+                slopes = np.log10(np.abs(r[:-1] / r[1:]))
+                assert np.all(slopes > slope_min), (q, order, slopes)
+            orc.set_pn_order(7)
+            assert abs(orc.pn35_consistency(mc, q, 1e6 * 5 * M / nu)) < 1e-6
+        # order 0 reproduces the Newtonian chirp
+        orc.set_pn_order(0)
+        t = np.array([0.0, 5e4, 9.9e4])
+        a = orc.waveform(1.3, 1e5, 0.4, t, q=1.7, wf=orc.WF_PN35)
+        b = orc.waveform(1.3, 1e5, 0.4, t, wf=orc.WF_NEWTON)
+        assert np.max(np.abs(a - b) / np.abs(b)) < 1e-13
+    finally:
+        orc.set_pn_order(7)
+    # analytic fdot, fddot against finite differences of f, fdot; the amplitude stays
+    # within a few per cent of the Newtonian one in this early-inspiral range
+    mc, q, tc = 1.2, 1.4, 2e5
+    t = np.array([0.0, 1e5, 1.9e5])
+    h = 2.0
+    w0 = orc.waveform(mc, tc, 0, t, q=q, wf=orc.WF_PN35)
+    wp = orc.waveform(mc, tc, 0, t + h, q=q, wf=orc.WF_PN35)
+    wm = orc.waveform(mc, tc, 0, t - h, q=q, wf=orc.WF_PN35)
+    assert np.max(np.abs((wp[:, 2] - wm[:, 2]) / (2 * h) / w0[:, 3] - 1)) < 1e-7
+    assert np.max(np.abs((wp[:, 3] - wm[:, 3]) / (2 * h) / w0[:, 4] - 1)) < 1e-6
+    wn = orc.waveform(mc, tc, 0, t, wf=orc.WF_NEWTON)
+    assert np.all(np.abs(w0[:, 0] / wn[:, 0] - 1) < 0.05)
