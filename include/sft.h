@@ -52,8 +52,9 @@ enum { SFT_KERNEL_DIRICHLET = 0, SFT_KERNEL_FRESNEL = 1, SFT_KERNEL_AUTO = 2 };
 /* arithmetic of the bin contraction and of the sums over SFTs; the waveform
  * phase, its reduction mod 2 pi and the bin split are FP64 in every mode */
 enum { SFT_PREC_FP64 = 0, SFT_PREC_FP32_KAHAN = 1, SFT_PREC_FP32_NAIVE = 2 };
-/* waveform model */
-enum { SFT_WF_NEWTON = 0 };
+/* waveform model: leading-order (Newtonian) chirp, or the 3.5PN closed-form inspiral
+ * (needs F32 or F64 storage; reads the bank's mass ratio q >= 1, NULL => q = 1) */
+enum { SFT_WF_NEWTON = 0, SFT_WF_PN35 = 1 };
 
 /* per-template flag bits */
 enum {
@@ -122,7 +123,10 @@ void sft_default_opts(sft_opts* opts);
 /* Template bank, structure of arrays in DEVICE memory owned by the caller.
  * Leading-order chirp (Newtonian) with chirp mass mc [Msun], coalescence time
  * t_c [s] and phase phi_c [rad]: f = (5M/tau)^{3/8}/(8 pi M), phi = phi_c - 2 (tau/5M)^{5/8},
- * A = (pi M f)^{2/3}, tau = t_c - t.  Template m uses SFT rows a_first[m]..a_last[m]
+ * A = (pi M f)^{2/3}, tau = t_c - t, M = mc * tsun.  The 3.5PN waveform uses in addition
+ * the mass ratio q (nu = q/(1+q)^2, total mass mc nu^(-3/5)); its phase and frequency are
+ * the post-Newtonian series in Theta = nu tau / (5 M_total) and its amplitude the
+ * dominant-mode amplitude through 2PN.  Template m uses SFT rows a_first[m]..a_last[m]
  * (inclusive, clamped to the data).  q (mass ratio) is read only by waveforms that
  * depend on it and may be NULL otherwise; phi_c, a_first, a_last may be NULL
  * (0, 0, n_sft - 1). */

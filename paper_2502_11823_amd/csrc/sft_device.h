@@ -121,6 +121,91 @@ __device__ inline Chirp newton_chirp(double tau, double inv5M, double cf, double
   return c;
 }
 
+// 3.5PN closed-form inspiral in Theta = nu (t_c - t) / (5 M), M the total mass [s] (the
+// time-domain post-Newtonian phase and frequency series of the PN literature; Blanchet,
+// Living Rev. Relativ. 17 (2014) 2).  With s = Theta^(-1/8) and L = ln Theta:
+//   GW phase  phi = phi_c - (2/nu) Theta s^3 [1 + sum_k p_k s^k]        (Theta^(5/8) = Theta s^3)
+//   X = 4 x = s^2 [1 + sum_k q_k s^k],  x = (M omega)^(2/3),  f = x^(3/2) / (pi M)
+// k = 2..7; p_5 = c5 L, p_6 = c6 + d6 L, q_6 = e6 + g6 L.  d/dTheta of c(L) Theta^p is
+// Theta^(p-1) (p c + c'), c' = dc/dL; 1/Theta = s^8.  Amplitude
+//   A = nu^(2/5) x (1 + x(-107/42 + 55 nu/42) + 2 pi x^(3/2) + x^2(-2173/1512 - 1069 nu/216 + 2047 nu^2/1512)).
+struct PNCoef {
+  double p2, p3, p4, c5, p6, d6, p7;   // phase series
+  double q2, q3, q4, q5, e6, g6, q7;   // x series
+  double a2, a4;                        // amplitude 1PN and 2PN factors
+};
+
+__device__ inline PNCoef pn_coefficients(double nu)
+{
+  const double pi = kPi, pi2 = kPi * kPi, euler = 0.57721566490153286061, ln256 = 5.5451774444795624753;
+  const double n2 = nu * nu, n3 = n2 * nu;
+  PNCoef c;
+  c.p2 = 3715.0 / 8064.0 + 55.0 / 96.0 * nu;
+  c.p3 = -0.75 * pi;
+  c.p4 = 9275495.0 / 14450688.0 + 284875.0 / 258048.0 * nu + 1855.0 / 2048.0 * n2;
+  c.c5 = (-38645.0 / 172032.0 + 65.0 / 2048.0 * nu) * pi;
+  c.d6 = 107.0 / 448.0;
+  c.p6 = 831032450749357.0 / 57682522275840.0 - 53.0 / 40.0 * pi2 - 107.0 / 56.0 * euler
+         + (-126510089885.0 / 4161798144.0 + 2255.0 / 2048.0 * pi2) * nu + 154565.0 / 1835008.0 * n2
+         - 1179625.0 / 1769472.0 * n3 - c.d6 * ln256;
+  c.p7 = (188516689.0 / 173408256.0 + 488825.0 / 516096.0 * nu - 141769.0 / 516096.0 * n2) * pi;
+  c.q2 = 743.0 / 4032.0 + 11.0 / 48.0 * nu;
+  c.q3 = -0.2 * pi;
+  c.q4 = 19583.0 / 254016.0 + 24401.0 / 193536.0 * nu + 31.0 / 288.0 * n2;
+  c.q5 = (-11891.0 / 53760.0 + 109.0 / 1920.0 * nu) * pi;
+  c.g6 = -107.0 / 3360.0;
+  c.e6 = -10052469856691.0 / 6008596070400.0 + pi2 / 6.0 + 107.0 / 420.0 * euler
+         + (3147553127.0 / 780337152.0 - 451.0 / 3072.0 * pi2) * nu - 15211.0 / 442368.0 * n2
+         + 25565.0 / 1327104.0 * n3 - c.g6 * ln256;
+  c.q7 = (-113868647.0 / 433520640.0 - 31821.0 / 143360.0 * nu + 294941.0 / 3870720.0 * n2) * pi;
+  c.a2 = -107.0 / 42.0 + 55.0 / 42.0 * nu;
+  c.a4 = -2173.0 / 1512.0 - 1069.0 / 216.0 * nu + 2047.0 / 1512.0 * n2;
+  return c;
+}
+
+// 3.5PN chirp at tau > 0; inv5Mnu = nu / (5 M), Mt = M [s], nu25 = nu^(2/5).
+__device__ inline Chirp pn35_chirp(double tau, double nu, double inv5Mnu, double Mt, double nu25,
+                                   double phi_c, double T, const PNCoef& c)
+{
+  const double th = tau * inv5Mnu;
+  const float thf = (float)th;
+  double s = (double)__builtin_amdgcn_exp2f(-0.125f * __builtin_amdgcn_logf(thf));
+  for (int it = 0; it < 2; ++it) {
+    const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
+    s = fma(s * 0.125, fma(-th, s8, 1.0), s);
+  }
+  const double L = log(th);
+  const double s2 = s * s, s3 = s2 * s, s4 = s2 * s2, s5 = s4 * s, s6 = s4 * s2, s7 = s6 * s, s8 = s4 * s4;
+  // phase bracket
+  const double p5 = c.c5 * L, p6 = fma(c.d6, L, c.p6);
+  const double Pb = 1.0 + c.p2 * s2 + c.p3 * s3 + c.p4 * s4 + p5 * s5 + p6 * s6 + c.p7 * s7;
+  // x bracket, terms q_k(L) s^(2+k) with powers p_k = -1/4 - k/8
+  const double q6 = fma(c.g6, L, c.e6);
+  const double t0 = s2, t2 = c.q2 * s4, t3 = c.q3 * s5, t4 = c.q4 * s6, t5 = c.q5 * s7, t6 = q6 * s8, t7 = c.q7 * s8 * s;
+  const double X = t0 + t2 + t3 + t4 + t5 + t6 + t7;
+  // dX/dTheta = s^8 sum_k (p_k term_k + g6 s^8 [k = 6]);  d2X/dTheta2 = s^16 sum_k ((p_k-1)(p_k term_k + b_k) + p_k b_k)
+  const double g6s = c.g6 * s8;
+  const double e0 = -0.25 * t0, e2 = -0.5 * t2, e3 = -0.625 * t3, e4 = -0.75 * t4, e5 = -0.875 * t5,
+               e6 = -1.0 * t6 + g6s, e7 = -1.125 * t7;
+  const double dX = s8 * (e0 + e2 + e3 + e4 + e5 + e6 + e7);
+  const double d2X = s8 * s8 * (-1.25 * e0 - 1.5 * e2 - 1.625 * e3 - 1.75 * e4 - 1.875 * e5
+                                + (-2.0 * e6 - g6s) - 2.125 * e7);
+  const double x = 0.25 * X, dx = 0.25 * dX, d2x = 0.25 * d2X;
+  const double sx = sqrt(x);
+  const double ipm = 1.0 / (kPi * Mt);
+  const double dth = -inv5Mnu;
+  Chirp ch;
+  const double f = x * sx * ipm;
+  ch.kappa = f * T;
+  ch.phase = fma(-2.0 / nu * th * s3, Pb, phi_c);
+  ch.amp = nu25 * x * (1.0 + x * (c.a2 + x * c.a4) + 2.0 * kPi * x * sx);
+  const double fdot = 1.5 * sx * dx * dth * ipm;
+  const double fddot = (0.75 / sx * dx * dx + 1.5 * sx * d2x) * dth * dth * ipm;
+  ch.beta = fdot * T * T;
+  ch.dres = 0.125 * fddot * T * T * T;
+  return ch;
+}
+
 // phi mod 2 pi in [-pi, pi] (two-constant Cody-Waite reduction in FP64)
 __device__ inline double reduce_2pi(double phi)
 {

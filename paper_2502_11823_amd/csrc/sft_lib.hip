@@ -351,6 +351,7 @@ struct ScanArgs {
   int32_t n_groups, n_ext, k_ext_lo, n_bins, k_lo, K;
   double T, beta_switch, tsun, delta_max;
   const double* mc;
+  const double* q;
   const double* t_c;
   const double* phi_c;
   const int32_t* a_first;
@@ -366,6 +367,7 @@ struct ScanArgs {
 };
 
 enum { KERN_DIRICHLET = 0, KERN_FRESNEL = 1 };
+enum { WF_NEWTON = SFT_WF_NEWTON, WF_PN35 = SFT_WF_PN35 };
 
 // unroll factor of the bin loops (4 keeps the Fresnel kernel at 5 waves per SIMD)
 #ifndef SFT_BIN_UNROLL
@@ -406,10 +408,10 @@ __device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // a group (one per detector) share the SFT midpoint, hence the chirp, the window and
 // all 2K+1 kernel weights: those are evaluated once per group and contracted with the
 // bins of each of the ND rows (the projector Lambda carries the detector dependence).
-template <typename Bin, int PREC, int KERN, int KC, int ND>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
 __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab);
 
-template <typename Bin, int PREC, int KERN, int KC, int ND>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
 __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
 {
   __shared__ float2 tab[SFT_G_NINT * (SFT_G_DEG + 1)];
@@ -438,12 +440,12 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
     const int tile = item % a.n_tiles;
     const int c = item / a.n_tiles;
     const int64_t m = (int64_t)tile * blockDim.x + threadIdx.x;
-    if (m < a.n_tmpl) scan_item<Bin, PREC, KERN, KC, ND>(a, K, m, c, tab);
+    if (m < a.n_tmpl) scan_item<Bin, PREC, KERN, KC, ND, WF>(a, K, m, c, tab);
     if (!a.persistent) break;
   }
 }
 
-template <typename Bin, int PREC, int KERN, int KC, int ND>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
 __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab)
 {
   using R = typename PrecTraits<PREC>::R;
@@ -460,6 +462,18 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
   const double cf = T / (8.0 * kPi * M);
   const double tc = a.t_c[m];
   const double phic = a.phi_c ? a.phi_c[m] : 0.0;
+  // 3.5PN: symmetric mass ratio, total mass, nu/(5M), nu^(2/5) and the series coefficients
+  double nu = 0.25, Mt = 0.0, inv5Mnu = 0.0, nu25 = 0.0;
+  PNCoef pcf{};
+  if constexpr (WF == WF_PN35) {
+    double qq = a.q ? a.q[m] : 1.0;
+    if (!(qq >= 1.0)) qq = 1.0 / qq;
+    nu = qq / ((1.0 + qq) * (1.0 + qq));
+    Mt = a.mc[m] * pow(nu, -0.6) * a.tsun;
+    inv5Mnu = nu / (5.0 * Mt);
+    nu25 = pow(nu, 0.4);
+    pcf = pn_coefficients(nu);
+  }
   const Bin* __restrict__ bins = (const Bin*)a.bins;
   const PS* __restrict__ psd = (const PS*)a.psd;
 
@@ -482,7 +496,9 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       fl |= kFlagTau;
       continue;
     }
-    const Chirp ch = newton_chirp(tau, inv5M, cf, phic, T);
+    Chirp ch;
+    if constexpr (WF == WF_PN35) ch = pn35_chirp(tau, nu, inv5Mnu, Mt, nu25, phic, T, pcf);
+    else ch = newton_chirp(tau, inv5M, cf, phic, T);
     if (a.delta_max > 0.0 && ch.dres > a.delta_max) fl |= kFlagTaylor;
     if (!(ch.kappa < 1.0e9)) {
       // frequency far above any stored band: no window bin and no norm bin exists
@@ -727,39 +743,52 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
 // ---------------------------------------------------------------------------- dispatch
 using ScanFn = void (*)(ScanArgs);
 
-template <typename Bin, int PREC, int KERN, int KC>
+// Newtonian: every detector-group width 1..4.  3.5PN: widths 1 and 4 (groups of 2 or 3
+// rows run in the width-4 kernel, whose absent rows are skipped by a uniform test).
+template <typename Bin, int PREC, int KERN, int KC, int WF>
 static ScanFn pick_nd(int nd)
 {
-  switch (nd) {
-  case 1: return scan_kernel<Bin, PREC, KERN, KC, 1>;
-  case 2: return scan_kernel<Bin, PREC, KERN, KC, 2>;
-  case 3: return scan_kernel<Bin, PREC, KERN, KC, 3>;
-  default: return scan_kernel<Bin, PREC, KERN, KC, 4>;
+  if constexpr (WF == WF_NEWTON) {
+    switch (nd) {
+    case 1: return scan_kernel<Bin, PREC, KERN, KC, 1, WF>;
+    case 2: return scan_kernel<Bin, PREC, KERN, KC, 2, WF>;
+    case 3: return scan_kernel<Bin, PREC, KERN, KC, 3, WF>;
+    default: return scan_kernel<Bin, PREC, KERN, KC, 4, WF>;
+    }
+  } else {
+    return nd == 1 ? scan_kernel<Bin, PREC, KERN, KC, 1, WF> : scan_kernel<Bin, PREC, KERN, KC, 4, WF>;
   }
 }
 
-template <typename Bin, int PREC, int KERN>
+template <typename Bin, int PREC, int KERN, int WF>
 static ScanFn pick_k(int K, int nd)
 {
-  if (PREC == SFT_PREC_FP64) return K == 4 ? pick_nd<Bin, PREC, KERN, 4>(nd) : pick_nd<Bin, PREC, KERN, -1>(nd);
-  return K == 8 ? pick_nd<Bin, PREC, KERN, 8>(nd) : pick_nd<Bin, PREC, KERN, -1>(nd);
+  if (PREC == SFT_PREC_FP64) return K == 4 ? pick_nd<Bin, PREC, KERN, 4, WF>(nd) : pick_nd<Bin, PREC, KERN, -1, WF>(nd);
+  return K == 8 ? pick_nd<Bin, PREC, KERN, 8, WF>(nd) : pick_nd<Bin, PREC, KERN, -1, WF>(nd);
 }
 
-template <typename Bin, int PREC>
+template <typename Bin, int PREC, int WF>
 static ScanFn pick_kern(int kern, int K, int nd)
 {
-  return kern == KERN_DIRICHLET ? pick_k<Bin, PREC, KERN_DIRICHLET>(K, nd) : pick_k<Bin, PREC, KERN_FRESNEL>(K, nd);
+  return kern == KERN_DIRICHLET ? pick_k<Bin, PREC, KERN_DIRICHLET, WF>(K, nd) : pick_k<Bin, PREC, KERN_FRESNEL, WF>(K, nd);
 }
 
 static ScanFn pick_kernel(const sft_data* d, const sft_opts* o)
 {
   const int kern = o->kernel == SFT_KERNEL_DIRICHLET ? KERN_DIRICHLET : KERN_FRESNEL;
-  if (o->precision == SFT_PREC_FP64) return pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET>(o->K, d->nd);
-  if (d->storage == SFT_STORE_F32)
-    return o->precision == SFT_PREC_FP32_KAHAN ? pick_kern<float2, SFT_PREC_FP32_KAHAN>(kern, o->K, d->nd)
-                                               : pick_kern<float2, SFT_PREC_FP32_NAIVE>(kern, o->K, d->nd);
-  return o->precision == SFT_PREC_FP32_KAHAN ? pick_kern<bf16x2, SFT_PREC_FP32_KAHAN>(kern, o->K, d->nd)
-                                             : pick_kern<bf16x2, SFT_PREC_FP32_NAIVE>(kern, o->K, d->nd);
+  const bool pn = o->waveform == SFT_WF_PN35;
+  if (o->precision == SFT_PREC_FP64)
+    return pn ? pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_PN35>(o->K, d->nd)
+              : pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_NEWTON>(o->K, d->nd);
+  if (d->storage == SFT_STORE_F32) {
+    if (pn)
+      return o->precision == SFT_PREC_FP32_KAHAN ? pick_kern<float2, SFT_PREC_FP32_KAHAN, WF_PN35>(kern, o->K, d->nd)
+                                                 : pick_kern<float2, SFT_PREC_FP32_NAIVE, WF_PN35>(kern, o->K, d->nd);
+    return o->precision == SFT_PREC_FP32_KAHAN ? pick_kern<float2, SFT_PREC_FP32_KAHAN, WF_NEWTON>(kern, o->K, d->nd)
+                                               : pick_kern<float2, SFT_PREC_FP32_NAIVE, WF_NEWTON>(kern, o->K, d->nd);
+  }
+  return o->precision == SFT_PREC_FP32_KAHAN ? pick_kern<bf16x2, SFT_PREC_FP32_KAHAN, WF_NEWTON>(kern, o->K, d->nd)
+                                             : pick_kern<bf16x2, SFT_PREC_FP32_NAIVE, WF_NEWTON>(kern, o->K, d->nd);
 }
 
 __global__ void zero_counter_kernel(int32_t* c)
@@ -773,7 +802,10 @@ static sft_status validate_scan(const sft_data* d, const sft_opts* o)
   if (o->K < 0 || o->K > SFT_K_MAX) return fail(SFT_E_RANGE, "scan: K=%d outside [0, %d]", o->K, SFT_K_MAX);
   if (o->kernel != SFT_KERNEL_DIRICHLET && o->kernel != SFT_KERNEL_FRESNEL && o->kernel != SFT_KERNEL_AUTO)
     return fail(SFT_E_INVALID, "scan: unknown kernel %d", o->kernel);
-  if (o->waveform != SFT_WF_NEWTON) return fail(SFT_E_UNSUPPORTED, "scan: waveform %d not available", o->waveform);
+  if (o->waveform != SFT_WF_NEWTON && o->waveform != SFT_WF_PN35)
+    return fail(SFT_E_INVALID, "scan: unknown waveform %d", o->waveform);
+  if (o->waveform == SFT_WF_PN35 && d->storage == SFT_STORE_BF16)
+    return fail(SFT_E_UNSUPPORTED, "scan: the 3.5PN waveform needs F32 or F64 storage");
   if (!(o->tsun > 0.0)) return fail(SFT_E_INVALID, "scan: tsun must be positive");
   if (o->precision == SFT_PREC_FP64) {
     if (d->storage != SFT_STORE_F64) return fail(SFT_E_UNSUPPORTED, "scan: FP64 precision needs F64 storage");
@@ -841,6 +873,7 @@ static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t 
   a.tsun = o->tsun;
   a.delta_max = o->delta_max;
   a.mc = bank->mc;
+  a.q = bank->q;
   a.t_c = bank->t_c;
   a.phi_c = bank->phi_c;
   a.a_first = bank->a_first;

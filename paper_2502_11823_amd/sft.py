@@ -19,7 +19,7 @@ SFT_OK = 0
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
 KERNEL = {"dirichlet": 0, "fresnel": 1, "auto": 2}
 PRECISION = {"fp64": 0, "fp32_kahan": 1, "fp32_naive": 2}
-WAVEFORM = {"newton": 0}
+WAVEFORM = {"newton": 0, "pn35": 1}
 FLAG_OUT_OF_BAND, FLAG_TAU_NONPOSITIVE, FLAG_TAYLOR_INVALID, FLAG_NONFINITE, FLAG_EMPTY = 1, 2, 4, 8, 64
 K_MAX = 64
 T_SUN = 4.925490947641267e-6

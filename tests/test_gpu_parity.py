@@ -42,8 +42,9 @@ def orc_scan(w, bank, x_bins=None, psd=None, **kw):
     kw = dict(kw)
     kw.pop("precision", None)
     kw["kernel"] = KERN[kw.get("kernel", "auto")]
-    return oracle.scan(od, bank["mc"], bank["t_c"], phi_c=bank["phi_c"], a_first=bank["a_first"],
-                       a_last=bank["a_last"], **kw)
+    kw["wf"] = {"newton": oracle.WF_NEWTON, "pn35": oracle.WF_PN35}[kw.pop("waveform", "newton")]
+    return oracle.scan(od, bank["mc"], bank["t_c"], phi_c=bank["phi_c"], q=bank.get("q"),
+                       a_first=bank["a_first"], a_last=bank["a_last"], **kw)
 
 
 def compare(g, o, idx=None, tol_z=1e-6, tol_rho=1e-5, tol_hh=1e-6, label="", noise_scale=None):
@@ -360,3 +361,31 @@ def test_precision_sweep_tiny_data_1e5_templates(tiny):
     assert rows[2][2] <= 1e-6 and rows[2][5] <= 1e-5
     assert rows[1][2] < 1e-5
     assert rows[3][2] < 3e-2
+
+
+# ----------------------------------------------------------------------------- 3.5PN waveform
+def _with_q(bank, seed):
+    b = dict(bank)
+    b["q"] = np.random.default_rng(seed).uniform(1.0, 2.0, b["mc"].size)
+    return b
+
+
+@pytest.mark.parametrize("K,kernel", [(8, "auto"), (5, "fresnel")])
+def test_pn35_multidetector(ground_small, K, kernel):
+    """The 3.5PN closed-form waveform (mass ratio per template) against the oracle's
+    independently written series, three detectors, Fresnel kernels."""
+    w = ground_small
+    bank = _with_q(w.bank, 5)
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=K, kernel=kernel, precision="fp32_kahan", a_plus=1.0, a_cross=1.0, waveform="pn35",
+              delta_max=0.05)
+    o = orc_scan(w, bank, **kw)
+    compare(gpu_scan(data, bank, **kw), o, label="pn35 ground-small K=%d %s" % (K, kernel))
+
+
+def test_pn35_fp64_tiny(tiny):
+    bank = _with_q(tiny.bank, 6)
+    data = sft.SFTData.from_workload(tiny, storage="f64")
+    kw = dict(K=4, kernel="dirichlet", precision="fp64", waveform="pn35")
+    e = compare(gpu_scan(data, bank, **kw), orc_scan(tiny, bank, **kw), label="pn35 tiny fp64")
+    assert e < 1e-8
