@@ -22,8 +22,9 @@ _LIB = os.path.join(_HERE, "_liboracle.so")
 # kernel / reference / waveform / flag codes (mirror the enums in sft_oracle.c)
 K_DIRICHLET, K_FRESNEL, K_AUTO, K_DISCRETE, K_QUAD = 0, 1, 2, 3, 4
 REF_MID, REF_START = 0, 1
-WF_NEWTON, WF_PN35 = 0, 1
+WF_NEWTON, WF_PN35, WF_SURROGATE = 0, 1, 2
 F_OUT_OF_BAND, F_TAU_NONPOSITIVE, F_TAYLOR_INVALID, F_NONFINITE, F_EMPTY = 1, 2, 4, 8, 64
+F_SURROGATE_FALLBACK = 32
 
 # GM_sun / c^3 in seconds (IAU 2015 nominal solar mass parameter)
 T_SUN = 4.925490947641267e-6
@@ -65,7 +66,13 @@ def _load():
                                   Int, Int, Int, D, D, D, D, Int, P, P, P]
     lib.orc_scan.argtypes = [L, L, D, L, L, P, P, P, P, P,
                              L, Int, P, P, P, P, P, P,
-                             Int, Int, Int, D, D, D, D, D, Int, P, P, P]
+                             Int, Int, Int, D, D, D, D, D, Int, P, P, P, P]
+    lib.orc_set_surrogate.argtypes = [Int, Int, P, P]
+    lib.orc_mlp_param_count.argtypes = [Int, Int]
+    lib.orc_mlp_param_count.restype = L
+    lib.orc_mlp_forward_eval.argtypes = [P, Int, Int, L, P, P, P]
+    lib.orc_mlp_forward_eval.restype = None
+    lib.orc_surrogate_targets.argtypes = [L, P, P, P, D, Int, D, D, P]
     lib.orc_td_product.argtypes = [P, P, L, D]
     lib.orc_td_product.restype = D
     lib.orc_fd_product.argtypes = [P, P, L, D, P]
@@ -230,16 +237,54 @@ def scan(data: SFTData, mc, t_c, phi_c=None, q=None, a_first=None, a_last=None, 
     out = np.empty((m, 7))
     fl = np.zeros(m, np.uint32)
     tie = np.zeros(m)
+    mm = np.zeros(m)
     rc = _load().orc_scan(*data._args(), _ptr(data.t_start), _ptr(data.x_bins), _ptr(data.psd),
                           _ptr(data.fplus), _ptr(data.fcross), m, int(wf), _ptr(mc), _ptr(q),
                           _ptr(t_c), _ptr(phi_c), _ptr(af), _ptr(al), int(K), int(kernel),
                           int(t_ref), float(beta_switch), float(a_plus), float(a_cross),
                           float(tsun), float(delta_max), int(compensated),
-                          _ptr(out), _ptr(fl), _ptr(tie))
+                          _ptr(out), _ptr(fl), _ptr(tie), _ptr(mm))
     if rc != 0:
         raise MemoryError("oracle scan failed")
     return {"zp": out[:, 0] + 1j * out[:, 1], "zx": out[:, 2] + 1j * out[:, 3],
-            "hhp": out[:, 4], "hhx": out[:, 5], "rho": out[:, 6], "flags": fl, "tie": tie}
+            "hhp": out[:, 4], "hhx": out[:, 5], "rho": out[:, 6], "flags": fl, "tie": tie,
+            "mismatch": mm}
+
+
+# --------------------------------------------------------------------------- surrogate
+def mlp_param_count(hidden=128, layers=4):
+    return int(_load().orc_mlp_param_count(int(hidden), int(layers)))
+
+
+def set_surrogate(params, cfg, hidden=128, layers=4):
+    """Install surrogate parameters (FP64 values) and its configuration dict with keys
+    mc_lo, mc_hi, q_lo, q_hi, lt_lo, lt_hi, c_phi, c_amp, judge_tol, head."""
+    params = _f64(params)
+    assert params.size == mlp_param_count(hidden, layers)
+    c = _f64([cfg["mc_lo"], cfg["mc_hi"], cfg["q_lo"], cfg["q_hi"], cfg["lt_lo"], cfg["lt_hi"],
+              cfg["c_phi"], cfg["c_amp"], cfg.get("judge_tol", 1e-4), 1.0 if cfg.get("head") else 0.0])
+    if _load().orc_set_surrogate(int(hidden), int(layers), _ptr(params), _ptr(c)) != 0:
+        raise MemoryError("surrogate")
+
+
+def mlp_forward(params, u, hidden=128, layers=4):
+    """Outputs y [n, 2] and their derivatives along the third input dy [n, 2] (FP64)."""
+    params = _f64(params)
+    u = _f64(np.atleast_2d(u))
+    y = np.empty((u.shape[0], 2))
+    dy = np.empty((u.shape[0], 2))
+    _load().orc_mlp_forward_eval(_ptr(params), int(hidden), int(layers), u.shape[0], _ptr(u), _ptr(y), _ptr(dy))
+    return y, dy
+
+
+def surrogate_targets(mc, q, tau, head, c_phi, c_amp, tsun=T_SUN):
+    """Training targets from the 3.5PN and Newtonian waveforms (FP64)."""
+    mc, q, tau = _f64(mc), _f64(q), _f64(tau)
+    y = np.empty((mc.size, 2))
+    if _load().orc_surrogate_targets(mc.size, _ptr(mc), _ptr(q), _ptr(tau), float(tsun), int(bool(head)),
+                                     float(c_phi), float(c_amp), _ptr(y)) != 0:
+        raise ValueError("tau must be positive")
+    return y
 
 
 # --------------------------------------------------------------------------- brute force

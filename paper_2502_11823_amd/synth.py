@@ -187,3 +187,28 @@ def space(seed: int = 3, n_templates: int = 200_000, n_sft: int = 60, n_use_lo: 
             "a_first": a_first, "a_last": np.full(n_templates, n_sft - 1, np.int32)}
     return Workload("space", t_start, np.zeros(n_sft, np.int32), n, t_sft, k_lo, xb, psd, fplus, fcross,
                     bank, dict(K=32, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0))
+
+
+def mlp_init(seed: int, hidden: int = 128, layers: int = 4) -> np.ndarray:
+    """Seeded initial parameters of the surrogate network, packed layer by layer
+    (W [n_in][n_out] input-major, then b [n_out]): W ~ N(0, 1/n_in), b = 0, the output
+    layer scaled by 0.1.  FP32 values returned as float64."""
+    g = rng(seed)
+    dims = [3] + [hidden] * layers + [2]
+    parts = []
+    for i in range(len(dims) - 1):
+        W = g.standard_normal((dims[i], dims[i + 1])) / np.sqrt(dims[i])
+        if i == len(dims) - 2:
+            W *= 0.1
+        parts += [W.ravel(), np.zeros(dims[i + 1])]
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)
+
+
+def surrogate_samples(n: int, seed: int, mc_lo: float, mc_hi: float, q_lo: float, q_hi: float,
+                      tau_lo: float, tau_hi: float):
+    """Training inputs: Mc, q uniform, ln(tau) uniform."""
+    g = rng(seed)
+    mc = g.uniform(mc_lo, mc_hi, n)
+    q = g.uniform(q_lo, q_hi, n)
+    tau = np.exp(g.uniform(np.log(tau_lo), np.log(tau_hi), n))
+    return mc, q, tau

@@ -414,3 +414,66 @@ def test_p13_pn35_series_consistency(orc):
     assert np.max(np.abs((wp[:, 3] - wm[:, 3]) / (2 * h) / w0[:, 4] - 1)) < 1e-6
     wn = orc.waveform(mc, tc, 0, t, wf=orc.WF_NEWTON)
     assert np.all(np.abs(w0[:, 0] / wn[:, 0] - 1) < 0.05)
+
+
+# --------------------------------------------------------------------------- P14 (surrogate network)
+def test_p14_mlp_backprop_and_tangent_finite_differences(orc):
+    """P14: the FP64 training reference's gradients against central finite differences of
+    its loss; the C oracle's forward pass agrees with it and its forward-mode derivative
+    along the third input matches finite differences."""
+    from oracle import mlp
+    hidden, layers = 8, 3
+    p = synth.mlp_init(5, hidden, layers) + 0.05 * np.random.default_rng(1).standard_normal(
+        orc.mlp_param_count(hidden, layers))
+    g = np.random.default_rng(2)
+    U = g.uniform(-1, 1, (6, 3))
+    T = g.standard_normal((6, 2))
+    loss, grad = mlp.loss_and_grad(p, U, T, hidden, layers)
+    idx = g.choice(p.size, 40, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = h
+        fd = (mlp.loss_and_grad(p + e, U, T, hidden, layers)[0] - mlp.loss_and_grad(p - e, U, T, hidden, layers)[0]) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-7 * max(1.0, abs(grad[i])), (i, fd, grad[i])
+    Y, _ = mlp.forward(p, U, hidden, layers)
+    Yc, dYc = orc.mlp_forward(p, U, hidden, layers)
+    assert np.max(np.abs(Y - Yc)) < 1e-13
+    for k in range(U.shape[0]):
+        up, um = U[k].copy(), U[k].copy()
+        up[2] += 1e-6
+        um[2] -= 1e-6
+        fd = (orc.mlp_forward(p, up, hidden, layers)[0] - orc.mlp_forward(p, um, hidden, layers)[0]) / 2e-6
+        assert np.max(np.abs(fd - dYc[k])) < 1e-7
+
+
+def test_p14_surrogate_limits(orc):
+    """A zero network with the analytic head is the 3.5PN phase truncated after 1.5PN (phase
+    and frequency); without the head it is the Newtonian chirp; the training targets vanish
+    at the truncation they remove."""
+    n = orc.mlp_param_count(16, 2)
+    cfg = dict(mc_lo=1.1, mc_hi=1.3, q_lo=1.0, q_hi=2.0, lt_lo=np.log(100.0), lt_hi=np.log(2e4),
+               c_phi=1.0, c_amp=1.0, judge_tol=1e-4, head=True)
+    t = np.array([0.0, 3e3, 9e3])
+    try:
+        orc.set_surrogate(np.zeros(n), cfg, hidden=16, layers=2)
+        s = orc.waveform(1.2, 1e4, 0.3, t, q=1.6, wf=orc.WF_SURROGATE)
+        orc.set_pn_order(3)
+        p3 = orc.waveform(1.2, 1e4, 0.3, t, q=1.6, wf=orc.WF_PN35)
+        assert np.max(np.abs(s[:, 1] - p3[:, 1])) < 1e-9 * np.max(np.abs(p3[:, 1]))
+        # the surrogate's frequency is d(phase)/dt / 2 pi of that truncated phase
+        h = 0.05
+        dphi = (orc.waveform(1.2, 1e4, 0.3, t + h, q=1.6, wf=orc.WF_PN35)[:, 1]
+                - orc.waveform(1.2, 1e4, 0.3, t - h, q=1.6, wf=orc.WF_PN35)[:, 1]) / (2 * h)
+        assert np.max(np.abs(s[:, 2] / (dphi / (2 * np.pi)) - 1)) < 1e-8
+        cfg["head"] = False
+        orc.set_surrogate(np.zeros(n), cfg, hidden=16, layers=2)
+        s0 = orc.waveform(1.2, 1e4, 0.3, t, q=1.6, wf=orc.WF_SURROGATE)
+        nw = orc.waveform(1.2, 1e4, 0.3, t, wf=orc.WF_NEWTON)
+        assert np.max(np.abs(s0 - nw) / np.abs(nw)) < 1e-14
+        y = orc.surrogate_targets([1.2], [1.6], [5e3], head=True, c_phi=1.0, c_amp=1.0)
+        assert abs(y[0, 0]) < 1e-9
+    finally:
+        orc.set_pn_order(7)
+    y7 = orc.surrogate_targets([1.2], [1.6], [5e3], head=True, c_phi=1.0, c_amp=1.0)
+    assert abs(y7[0, 0]) > 1e-3
