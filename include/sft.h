@@ -52,9 +52,11 @@ enum { SFT_KERNEL_DIRICHLET = 0, SFT_KERNEL_FRESNEL = 1, SFT_KERNEL_AUTO = 2 };
 /* arithmetic of the bin contraction and of the sums over SFTs; the waveform
  * phase, its reduction mod 2 pi and the bin split are FP64 in every mode */
 enum { SFT_PREC_FP64 = 0, SFT_PREC_FP32_KAHAN = 1, SFT_PREC_FP32_NAIVE = 2 };
-/* waveform model: leading-order (Newtonian) chirp, or the 3.5PN closed-form inspiral
- * (needs F32 or F64 storage; reads the bank's mass ratio q >= 1, NULL => q = 1) */
-enum { SFT_WF_NEWTON = 0, SFT_WF_PN35 = 1 };
+/* waveform model: leading-order (Newtonian) chirp, the 3.5PN closed-form inspiral, or
+ * the learned surrogate (opts.surrogate) with the 3.5PN waveform as judge and fallback.
+ * PN35 and SURROGATE need F32 or F64 storage and read the bank's mass ratio q >= 1
+ * (NULL => q = 1). */
+enum { SFT_WF_NEWTON = 0, SFT_WF_PN35 = 1, SFT_WF_SURROGATE = 2 };
 
 /* per-template flag bits */
 enum {
@@ -62,6 +64,7 @@ enum {
   SFT_FLAG_TAU_NONPOSITIVE = 2u,  /* an SFT of the template's range starts its midpoint at or after t_c; skipped */
   SFT_FLAG_TAYLOR_INVALID = 4u,   /* fddot T^3 / 8 > delta_max in some SFT (Eq. max_tsft, midpoint lever arm) */
   SFT_FLAG_NONFINITE = 8u,        /* an output is not finite */
+  SFT_FLAG_SURROGATE_FALLBACK = 32u, /* surrogate judged worse than the tolerance: 3.5PN waveform used */
   SFT_FLAG_EMPTY = 64u            /* no SFT contributed to the norm; rho is set to 0 */
 };
 
@@ -114,10 +117,12 @@ typedef struct {
   double a_cross;       /* Ax of the projector, used for rho */
   double tsun;          /* G M_sun / c^3 [s]; M = Mc * tsun */
   double delta_max;     /* Taylor-validity threshold in bins (Eq. max_tsft); <= 0 disables the flag */
+  const struct sft_surrogate* surrogate;  /* network of SFT_WF_SURROGATE; NULL otherwise */
 } sft_opts;
 
 /* Fill *opts with K = 8, AUTO kernel, FP32_KAHAN, Newtonian waveform,
- * beta_switch = 1e-7, A+ = 1, Ax = 0, tsun = 4.925490947641267e-6 s, delta_max = 0. */
+ * beta_switch = 1e-7, A+ = 1, Ax = 0, tsun = 4.925490947641267e-6 s, delta_max = 0,
+ * surrogate = NULL. */
 void sft_default_opts(sft_opts* opts);
 
 /* Template bank, structure of arrays in DEVICE memory owned by the caller.
@@ -140,7 +145,9 @@ typedef struct {
 } sft_bank;
 
 /* Outputs, DEVICE memory owned by the caller: zp, zx are [n][2] (re, im);
- * hhp, hhx, rho are [n]; flags is [n]. */
+ * hhp, hhx, rho are [n]; flags is [n].  mismatch [n] may be NULL; with the surrogate
+ * waveform it receives each template's judge mismatch (see SFT_WF_SURROGATE below),
+ * other waveforms leave it untouched. */
 typedef struct {
   double* zp;
   double* zx;
@@ -148,6 +155,7 @@ typedef struct {
   double* hhx;
   double* rho;
   uint32_t* flags;
+  double* mismatch;
 } sft_out;
 
 /*
@@ -212,6 +220,105 @@ sft_status sft_plan_create(const sft_data* data, const sft_bank* bank, int64_t n
                            const sft_opts* opts, sft_out* out, sft_plan** plan);
 sft_status sft_plan_launch(sft_plan* plan, void* hip_stream);
 void sft_plan_destroy(sft_plan* plan);
+
+/*
+ * Learned surrogate waveform (an MLP correction to the leading-order chirp; the method
+ * evaluates any waveform model at the SFT midpoints, Sec. III.A, and the 3.5PN model
+ * serves to train it and to judge it).
+ *
+ * Network: u = (u_mc, u_q, u_tau) -> `layers` hidden layers of width `hidden` with SiLU
+ * -> (y1, y2), inputs mapped to [-1, 1]: u_mc = 2 (mc - mc_lo) / (mc_hi - mc_lo) - 1,
+ * u_q likewise, u_tau = 2 (ln tau - lt_lo) / (lt_hi - lt_lo) - 1.  Parameters are FP32,
+ * packed layer by layer: W [n_in][n_out] (input-major), then b [n_out].
+ * Waveform at tau = t_c - t, with M = mc tsun, Theta_N = tau / (5 M) and p = 1/8 when
+ * head = 1, 3/8 when head = 0:
+ *   phi  = phi_Newton + head * phi_head + c_phi Theta_N^p y1,
+ *   A    = A_Newton exp(c_amp y2),
+ *   f    = f_Newton - (d/dtau)(head * phi_head + c_phi Theta_N^p y1) / (2 pi)
+ *          (dy1/dtau by forward-mode differentiation through the network),
+ *   fdot = fdot_Newton (f / f_Newton)^(11/3),  fddot = (11/3) fdot^2 / f,
+ * phi_head = the 1PN and 1.5PN terms of the 3.5PN phase series.  Trained on targets
+ * y1 = (phi_3.5PN - phi_Newton - head * phi_head) / (c_phi Theta_N^p),
+ * y2 = ln(A_3.5PN / A_Newton) / c_amp.
+ * Judge: per template, over the SFT rows it uses, the match of the surrogate against
+ * the 3.5PN waveform in the SFT picture, mismatch = 1 - |sum_a w_a exp(i dphi_a)
+ * sinc(T df_a)| / sum_a w_a with w_a = A_3.5PN,a^2, dphi and df the surrogate minus
+ * 3.5PN phase and frequency at the SFT midpoint.  A template whose mismatch is not
+ * <= judge_tol is evaluated with the 3.5PN waveform and flagged
+ * SFT_FLAG_SURROGATE_FALLBACK.  The scan evaluates the network in FP64 (from the FP32
+ * parameters, or from their BF16 roundings when weights_bf16 = 1).
+ */
+typedef struct {
+  int32_t hidden;        /* hidden width, 8 .. 256 */
+  int32_t layers;        /* hidden layers, 1 .. 8 */
+  int32_t head;          /* 1: analytic 1PN + 1.5PN phase head; 0: the network carries it */
+  int32_t weights_bf16;  /* 1: inference with BF16-rounded parameters */
+  double mc_lo, mc_hi;   /* input ranges of the normalisation */
+  double q_lo, q_hi;
+  double lt_lo, lt_hi;   /* range of ln(tau / s) */
+  double c_phi;          /* phase scale [rad] */
+  double c_amp;          /* log-amplitude scale */
+  double judge_tol;      /* mismatch tolerance of the judge (e.g. 1e-4) */
+} sft_surrogate_desc;
+
+typedef struct sft_surrogate sft_surrogate;  /* opaque; owns its device buffers */
+
+/* Parameter count of a network (0 for hidden < 1 or layers < 1). */
+int64_t sft_surrogate_param_count(int32_t hidden, int32_t layers);
+
+/* Create a network on the current device from host FP32 parameters
+ * [sft_surrogate_param_count] (copied).  Errors: SFT_E_INVALID (null pointer, empty
+ * ranges, zero scales), SFT_E_RANGE (hidden, layers), SFT_E_NOMEM, SFT_E_DEVICE. */
+sft_status sft_surrogate_create(const sft_surrogate_desc* desc, const float* params, sft_surrogate** out);
+void sft_surrogate_free(sft_surrogate* s);
+/* Copy the current FP32 parameters to host memory (synchronous). */
+sft_status sft_surrogate_get_params(const sft_surrogate* s, float* params);
+
+/*
+ * sft_surrogate_targets -- training pairs from the library's own Newtonian and 3.5PN
+ * waveforms: device mc, q, tau [n] (FP64) -> device u [n][3] and y [n][2] (FP32, the
+ * network inputs and targets defined above).  Asynchronous on hip_stream.
+ * Errors: SFT_E_INVALID (null pointers, n < 0), SFT_E_DEVICE.
+ */
+sft_status sft_surrogate_targets(const sft_surrogate* s, const double* mc, const double* q, const double* tau,
+                                 int64_t n, double tsun, float* u, float* y, void* hip_stream);
+
+/*
+ * sft_surrogate_loss_grad -- loss L = (1/n) sum_i |net(u_i) - y_i|^2 of the FP32 network
+ * on device u [n][3], y [n][2], and its gradient: *loss (device, one float) and grad
+ * (device [P] floats, may be NULL; the network keeps it too).  Asynchronous on
+ * hip_stream.  Errors: SFT_E_INVALID, SFT_E_RANGE (n outside [1, 2^21]), SFT_E_NOMEM,
+ * SFT_E_DEVICE.
+ */
+sft_status sft_surrogate_loss_grad(sft_surrogate* s, const float* u, const float* y, int64_t n, float* loss,
+                                   float* grad, void* hip_stream);
+
+/*
+ * sft_surrogate_adam -- one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected)
+ * with learning rate lr on the gradient of the last sft_surrogate_loss_grad call.
+ * Asynchronous on hip_stream.  Errors: SFT_E_INVALID, SFT_E_DEVICE.
+ */
+sft_status sft_surrogate_adam(sft_surrogate* s, float lr, void* hip_stream);
+
+/*
+ * sft_surrogate_train -- epochs of mini-batch Adam over device u [n][3], y [n][2] in order
+ * (batches of `batch` consecutive rows, the last partial batch dropped; shuffle between
+ * calls if wanted), learning rate on a cosine schedule from lr to lr_min over the call.
+ * epoch_loss (host [epochs], may be NULL) receives the mean batch loss of each epoch.
+ * Synchronises hip_stream; refreshes the inference copy of the parameters.
+ * Errors: SFT_E_INVALID, SFT_E_RANGE (batch outside [16, min(n, 2^20)], epochs < 1),
+ * SFT_E_NOMEM, SFT_E_DEVICE.
+ */
+sft_status sft_surrogate_train(sft_surrogate* s, const float* u, const float* y, int64_t n, int32_t batch,
+                               int32_t epochs, float lr, float lr_min, void* hip_stream, float* epoch_loss);
+
+/*
+ * sft_surrogate_infer -- the scan's FP64 evaluation of the network: device u [n][3]
+ * (FP64) -> y [n][2] and dy [n][2] = dy/du_tau.  Asynchronous on hip_stream.
+ * Errors: SFT_E_INVALID, SFT_E_NOMEM, SFT_E_DEVICE.
+ */
+sft_status sft_surrogate_infer(const sft_surrogate* s, const double* u, int64_t n, double* y, double* dy,
+                               void* hip_stream);
 
 /*
  * sft_inner_product -- one template, host arguments and host results; runs the

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsft.so")
-SOURCES = [os.path.join(CSRC, "sft_lib.hip")]
+SOURCES = [os.path.join(CSRC, "sft_lib.hip"), os.path.join(CSRC, "sft_mlp.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled on purpose (-packed-fp32-ops).

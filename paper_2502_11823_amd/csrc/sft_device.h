@@ -42,6 +42,7 @@ enum : uint32_t {
   kFlagTau = 2u,
   kFlagTaylor = 4u,
   kFlagNonfinite = 8u,
+  kFlagSurrogateFallback = 32u,
   kFlagEmpty = 64u
 };
 

@@ -28,6 +28,7 @@
 
 #include "../../include/sft.h"
 #include "sft_device.h"
+#include "sft_mlp.h"
 
 using namespace sftk;
 
@@ -53,6 +54,12 @@ static sft_status fail(sft_status st, const char* fmt, ...)
       return fail(e_ == hipErrorOutOfMemory ? SFT_E_NOMEM : SFT_E_DEVICE, "%s: %s (%s:%d)", \
                   #call, hipGetErrorString(e_), __FILE__, __LINE__);                      \
   } while (0)
+
+sft_status sft_set_error(sft_status st, const char* msg)
+{
+  g_err = msg;
+  return st;
+}
 
 extern "C" const char* sft_last_error(void) { return g_err.c_str(); }
 extern "C" const char* sft_version(void) { return "libsft 0.1.0 gfx950"; }
@@ -338,6 +345,7 @@ extern "C" void sft_default_opts(sft_opts* o)
   o->a_cross = 0.0;
   o->tsun = 4.925490947641267e-6;
   o->delta_max = 0.0;
+  o->surrogate = nullptr;
 }
 
 // ============================================================================ scan
@@ -364,10 +372,13 @@ struct ScanArgs {
   int32_t* counter;         // work-queue head (zeroed before the launch)
   double* part;      // [n_chunks][6][n_tmpl]
   uint32_t* pflags;  // [n_chunks][n_tmpl]
+  const double* wtab;  // chirp table (WF_TABLE): 5 planes [n_groups][n_tmpl] kappa, phase, amp, beta, dres
 };
 
 enum { KERN_DIRICHLET = 0, KERN_FRESNEL = 1 };
-enum { WF_NEWTON = SFT_WF_NEWTON, WF_PN35 = SFT_WF_PN35 };
+// WF_TABLE: the chirp of every (template, group) comes precomputed from a table (the
+// surrogate path fills it); an internal value, never accepted from the caller
+enum { WF_NEWTON = SFT_WF_NEWTON, WF_PN35 = SFT_WF_PN35, WF_TABLE = 100 };
 
 // unroll factor of the bin loops (4 keeps the Fresnel kernel at 5 waves per SIMD)
 #ifndef SFT_BIN_UNROLL
@@ -457,9 +468,12 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
   const int hi = a.a_last ? (int)a.a_last[m] : 0x7fffffff;
 
   const double T = a.T;
-  const double M = a.mc[m] * a.tsun;
-  const double inv5M = 1.0 / (5.0 * M);
-  const double cf = T / (8.0 * kPi * M);
+  double inv5M = 0.0, cf = 0.0;
+  if constexpr (WF == WF_NEWTON) {
+    const double M = a.mc[m] * a.tsun;
+    inv5M = 1.0 / (5.0 * M);
+    cf = T / (8.0 * kPi * M);
+  }
   const double tc = a.t_c[m];
   const double phic = a.phi_c ? a.phi_c[m] : 0.0;
   // 3.5PN: symmetric mass ratio, total mass, nu/(5M), nu^(2/5) and the series coefficients
@@ -497,8 +511,19 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       continue;
     }
     Chirp ch;
-    if constexpr (WF == WF_PN35) ch = pn35_chirp(tau, nu, inv5Mnu, Mt, nu25, phic, T, pcf);
-    else ch = newton_chirp(tau, inv5M, cf, phic, T);
+    if constexpr (WF == WF_PN35) {
+      ch = pn35_chirp(tau, nu, inv5Mnu, Mt, nu25, phic, T, pcf);
+    } else if constexpr (WF == WF_TABLE) {
+      const int64_t ps = (int64_t)a.n_groups * a.n_tmpl;
+      const double* w = a.wtab + (int64_t)g * a.n_tmpl + m;
+      ch.kappa = w[0];
+      ch.phase = w[ps];
+      ch.amp = w[2 * ps];
+      ch.beta = w[3 * ps];
+      ch.dres = w[4 * ps];
+    } else {
+      ch = newton_chirp(tau, inv5M, cf, phic, T);
+    }
     if (a.delta_max > 0.0 && ch.dres > a.delta_max) fl |= kFlagTaylor;
     if (!(ch.kappa < 1.0e9)) {
       // frequency far above any stored band: no window bin and no norm bin exists
@@ -705,7 +730,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
                                                        int64_t n, int32_t n_chunks, double a_plus, double a_cross,
                                                        double* __restrict__ zp, double* __restrict__ zx,
                                                        double* __restrict__ hhp, double* __restrict__ hhx,
-                                                       double* __restrict__ rho, uint32_t* __restrict__ flags)
+                                                       double* __restrict__ rho, uint32_t* __restrict__ flags,
+                                                       const uint32_t* __restrict__ xflags)
 {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
@@ -730,6 +756,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   bool fin = isfinite(r);
   for (int q = 0; q < 6; ++q) fin = fin && isfinite(v[q]);
   if (!fin) fl |= kFlagNonfinite;
+  if (xflags) fl |= xflags[m];
   zp[2 * m] = v[0];
   zp[2 * m + 1] = v[1];
   zx[2 * m] = v[2];
@@ -773,20 +800,30 @@ static ScanFn pick_kern(int kern, int K, int nd)
   return kern == KERN_DIRICHLET ? pick_k<Bin, PREC, KERN_DIRICHLET, WF>(K, nd) : pick_k<Bin, PREC, KERN_FRESNEL, WF>(K, nd);
 }
 
-static ScanFn pick_kernel(const sft_data* d, const sft_opts* o)
+template <typename Bin, int PREC>
+static ScanFn pick_wf(int wf, int kern, int K, int nd)
+{
+  switch (wf) {
+  case WF_PN35: return pick_kern<Bin, PREC, WF_PN35>(kern, K, nd);
+  case WF_TABLE: return pick_kern<Bin, PREC, WF_TABLE>(kern, K, nd);
+  default: return pick_kern<Bin, PREC, WF_NEWTON>(kern, K, nd);
+  }
+}
+
+// wf: WF_NEWTON, WF_PN35 or WF_TABLE (the surrogate path)
+static ScanFn pick_kernel(const sft_data* d, const sft_opts* o, int wf)
 {
   const int kern = o->kernel == SFT_KERNEL_DIRICHLET ? KERN_DIRICHLET : KERN_FRESNEL;
-  const bool pn = o->waveform == SFT_WF_PN35;
-  if (o->precision == SFT_PREC_FP64)
-    return pn ? pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_PN35>(o->K, d->nd)
-              : pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_NEWTON>(o->K, d->nd);
-  if (d->storage == SFT_STORE_F32) {
-    if (pn)
-      return o->precision == SFT_PREC_FP32_KAHAN ? pick_kern<float2, SFT_PREC_FP32_KAHAN, WF_PN35>(kern, o->K, d->nd)
-                                                 : pick_kern<float2, SFT_PREC_FP32_NAIVE, WF_PN35>(kern, o->K, d->nd);
-    return o->precision == SFT_PREC_FP32_KAHAN ? pick_kern<float2, SFT_PREC_FP32_KAHAN, WF_NEWTON>(kern, o->K, d->nd)
-                                               : pick_kern<float2, SFT_PREC_FP32_NAIVE, WF_NEWTON>(kern, o->K, d->nd);
+  if (o->precision == SFT_PREC_FP64) {
+    switch (wf) {
+    case WF_PN35: return pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_PN35>(o->K, d->nd);
+    case WF_TABLE: return pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_TABLE>(o->K, d->nd);
+    default: return pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_NEWTON>(o->K, d->nd);
+    }
   }
+  if (d->storage == SFT_STORE_F32)
+    return o->precision == SFT_PREC_FP32_KAHAN ? pick_wf<float2, SFT_PREC_FP32_KAHAN>(wf, kern, o->K, d->nd)
+                                               : pick_wf<float2, SFT_PREC_FP32_NAIVE>(wf, kern, o->K, d->nd);
   return o->precision == SFT_PREC_FP32_KAHAN ? pick_kern<bf16x2, SFT_PREC_FP32_KAHAN, WF_NEWTON>(kern, o->K, d->nd)
                                              : pick_kern<bf16x2, SFT_PREC_FP32_NAIVE, WF_NEWTON>(kern, o->K, d->nd);
 }
@@ -802,10 +839,17 @@ static sft_status validate_scan(const sft_data* d, const sft_opts* o)
   if (o->K < 0 || o->K > SFT_K_MAX) return fail(SFT_E_RANGE, "scan: K=%d outside [0, %d]", o->K, SFT_K_MAX);
   if (o->kernel != SFT_KERNEL_DIRICHLET && o->kernel != SFT_KERNEL_FRESNEL && o->kernel != SFT_KERNEL_AUTO)
     return fail(SFT_E_INVALID, "scan: unknown kernel %d", o->kernel);
-  if (o->waveform != SFT_WF_NEWTON && o->waveform != SFT_WF_PN35)
+  if (o->waveform != SFT_WF_NEWTON && o->waveform != SFT_WF_PN35 && o->waveform != SFT_WF_SURROGATE)
     return fail(SFT_E_INVALID, "scan: unknown waveform %d", o->waveform);
-  if (o->waveform == SFT_WF_PN35 && d->storage == SFT_STORE_BF16)
-    return fail(SFT_E_UNSUPPORTED, "scan: the 3.5PN waveform needs F32 or F64 storage");
+  if (o->waveform == SFT_WF_SURROGATE && !o->surrogate)
+    return fail(SFT_E_INVALID, "scan: the surrogate waveform needs opts.surrogate");
+  if (o->waveform != SFT_WF_NEWTON && d->storage == SFT_STORE_BF16)
+    return fail(SFT_E_UNSUPPORTED, "scan: the 3.5PN and surrogate waveforms need F32 or F64 storage");
+  if (o->waveform == SFT_WF_SURROGATE) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != o->surrogate->device)
+      return fail(SFT_E_INVALID, "scan: the surrogate lives on device %d, not on the current device", o->surrogate->device);
+  }
   if (!(o->tsun > 0.0)) return fail(SFT_E_INVALID, "scan: tsun must be positive");
   if (o->precision == SFT_PREC_FP64) {
     if (d->storage != SFT_STORE_F64) return fail(SFT_E_UNSUPPORTED, "scan: FP64 precision needs F64 storage");
@@ -844,6 +888,7 @@ static sft_status validate_tuning(const sft_tuning* t)
 struct Prepared {
   ScanArgs a;
   ScanFn fn;
+  const uint32_t* xflags;  // extra per-template flags ORed in by the finalize kernel (or null)
   dim3 grid, block;
   size_t part_bytes, flag_bytes, counter_off, ws_bytes;
   int64_t n;
@@ -851,7 +896,8 @@ struct Prepared {
 };
 
 static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o,
-                               const sft_tuning& t, Prepared& P)
+                               const sft_tuning& t, Prepared& P, int wf = -1, const double* wtab = nullptr,
+                               const uint32_t* xflags = nullptr)
 {
   ScanArgs& a = P.a;
   std::memset(&a, 0, sizeof(a));
@@ -879,7 +925,9 @@ static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t 
   a.a_first = bank->a_first;
   a.a_last = bank->a_last;
   a.n_tmpl = n;
-  P.fn = pick_kernel(d, o);
+  a.wtab = wtab;
+  P.xflags = xflags;
+  P.fn = pick_kernel(d, o, wf >= 0 ? wf : o->waveform);
   const int B = t.block ? t.block : 256;
   a.n_tiles = (int32_t)((n + B - 1) / B);
   int nb_cu = 0;
@@ -938,8 +986,305 @@ static hipError_t enqueue_scan(Prepared& P, void* ws, sft_out* out, hipStream_t 
   if (ev_e) (void)hipEventRecord(ev_e, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, a.part, a.pflags, P.n,
-                     a.n_chunks, P.a_plus, P.a_cross, out->zp, out->zx, out->hhp, out->hhx, out->rho, out->flags);
+                     a.n_chunks, P.a_plus, P.a_cross, out->zp, out->zx, out->hhp, out->hhx, out->rho, out->flags,
+                     P.xflags);
   return hipGetLastError();
+}
+
+// ============================================================================ surrogate
+// Parameters of the surrogate waveform shared by its kernels.
+struct SurArgs {
+  double mc_lo, mc_span, q_lo, q_span, lt_lo, lt_span;  // input normalisation
+  double c_phi, c_amp, p, judge_tol, tsun;
+  int32_t head;
+};
+
+static SurArgs sur_args(const sft_surrogate* s, double tsun)
+{
+  SurArgs a;
+  a.mc_lo = s->d.mc_lo;
+  a.mc_span = s->d.mc_hi - s->d.mc_lo;
+  a.q_lo = s->d.q_lo;
+  a.q_span = s->d.q_hi - s->d.q_lo;
+  a.lt_lo = s->d.lt_lo;
+  a.lt_span = s->d.lt_hi - s->d.lt_lo;
+  a.c_phi = s->d.c_phi;
+  a.c_amp = s->d.c_amp;
+  a.p = s->d.head ? 0.125 : 0.375;
+  a.judge_tol = s->d.judge_tol;
+  a.tsun = tsun;
+  a.head = s->d.head;
+  return a;
+}
+
+// network inputs in [-1, 1]
+__device__ inline void sur_inputs(const SurArgs& a, double mc, double q, double tau, double* u)
+{
+  u[0] = 2.0 * (mc - a.mc_lo) / a.mc_span - 1.0;
+  u[1] = 2.0 * (q - a.q_lo) / a.q_span - 1.0;
+  u[2] = 2.0 * (log(tau) - a.lt_lo) / a.lt_span - 1.0;
+}
+
+// mass parameters of the 3.5PN model: nu, total mass [s], nu / (5 M), nu^(2/5)
+struct PNMass {
+  double nu, Mt, inv5Mnu, nu25;
+};
+__device__ inline PNMass pn_mass(double mc, double q, double tsun)
+{
+  double qq = q;
+  if (!(qq >= 1.0)) qq = 1.0 / qq;
+  PNMass r;
+  r.nu = qq / ((1.0 + qq) * (1.0 + qq));
+  r.Mt = mc * pow(r.nu, -0.6) * tsun;
+  r.inv5Mnu = r.nu / (5.0 * r.Mt);
+  r.nu25 = pow(r.nu, 0.4);
+  return r;
+}
+
+// 1PN + 1.5PN part of the 3.5PN phase, -(2/nu) Theta^(5/8) (p2 Theta^(-1/4) + p3 Theta^(-3/8)),
+// and its tau-derivative
+__device__ inline void pn_head(const PNMass& pm, const PNCoef& c, double tau, double& ph, double& dph)
+{
+  const double th = tau * pm.inv5Mnu;
+  const double t38 = pow(th, 0.375), t14 = pow(th, 0.25);
+  ph = -2.0 / pm.nu * (c.p2 * t38 + c.p3 * t14);
+  dph = -2.0 / pm.nu * (0.375 * c.p2 * t38 + 0.25 * c.p3 * t14) / th * pm.inv5Mnu;
+}
+
+// training pairs: u [n][3], y [n][2] (FP32) from FP64 Newtonian and 3.5PN waveforms
+__global__ __launch_bounds__(256) void sur_targets_kernel(SurArgs sa, const double* __restrict__ mc,
+                                                          const double* __restrict__ q, const double* __restrict__ tau,
+                                                          int64_t n, float* __restrict__ u, float* __restrict__ y)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double m = mc[i], qq = q[i], t = tau[i];
+  const double M = m * sa.tsun;
+  const double inv5M = 1.0 / (5.0 * M);
+  const Chirp cn = newton_chirp(t, inv5M, 1.0 / (8.0 * kPi * M), 0.0, 1.0);
+  const PNMass pm = pn_mass(m, qq, sa.tsun);
+  const PNCoef pc = pn_coefficients(pm.nu);
+  const Chirp cp = pn35_chirp(t, pm.nu, pm.inv5Mnu, pm.Mt, pm.nu25, 0.0, 1.0, pc);
+  double d = cp.phase - cn.phase;
+  if (sa.head) {
+    double hp, hd;
+    pn_head(pm, pc, t, hp, hd);
+    d -= hp;
+  }
+  const double Phi = pow(t * inv5M, sa.p);
+  double uu[3];
+  sur_inputs(sa, m, qq, t, uu);
+  u[3 * i] = (float)uu[0];
+  u[3 * i + 1] = (float)uu[1];
+  u[3 * i + 2] = (float)uu[2];
+  y[2 * i] = (float)(d / (sa.c_phi * Phi));
+  y[2 * i + 1] = (float)(log(cp.amp / cn.amp) / sa.c_amp);
+}
+
+// network inputs of a template batch, row r = g * nb + m (group-major)
+__global__ __launch_bounds__(256) void sur_inputs_kernel(SurArgs sa, const double* __restrict__ mc,
+                                                         const double* __restrict__ q, const double* __restrict__ t_c,
+                                                         const double* __restrict__ g_tmid, int64_t nb, int32_t n_groups,
+                                                         double* __restrict__ U)
+{
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb * n_groups) return;
+  const int64_t m = r % nb;
+  const int g = (int)(r / nb);
+  const double tau = t_c[m] - g_tmid[g];
+  double u[3];
+  sur_inputs(sa, mc[m], q ? q[m] : 1.0, tau > 0.0 ? tau : 1.0, u);
+  U[3 * r] = u[0];
+  U[3 * r + 1] = u[1];
+  U[3 * r + 2] = u[2];
+}
+
+// One lane per template of the batch: the surrogate chirp of every group the template
+// uses (Newtonian chirp plus the network's corrections), the judge against the 3.5PN
+// chirp, and the chirp table the scan reads (the 3.5PN chirps for a rejected template).
+__global__ __launch_bounds__(256) void sur_post_kernel(SurArgs sa, const double* __restrict__ mc,
+                                                       const double* __restrict__ q, const double* __restrict__ t_c,
+                                                       const double* __restrict__ phi_c, const int32_t* __restrict__ a_first,
+                                                       const int32_t* __restrict__ a_last,
+                                                       const double* __restrict__ g_tmid, const int32_t* __restrict__ g_rows,
+                                                       int64_t nb, int32_t n_groups, double T,
+                                                       const double* __restrict__ Y, const double* __restrict__ dY,
+                                                       double* __restrict__ tab, uint32_t* __restrict__ xflags,
+                                                       double* __restrict__ mismatch)
+{
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nb) return;
+  const int lo = a_first ? (int)a_first[m] : 0;
+  const int hi = a_last ? (int)a_last[m] : 0x7fffffff;
+  const double tc = t_c[m], phic = phi_c ? phi_c[m] : 0.0;
+  const double M = mc[m] * sa.tsun;
+  const double inv5M = 1.0 / (5.0 * M);
+  const double cf = T / (8.0 * kPi * M);
+  const PNMass pm = pn_mass(mc[m], q ? q[m] : 1.0, sa.tsun);
+  const PNCoef pc = pn_coefficients(pm.nu);
+  const double dlt = 2.0 / sa.lt_span;   // du_tau / d ln tau
+  const int64_t ps = (int64_t)n_groups * nb;
+  double sr = 0.0, si = 0.0, sw = 0.0;
+  for (int g = 0; g < n_groups; ++g) {
+    int n_act = 0;
+    for (int d = 0; d < SFT_GROUP_MAX; ++d) {
+      const int r = g_rows[g * SFT_GROUP_MAX + d];
+      n_act += (r >= 0 && r >= lo && r <= hi) ? 1 : 0;
+    }
+    const double tau = tc - g_tmid[g];
+    if (n_act == 0 || !(tau > 0.0)) continue;
+    const int64_t r = (int64_t)g * nb + m;
+    const double y1 = Y[2 * r], y2 = Y[2 * r + 1], dy1 = dY[2 * r];
+    const Chirp cn = newton_chirp(tau, inv5M, cf, phic, T);
+    const double Phi = pow(tau * inv5M, sa.p);
+    double dphi = sa.c_phi * Phi * y1;
+    double ddphi = sa.c_phi * Phi * (sa.p * y1 + dy1 * dlt) / tau;   // d(dphi)/dtau
+    if (sa.head) {
+      double hp, hd;
+      pn_head(pm, pc, tau, hp, hd);
+      dphi += hp;
+      ddphi += hd;
+    }
+    Chirp cs;
+    cs.kappa = cn.kappa - ddphi * T / (2.0 * kPi);   // dphi/dt = -dphi/dtau
+    cs.phase = cn.phase + dphi;
+    cs.amp = cn.amp * exp(sa.c_amp * y2);
+    cs.beta = cn.beta * pow(cs.kappa / cn.kappa, 11.0 / 3.0);
+    cs.dres = (11.0 / 24.0) * cs.beta * cs.beta / cs.kappa;
+    double* w = tab + r;
+    w[0] = cs.kappa;
+    w[ps] = cs.phase;
+    w[2 * ps] = cs.amp;
+    w[3 * ps] = cs.beta;
+    w[4 * ps] = cs.dres;
+    // judge term: A_PN^2 exp(i dphi) sinc(dkappa) per SFT row
+    const Chirp cp = pn35_chirp(tau, pm.nu, pm.inv5Mnu, pm.Mt, pm.nu25, phic, T, pc);
+    const double dk = cs.kappa - cp.kappa;
+    const double snc = fabs(dk) < 1e-8 ? 1.0 - kPi * kPi * dk * dk / 6.0 : sin(kPi * dk) / (kPi * dk);
+    const double wt = cp.amp * cp.amp * (double)n_act;
+    double sd, cd;
+    sincos(cs.phase - cp.phase, &sd, &cd);
+    sr += wt * cd * snc;
+    si += wt * sd * snc;
+    sw += wt;
+  }
+  const double mm = sw > 0.0 ? 1.0 - sqrt(sr * sr + si * si) / sw : 0.0;
+  if (mismatch) mismatch[m] = mm;
+  const bool fallback = !(mm <= sa.judge_tol);
+  xflags[m] = fallback ? kFlagSurrogateFallback : 0u;
+  if (!fallback) return;
+  for (int g = 0; g < n_groups; ++g) {
+    int n_act = 0;
+    for (int d = 0; d < SFT_GROUP_MAX; ++d) {
+      const int r = g_rows[g * SFT_GROUP_MAX + d];
+      n_act += (r >= 0 && r >= lo && r <= hi) ? 1 : 0;
+    }
+    const double tau = tc - g_tmid[g];
+    if (n_act == 0 || !(tau > 0.0)) continue;
+    const Chirp cp = pn35_chirp(tau, pm.nu, pm.inv5Mnu, pm.Mt, pm.nu25, phic, T, pc);
+    double* w = tab + (int64_t)g * nb + m;
+    w[0] = cp.kappa;
+    w[ps] = cp.phase;
+    w[2 * ps] = cp.amp;
+    w[3 * ps] = cp.beta;
+    w[4 * ps] = cp.dres;
+  }
+}
+
+extern "C" sft_status sft_surrogate_targets(const sft_surrogate* s, const double* mc, const double* q,
+                                            const double* tau, int64_t n, double tsun, float* u, float* y,
+                                            void* hip_stream)
+{
+  if (!s || !mc || !q || !tau || !u || !y) return fail(SFT_E_INVALID, "sft_surrogate_targets: null argument");
+  if (n < 0) return fail(SFT_E_INVALID, "sft_surrogate_targets: negative n");
+  if (!(tsun > 0.0)) return fail(SFT_E_INVALID, "sft_surrogate_targets: tsun must be positive");
+  if (n == 0) return SFT_OK;
+  hipLaunchKernelGGL(sur_targets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream,
+                     sur_args(s, tsun), mc, q, tau, n, u, y);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SFT_OK : fail(SFT_E_DEVICE, "sft_surrogate_targets: %s", hipGetErrorString(e));
+}
+
+// Templates per surrogate batch: about 2^23 network evaluations (one per template and
+// timestamp group), which bounds the batch workspace near 1 GiB.
+static int64_t sur_batch(int64_t n, int32_t n_groups)
+{
+  int64_t b = ((int64_t)1 << 23) / std::max(1, n_groups);
+  b = std::max<int64_t>(256, b / 256 * 256);
+  return std::min(b, n);
+}
+
+// Scan with the surrogate waveform, batch by batch: network inputs, FP64 network
+// evaluation (values and d/du_tau), surrogate chirps + judge -> chirp table, then the
+// table-driven scan of the batch.
+static sft_status surrogate_scan(const sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o, sft_out* out,
+                                 hipStream_t st)
+{
+  const sft_surrogate* sur = o->surrogate;
+  const SurArgs sa = sur_args(sur, o->tsun);
+  const int64_t B = sur_batch(n, d->n_groups);
+  const int64_t R = B * d->n_groups;
+  const int64_t chunk = std::min<int64_t>(R, 1 << 16);
+  // workspace: U [R][3], Y, dY [R][2], table [5][R], xflags [B], network scratch, scan workspace
+  Prepared P0;
+  sft_status s = prepare_scan(d, bank, B, o, d->tune, P0, WF_TABLE, nullptr, nullptr);
+  if (s != SFT_OK) return s;
+  const size_t off_y = (size_t)R * 3 * sizeof(double);
+  const size_t off_dy = off_y + (size_t)R * 2 * sizeof(double);
+  const size_t off_tab = off_dy + (size_t)R * 2 * sizeof(double);
+  const size_t off_xf = off_tab + (size_t)R * 5 * sizeof(double);
+  const size_t off_nn = (off_xf + (size_t)B * sizeof(uint32_t) + 255) / 256 * 256;
+  const size_t off_scan = (off_nn + mlp_infer_scratch_bytes(sur->d.hidden, chunk) + 255) / 256 * 256;
+  size_t scan_ws = P0.ws_bytes;
+  for (int64_t m0 = 0; m0 < n; m0 += B) {   // the last batch may have a different shape
+    const int64_t nb = std::min(B, n - m0);
+    Prepared Pt;
+    if ((s = prepare_scan(d, bank, nb, o, d->tune, Pt, WF_TABLE, nullptr, nullptr)) != SFT_OK) return s;
+    scan_ws = std::max(scan_ws, Pt.ws_bytes);
+  }
+  char* ws = nullptr;
+  HIP_OR_FAIL(hipMallocAsync((void**)&ws, off_scan + scan_ws, st));
+  double* U = (double*)ws;
+  double* Y = (double*)(ws + off_y);
+  double* dY = (double*)(ws + off_dy);
+  double* tab = (double*)(ws + off_tab);
+  uint32_t* xf = (uint32_t*)(ws + off_xf);
+  hipError_t e = hipSuccess;
+  for (int64_t m0 = 0; m0 < n && e == hipSuccess && s == SFT_OK; m0 += B) {
+    const int64_t nb = std::min(B, n - m0);
+    const int64_t rows = nb * d->n_groups;
+    sft_bank b = *bank;
+    b.mc += m0;
+    b.t_c += m0;
+    if (b.q) b.q += m0;
+    if (b.phi_c) b.phi_c += m0;
+    if (b.a_first) b.a_first += m0;
+    if (b.a_last) b.a_last += m0;
+    sft_out ob = *out;
+    ob.zp += 2 * m0;
+    ob.zx += 2 * m0;
+    ob.hhp += m0;
+    ob.hhx += m0;
+    ob.rho += m0;
+    ob.flags += m0;
+    if (ob.mismatch) ob.mismatch += m0;
+    hipLaunchKernelGGL(sur_inputs_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, sa, b.mc, b.q, b.t_c,
+                       d->g_tmid, nb, d->n_groups, U);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    if ((e = mlp_infer(sur, U, rows, Y, dY, ws + off_nn, chunk, st)) != hipSuccess) break;
+    hipLaunchKernelGGL(sur_post_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, sa, b.mc, b.q, b.t_c,
+                       b.phi_c, b.a_first, b.a_last, d->g_tmid, d->g_rows, nb, d->n_groups, d->T, Y, dY, tab, xf,
+                       ob.mismatch);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    Prepared P;
+    if ((s = prepare_scan(d, &b, nb, o, d->tune, P, WF_TABLE, tab, xf)) != SFT_OK) break;
+    e = enqueue_scan(P, ws + off_scan, &ob, st, m0 == 0);
+  }
+  hipError_t e2 = hipFreeAsync(ws, st);
+  if (s != SFT_OK) return s;
+  if (e != hipSuccess) return fail(SFT_E_DEVICE, "scan (surrogate): %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(SFT_E_DEVICE, "scan (surrogate): hipFreeAsync: %s", hipGetErrorString(e2));
+  return SFT_OK;
 }
 
 extern "C" sft_status sft_template_bank_scan(const sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o,
@@ -949,6 +1294,7 @@ extern "C" sft_status sft_template_bank_scan(const sft_data* d, const sft_bank* 
   if (s != SFT_OK) return s;
   if ((s = validate_io(bank, n, out)) != SFT_OK || n == 0) return s;
   hipStream_t st = (hipStream_t)hip_stream;
+  if (o->waveform == SFT_WF_SURROGATE) return surrogate_scan(d, bank, n, o, out, st);
   Prepared P;
   if ((s = prepare_scan(d, bank, n, o, d->tune, P)) != SFT_OK) return s;
   void* ws = nullptr;
@@ -985,6 +1331,8 @@ extern "C" sft_status sft_autotune(sft_data* d, const sft_bank* bank, int64_t n,
   if (s != SFT_OK) return s;
   if ((s = validate_io(bank, n, out)) != SFT_OK) return s;
   if (n == 0) return fail(SFT_E_INVALID, "sft_autotune: needs at least one template");
+  if (o->waveform == SFT_WF_SURROGATE)
+    return fail(SFT_E_UNSUPPORTED, "sft_autotune: tune with the Newtonian or 3.5PN waveform");
   if (reps < 1 || reps > 100) return fail(SFT_E_RANGE, "sft_autotune: reps must be in [1, 100]");
   hipStream_t st = (hipStream_t)hip_stream;
   std::vector<sft_tuning> cand;
@@ -1068,6 +1416,8 @@ extern "C" sft_status sft_plan_create(const sft_data* d, const sft_bank* bank, i
   if (s != SFT_OK) return s;
   if ((s = validate_io(bank, n, out)) != SFT_OK) return s;
   if (n == 0) return fail(SFT_E_INVALID, "sft_plan_create: needs at least one template");
+  if (o->waveform == SFT_WF_SURROGATE)
+    return fail(SFT_E_UNSUPPORTED, "sft_plan_create: the surrogate waveform is not captured into graphs");
   sft_plan* p = new sft_plan();
   p->ws = nullptr;
   p->graph = nullptr;

@@ -1,0 +1,576 @@
+// sft_mlp.hip -- the learned surrogate's network on gfx950: training (FP32 forward,
+// backward, Adam) and inference (FP64 forward with the forward-mode derivative along
+// the ln(tau) input), built from one tiled GEMM kernel and small element-wise kernels.
+//
+// GEMM: C[M][N] = op(A)[M][K] op(B)[K][N] for a 64 x 64 tile per 256-thread workgroup,
+// 4 x 4 outputs per thread, K staged through LDS in steps of 16 (vector FMA: FP64 has
+// the same dense peak on the vector units as on the matrix cores of gfx950, and the
+// FP32 training GEMMs are a small, off-scan cost); a grid z-dimension
+// splits K into slices written to separate C planes (summed by a reduction kernel),
+// which gives the weight gradients (K = batch) enough workgroups.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "sft_mlp.h"
+
+// ---------------------------------------------------------------------------- geometry
+MlpLayer mlp_layer(int hidden, int layers, int l)
+{
+  MlpLayer L;
+  int64_t off = 0;
+  for (int i = 0; i <= l; ++i) {
+    const int n_in = i == 0 ? 3 : hidden;
+    const int n_out = i == layers ? 2 : hidden;
+    if (i == l) {
+      L.n_in = n_in;
+      L.n_out = n_out;
+      L.w_off = off;
+      L.b_off = off + (int64_t)n_in * n_out;
+    }
+    off += (int64_t)n_in * n_out + n_out;
+  }
+  return L;
+}
+
+int64_t mlp_param_count(int hidden, int layers)
+{
+  const MlpLayer L = mlp_layer(hidden, layers, layers);
+  return L.b_off + L.n_out;
+}
+
+// ---------------------------------------------------------------------------- GEMM
+template <typename T, bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const T* __restrict__ A, int lda,
+                                                   const T* __restrict__ B, int ldb, T* __restrict__ C, int ldc,
+                                                   int k_slice, int64_t c_plane)
+{
+  __shared__ T As[16][64 + 1];
+  __shared__ T Bs[16][64 + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int kb = blockIdx.z * k_slice;
+  const int ke = min(K, kb + k_slice);
+  T acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = (T)0;
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      int ii, kk;
+      if (TA) { ii = e & 63; kk = e >> 6; } else { ii = e >> 4; kk = e & 15; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      T v = (T)0;
+      if (gi < M && gk < ke) v = TA ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk];
+      As[kk][ii] = v;
+    }
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      int jj, kk;
+      if (TB) { jj = e >> 4; kk = e & 15; } else { jj = e & 63; kk = e >> 6; }
+      const int gj = j0 + jj, gk = k0 + kk;
+      T v = (T)0;
+      if (gj < N && gk < ke) v = TB ? B[(int64_t)gj * ldb + gk] : B[(int64_t)gk * ldb + gj];
+      Bs[kk][jj] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = As[kk][ty + 16 * r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    }
+    __syncthreads();
+  }
+  // thread (tx, ty) owns rows ty + 16 r and columns tx + 16 c of the tile, so that a
+  // wavefront's LDS reads and global stores touch consecutive addresses
+  T* Cp = C + (int64_t)blockIdx.z * c_plane;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int gi = i0 + ty + 16 * r;
+    if (gi >= M) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int gj = j0 + tx + 16 * c;
+      if (gj < N) Cp[(int64_t)gi * ldc + gj] = acc[r][c];
+    }
+  }
+}
+
+// C = op(A) op(B) with k split into `splits` planes of C (plane stride c_plane)
+template <typename T>
+static hipError_t gemm(bool ta, bool tb, int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
+                       int splits, int64_t c_plane, hipStream_t st)
+{
+  const int k_slice = ((K + splits - 1) / splits + 15) / 16 * 16;
+  const int z = (K + k_slice - 1) / k_slice;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, z);
+  if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, false, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, k_slice, c_plane);
+  else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<T, true, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, k_slice, c_plane);
+  else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<T, false, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, k_slice, c_plane);
+  else hipLaunchKernelGGL((gemm_kernel<T, true, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, k_slice, c_plane);
+  return hipGetLastError();
+}
+
+// number of K slices actually used by gemm() for a requested split count
+static int gemm_planes(int K, int splits)
+{
+  const int k_slice = ((K + splits - 1) / splits + 15) / 16 * 16;
+  return (K + k_slice - 1) / k_slice;
+}
+
+// ---------------------------------------------------------------------------- element-wise
+template <typename T>
+__device__ inline T sigm(T z) { return (T)1 / ((T)1 + exp(-z)); }
+
+// training forward epilogue: Z += b (in place), H = SiLU(Z)
+__global__ void bias_silu_kernel(float* __restrict__ Z, float* __restrict__ H, const float* __restrict__ b, int64_t rows,
+                                 int n)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * n) return;
+  const float z = Z[i] + b[i % n];
+  Z[i] = z;
+  H[i] = z * sigm(z);
+}
+
+// output layer: Y = Z + b, residual r = Y - T, loss partials per block, G = 2 r / batch
+__global__ void out_loss_kernel(const float* __restrict__ Z, const float* __restrict__ b, const float* __restrict__ Tg,
+                                int64_t rows, float inv_b2, float* __restrict__ G, double* __restrict__ part)
+{
+  __shared__ double red[256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double sq = 0.0;
+  if (i < rows * 2) {
+    const float y = Z[i] + b[i & 1];
+    const float r = y - Tg[i];
+    G[i] = r * inv_b2;
+    sq = (double)r * (double)r;
+  }
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_parts_kernel(const double* __restrict__ part, int n, double scale, float* __restrict__ out)
+{
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)(red[0] * scale);
+}
+
+// backward through SiLU: G *= SiLU'(Z)
+__global__ void silu_back_kernel(float* __restrict__ G, const float* __restrict__ Z, int64_t count)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float z = Z[i];
+  const float s = sigm(z);
+  G[i] *= s * (1.0f + z * (1.0f - s));
+}
+
+// sum of `planes` planes of `count` values into dst (fixed order)
+__global__ void sum_planes_kernel(const float* __restrict__ src, int planes, int64_t count, float* __restrict__ dst)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float s = 0.f;
+  for (int p = 0; p < planes; ++p) s += src[(int64_t)p * count + i];
+  dst[i] = s;
+}
+
+// db[j] = sum_r G[r][j], one workgroup per column (fixed-order tree)
+__global__ void col_sum_kernel(const float* __restrict__ G, int64_t rows, int n, float* __restrict__ db)
+{
+  __shared__ float red[256];
+  const int j = blockIdx.x;
+  float s = 0.f;
+  for (int64_t r = threadIdx.x; r < rows; r += 256) s += G[r * n + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[j] = red[0];
+}
+
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
+                            float* __restrict__ m2, int64_t count, float lr, float b1, float b2, float eps, float c1,
+                            float c2)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.f - b1) * gi;
+  const float v = b2 * m2[i] + (1.f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = v;
+  p[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// inference epilogue on [2R][n] (rows 0..R-1 values, R..2R-1 tangents):
+// value h = SiLU(z + b), tangent t = SiLU'(z + b) zt
+__global__ void act_tangent_kernel(double* __restrict__ Z, const double* __restrict__ b, int64_t R, int n)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R * n) return;
+  const double z = Z[i] + b[i % n];
+  const double s = sigm(z);
+  Z[i] = z * s;
+  Z[R * n + i] *= s * (1.0 + z * (1.0 - s));
+}
+
+// inference input rows: [U; e3] for the value and tangent passes
+__global__ void infer_input_kernel(const double* __restrict__ U, int64_t R, double* __restrict__ H)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R * 3) return;
+  H[i] = U[i];
+  H[R * 3 + i] = (i % 3 == 2) ? 1.0 : 0.0;
+}
+
+__global__ void infer_output_kernel(const double* __restrict__ Z, const double* __restrict__ b, int64_t R,
+                                    double* __restrict__ Y, double* __restrict__ dY)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R * 2) return;
+  Y[i] = Z[i] + b[i & 1];
+  dY[i] = Z[R * 2 + i];
+}
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// ---------------------------------------------------------------------------- inference
+size_t mlp_infer_scratch_bytes(int hidden, int64_t chunk)
+{
+  return 2 * (size_t)(2 * chunk) * (size_t)std::max(hidden, 3) * sizeof(double) + 256;
+}
+
+hipError_t mlp_infer(const sft_surrogate* s, const double* U, int64_t n, double* Y, double* dY, void* scratch,
+                     int64_t chunk, hipStream_t st)
+{
+  const int H = s->d.hidden, L = s->d.layers;
+  double* b0 = (double*)scratch;
+  double* b1 = b0 + (size_t)(2 * chunk) * std::max(H, 3);
+  for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+    const int64_t R = std::min(chunk, n - r0);
+    hipLaunchKernelGGL(infer_input_kernel, dim3(nblk(R * 3)), dim3(256), 0, st, U + r0 * 3, R, b0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double* hin = b0;
+    double* z = b1;
+    for (int l = 0; l <= L; ++l) {
+      const MlpLayer ly = mlp_layer(H, L, l);
+      e = gemm<double>(false, false, (int)(2 * R), ly.n_out, ly.n_in, hin, ly.n_in, s->par_inf + ly.w_off, ly.n_out,
+                       z, ly.n_out, 1, 0, st);
+      if (e != hipSuccess) return e;
+      if (l < L) {
+        hipLaunchKernelGGL(act_tangent_kernel, dim3(nblk(R * ly.n_out)), dim3(256), 0, st, z, s->par_inf + ly.b_off,
+                           R, ly.n_out);
+      } else {
+        hipLaunchKernelGGL(infer_output_kernel, dim3(nblk(R * 2)), dim3(256), 0, st, z, s->par_inf + ly.b_off, R,
+                           Y + r0 * 2, dY + r0 * 2);
+      }
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      std::swap(hin, z);
+    }
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------- training
+struct TrainBuf {
+  float* Z;      // [L+1][B][H] pre-activations (layer l at l*B*H); the output layer's [B][2] at L*B*H
+  float* Hs;     // [L+1][B][H] layer inputs: Hs[0] = U ([B][3]), Hs[l] = SiLU(Z[l-1])
+  float* G;      // [B][H] gradient buffer
+  float* G2;     // [B][H]
+  float* plane;  // [splits][H][H] split-K partial weight gradients
+  double* part;  // loss partials
+  int splits;
+};
+
+static size_t train_bytes(int H, int L, int64_t B, int splits)
+{
+  size_t f = (size_t)(L + 1) * B * H * 2 + (size_t)B * H * 2 + (size_t)splits * H * H;
+  return f * sizeof(float) + (size_t)nblk(B * 2) * sizeof(double) + 1024;
+}
+
+static void train_layout(void* ws, int H, int L, int64_t B, int splits, TrainBuf& t)
+{
+  float* f = (float*)ws;
+  t.Z = f;
+  f += (size_t)(L + 1) * B * H;
+  t.Hs = f;
+  f += (size_t)(L + 1) * B * H;
+  t.G = f;
+  f += (size_t)B * H;
+  t.G2 = f;
+  f += (size_t)B * H;
+  t.plane = f;
+  f += (size_t)splits * H * H;
+  t.part = (double*)(((uintptr_t)f + 255) / 256 * 256);
+  t.splits = splits;
+}
+
+// loss (mean over the batch of the summed squared residuals) and its gradient into s->grad
+static hipError_t loss_grad(sft_surrogate* s, const float* U, const float* Tg, int64_t B, float* loss, TrainBuf& t,
+                            hipStream_t st)
+{
+  const int H = s->d.hidden, L = s->d.layers;
+  hipError_t e;
+  // forward
+  const float* hin = U;
+  for (int l = 0; l <= L; ++l) {
+    const MlpLayer ly = mlp_layer(H, L, l);
+    float* Z = t.Z + (size_t)l * B * H;
+    if ((e = gemm<float>(false, false, (int)B, ly.n_out, ly.n_in, hin, ly.n_in, s->par + ly.w_off, ly.n_out, Z,
+                         ly.n_out, 1, 0, st)) != hipSuccess)
+      return e;
+    if (l < L) {
+      float* Hn = t.Hs + (size_t)(l + 1) * B * H;
+      hipLaunchKernelGGL(bias_silu_kernel, dim3(nblk(B * ly.n_out)), dim3(256), 0, st, Z, Hn, s->par + ly.b_off, B,
+                         ly.n_out);
+      hin = Hn;
+    } else {
+      hipLaunchKernelGGL(out_loss_kernel, dim3(nblk(B * 2)), dim3(256), 0, st, Z, s->par + ly.b_off, Tg, B,
+                         2.0f / (float)B, t.G, t.part);
+      hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, st, t.part, (int)nblk(B * 2), 1.0 / (double)B, loss);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // backward: t.G holds dL/dY [B][2]
+  float* G = t.G;
+  float* Gn = t.G2;
+  for (int l = L; l >= 0; --l) {
+    const MlpLayer ly = mlp_layer(H, L, l);
+    const float* Hl = l == 0 ? U : t.Hs + (size_t)l * B * H;
+    if (l < L) {
+      hipLaunchKernelGGL(silu_back_kernel, dim3(nblk(B * ly.n_out)), dim3(256), 0, st, G, t.Z + (size_t)l * B * H,
+                         B * ly.n_out);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // dW = Hl^T G  (K = B, split into planes), db = column sums of G
+    const int planes = gemm_planes((int)B, t.splits);
+    if ((e = gemm<float>(true, false, ly.n_in, ly.n_out, (int)B, Hl, ly.n_in, G, ly.n_out, t.plane, ly.n_out,
+                         t.splits, (int64_t)ly.n_in * ly.n_out, st)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(sum_planes_kernel, dim3(nblk((int64_t)ly.n_in * ly.n_out)), dim3(256), 0, st, t.plane, planes,
+                       (int64_t)ly.n_in * ly.n_out, s->grad + ly.w_off);
+    hipLaunchKernelGGL(col_sum_kernel, dim3(ly.n_out), dim3(256), 0, st, G, B, ly.n_out, s->grad + ly.b_off);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (l > 0) {
+      // G_prev = G W^T
+      if ((e = gemm<float>(false, true, (int)B, ly.n_in, ly.n_out, G, ly.n_out, s->par + ly.w_off, ly.n_out, Gn,
+                           ly.n_in, 1, 0, st)) != hipSuccess)
+        return e;
+      std::swap(G, Gn);
+    }
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------- C ABI
+static sft_status mlp_fail(sft_status st, const char* msg, hipError_t e = hipSuccess)
+{
+  char buf[320];
+  snprintf(buf, sizeof(buf), "%s%s%s", msg, e != hipSuccess ? ": " : "", e != hipSuccess ? hipGetErrorString(e) : "");
+  return sft_set_error(st, buf);
+}
+
+// inference copy: FP64 values of the FP32 parameters, optionally rounded to BF16
+// (round to nearest even on the upper 16 bits)
+__global__ void inference_copy_kernel(const float* __restrict__ p, double* __restrict__ q, int64_t n, int bf16)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float v = p[i];
+  if (bf16) {
+    uint32_t u = __float_as_uint(v);
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    v = __uint_as_float(u);
+  }
+  q[i] = (double)v;
+}
+
+static hipError_t refresh_inference_copy(sft_surrogate* s, hipStream_t st)
+{
+  hipLaunchKernelGGL(inference_copy_kernel, dim3(nblk(s->P)), dim3(256), 0, st, s->par, s->par_inf, s->P,
+                     s->d.weights_bf16);
+  return hipGetLastError();
+}
+
+extern "C" int64_t sft_surrogate_param_count(int32_t hidden, int32_t layers)
+{
+  if (hidden < 1 || layers < 1) return 0;
+  return mlp_param_count(hidden, layers);
+}
+
+extern "C" void sft_surrogate_free(sft_surrogate* s)
+{
+  if (!s) return;
+  if (s->par) (void)hipFree(s->par);
+  if (s->grad) (void)hipFree(s->grad);
+  if (s->mom1) (void)hipFree(s->mom1);
+  if (s->mom2) (void)hipFree(s->mom2);
+  if (s->par_inf) (void)hipFree(s->par_inf);
+  delete s;
+}
+
+extern "C" sft_status sft_surrogate_create(const sft_surrogate_desc* d, const float* params, sft_surrogate** out)
+{
+  if (!d || !params || !out) return mlp_fail(SFT_E_INVALID, "sft_surrogate_create: null argument");
+  *out = nullptr;
+  if (d->hidden < 8 || d->hidden > 256 || d->layers < 1 || d->layers > 8)
+    return mlp_fail(SFT_E_RANGE, "sft_surrogate_create: hidden must be in [8, 256], layers in [1, 8]");
+  if (!(d->mc_hi > d->mc_lo) || !(d->q_hi > d->q_lo) || !(d->lt_hi > d->lt_lo) || !(d->c_phi != 0.0) ||
+      !(d->c_amp != 0.0) || !(d->judge_tol >= 0.0))
+    return mlp_fail(SFT_E_INVALID, "sft_surrogate_create: bad ranges or scales");
+  sft_surrogate* s = new sft_surrogate();
+  std::memset(s, 0, sizeof(*s));
+  s->d = *d;
+  s->P = mlp_param_count(d->hidden, d->layers);
+  hipError_t e = hipGetDevice(&s->device);
+  if (e == hipSuccess) e = hipMalloc(&s->par, s->P * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&s->grad, s->P * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&s->mom1, s->P * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&s->mom2, s->P * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&s->par_inf, s->P * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(s->par, params, s->P * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(s->grad, 0, s->P * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(s->mom1, 0, s->P * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(s->mom2, 0, s->P * sizeof(float));
+  if (e == hipSuccess) e = refresh_inference_copy(s, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    sft_surrogate_free(s);
+    return mlp_fail(e == hipErrorOutOfMemory ? SFT_E_NOMEM : SFT_E_DEVICE, "sft_surrogate_create", e);
+  }
+  *out = s;
+  return SFT_OK;
+}
+
+extern "C" sft_status sft_surrogate_get_params(const sft_surrogate* s, float* params)
+{
+  if (!s || !params) return mlp_fail(SFT_E_INVALID, "sft_surrogate_get_params: null argument");
+  hipError_t e = hipMemcpy(params, s->par, s->P * sizeof(float), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? SFT_OK : mlp_fail(SFT_E_DEVICE, "sft_surrogate_get_params", e);
+}
+
+extern "C" sft_status sft_surrogate_loss_grad(sft_surrogate* s, const float* u, const float* y, int64_t n, float* loss,
+                                              float* grad, void* hip_stream)
+{
+  if (!s || !u || !y || !loss) return mlp_fail(SFT_E_INVALID, "sft_surrogate_loss_grad: null argument");
+  if (n < 1 || n > (1 << 21)) return mlp_fail(SFT_E_RANGE, "sft_surrogate_loss_grad: n outside [1, 2^21]");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, n / 256));
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, train_bytes(s->d.hidden, s->d.layers, n, splits), st);
+  if (e != hipSuccess) return mlp_fail(SFT_E_NOMEM, "sft_surrogate_loss_grad", e);
+  TrainBuf t;
+  train_layout(ws, s->d.hidden, s->d.layers, n, splits, t);
+  e = loss_grad(s, u, y, n, loss, t, st);
+  if (e == hipSuccess && grad) e = hipMemcpyAsync(grad, s->grad, s->P * sizeof(float), hipMemcpyDeviceToDevice, st);
+  hipError_t e2 = hipFreeAsync(ws, st);
+  if (e != hipSuccess) return mlp_fail(SFT_E_DEVICE, "sft_surrogate_loss_grad", e);
+  if (e2 != hipSuccess) return mlp_fail(SFT_E_DEVICE, "sft_surrogate_loss_grad: free", e2);
+  return SFT_OK;
+}
+
+extern "C" sft_status sft_surrogate_adam(sft_surrogate* s, float lr, void* hip_stream)
+{
+  if (!s) return mlp_fail(SFT_E_INVALID, "sft_surrogate_adam: null argument");
+  hipStream_t st = (hipStream_t)hip_stream;
+  s->step += 1;
+  const float c1 = 1.0f - powf(0.9f, (float)s->step), c2 = 1.0f - powf(0.999f, (float)s->step);
+  hipLaunchKernelGGL(adam_kernel, dim3(nblk(s->P)), dim3(256), 0, st, s->par, s->grad, s->mom1, s->mom2, s->P, lr, 0.9f,
+                     0.999f, 1e-8f, c1, c2);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = refresh_inference_copy(s, st);
+  return e == hipSuccess ? SFT_OK : mlp_fail(SFT_E_DEVICE, "sft_surrogate_adam", e);
+}
+
+extern "C" sft_status sft_surrogate_train(sft_surrogate* s, const float* u, const float* y, int64_t n, int32_t batch,
+                                          int32_t epochs, float lr, float lr_min, void* hip_stream, float* epoch_loss)
+{
+  if (!s || !u || !y) return mlp_fail(SFT_E_INVALID, "sft_surrogate_train: null argument");
+  if (batch < 16 || batch > (1 << 20) || n < batch || epochs < 1)
+    return mlp_fail(SFT_E_RANGE, "sft_surrogate_train: need 16 <= batch <= n and epochs >= 1");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int splits = std::min(64, std::max(1, batch / 256));
+  const int64_t steps = n / batch;
+  void* ws = nullptr;
+  float* dloss = nullptr;
+  hipError_t e = hipMallocAsync(&ws, train_bytes(s->d.hidden, s->d.layers, batch, splits) + steps * sizeof(float), st);
+  if (e != hipSuccess) return mlp_fail(SFT_E_NOMEM, "sft_surrogate_train", e);
+  TrainBuf t;
+  train_layout(ws, s->d.hidden, s->d.layers, batch, splits, t);
+  dloss = (float*)((char*)ws + train_bytes(s->d.hidden, s->d.layers, batch, splits));
+  std::vector<float> hl(steps);
+  const double total = (double)epochs * steps;
+  int64_t it = 0;
+  for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+    for (int64_t k = 0; k < steps && e == hipSuccess; ++k, ++it) {
+      // cosine learning-rate schedule from lr to lr_min
+      const float lrt = lr_min + 0.5f * (lr - lr_min) * (1.0f + (float)cos(M_PI * (double)it / total));
+      e = loss_grad(s, u + k * batch * 3, y + k * batch * 2, batch, dloss + k, t, st);
+      if (e != hipSuccess) break;
+      s->step += 1;
+      const float c1 = 1.0f - powf(0.9f, (float)s->step), c2 = 1.0f - powf(0.999f, (float)s->step);
+      hipLaunchKernelGGL(adam_kernel, dim3(nblk(s->P)), dim3(256), 0, st, s->par, s->grad, s->mom1, s->mom2, s->P, lrt,
+                         0.9f, 0.999f, 1e-8f, c1, c2);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess && epoch_loss) {
+      e = hipMemcpyAsync(hl.data(), dloss, steps * sizeof(float), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      double m = 0.0;
+      for (float v : hl) m += v;
+      epoch_loss[ep] = (float)(m / (double)steps);
+    }
+  }
+  if (e == hipSuccess) e = refresh_inference_copy(s, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipError_t e2 = hipFreeAsync(ws, st);
+  if (e != hipSuccess) return mlp_fail(SFT_E_DEVICE, "sft_surrogate_train", e);
+  if (e2 != hipSuccess) return mlp_fail(SFT_E_DEVICE, "sft_surrogate_train: free", e2);
+  return SFT_OK;
+}
+
+extern "C" sft_status sft_surrogate_infer(const sft_surrogate* s, const double* u, int64_t n, double* y, double* dy,
+                                          void* hip_stream)
+{
+  if (!s || !u || !y || !dy) return mlp_fail(SFT_E_INVALID, "sft_surrogate_infer: null argument");
+  if (n < 0) return mlp_fail(SFT_E_INVALID, "sft_surrogate_infer: negative n");
+  if (n == 0) return SFT_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t chunk = std::min<int64_t>(n, 1 << 16);
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, mlp_infer_scratch_bytes(s->d.hidden, chunk), st);
+  if (e != hipSuccess) return mlp_fail(SFT_E_NOMEM, "sft_surrogate_infer", e);
+  e = mlp_infer(s, u, n, y, dy, ws, chunk, st);
+  hipError_t e2 = hipFreeAsync(ws, st);
+  if (e != hipSuccess) return mlp_fail(SFT_E_DEVICE, "sft_surrogate_infer", e);
+  if (e2 != hipSuccess) return mlp_fail(SFT_E_DEVICE, "sft_surrogate_infer: free", e2);
+  return SFT_OK;
+}

@@ -19,8 +19,9 @@ SFT_OK = 0
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
 KERNEL = {"dirichlet": 0, "fresnel": 1, "auto": 2}
 PRECISION = {"fp64": 0, "fp32_kahan": 1, "fp32_naive": 2}
-WAVEFORM = {"newton": 0, "pn35": 1}
+WAVEFORM = {"newton": 0, "pn35": 1, "surrogate": 2}
 FLAG_OUT_OF_BAND, FLAG_TAU_NONPOSITIVE, FLAG_TAYLOR_INVALID, FLAG_NONFINITE, FLAG_EMPTY = 1, 2, 4, 8, 64
+FLAG_SURROGATE_FALLBACK = 32
 K_MAX = 64
 T_SUN = 4.925490947641267e-6
 
@@ -40,7 +41,8 @@ class DataDesc(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("waveform", ctypes.c_int32), ("beta_switch", ctypes.c_double), ("a_plus", ctypes.c_double),
-                ("a_cross", ctypes.c_double), ("tsun", ctypes.c_double), ("delta_max", ctypes.c_double)]
+                ("a_cross", ctypes.c_double), ("tsun", ctypes.c_double), ("delta_max", ctypes.c_double),
+                ("surrogate", ctypes.c_void_p)]
 
 
 class Bank(ctypes.Structure):
@@ -50,7 +52,16 @@ class Bank(ctypes.Structure):
 
 class Out(ctypes.Structure):
     _fields_ = [("zp", ctypes.c_void_p), ("zx", ctypes.c_void_p), ("hhp", ctypes.c_void_p),
-                ("hhx", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+                ("hhx", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("mismatch", ctypes.c_void_p)]
+
+
+class SurrogateDesc(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_int32), ("layers", ctypes.c_int32), ("head", ctypes.c_int32),
+                ("weights_bf16", ctypes.c_int32), ("mc_lo", ctypes.c_double), ("mc_hi", ctypes.c_double),
+                ("q_lo", ctypes.c_double), ("q_hi", ctypes.c_double), ("lt_lo", ctypes.c_double),
+                ("lt_hi", ctypes.c_double), ("c_phi", ctypes.c_double), ("c_amp", ctypes.c_double),
+                ("judge_tol", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -64,7 +75,9 @@ class Tuning(ctypes.Structure):
 EXPORTS = ["sft_load_data", "sft_free_data", "sft_default_opts", "sft_template_bank_scan",
            "sft_inner_product", "sft_last_error", "sft_version", "sft_kernel_timing", "sft_kernel_times",
            "sft_get_tuning", "sft_set_tuning", "sft_autotune", "sft_plan_create", "sft_plan_launch",
-           "sft_plan_destroy"]
+           "sft_plan_destroy", "sft_surrogate_param_count", "sft_surrogate_create", "sft_surrogate_free",
+           "sft_surrogate_get_params", "sft_surrogate_targets", "sft_surrogate_loss_grad", "sft_surrogate_adam",
+           "sft_surrogate_train", "sft_surrogate_infer"]
 
 _lib = None
 
@@ -113,6 +126,25 @@ def lib():
     L.sft_kernel_timing.restype = ctypes.c_int32
     L.sft_kernel_times.argtypes = [P, ctypes.c_int32]
     L.sft_kernel_times.restype = ctypes.c_int32
+    I32, I64, F32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    L.sft_surrogate_param_count.argtypes = [I32, I32]
+    L.sft_surrogate_param_count.restype = I64
+    L.sft_surrogate_create.argtypes = [ctypes.POINTER(SurrogateDesc), P, ctypes.POINTER(P)]
+    L.sft_surrogate_create.restype = I32
+    L.sft_surrogate_free.argtypes = [P]
+    L.sft_surrogate_free.restype = None
+    L.sft_surrogate_get_params.argtypes = [P, P]
+    L.sft_surrogate_get_params.restype = I32
+    L.sft_surrogate_targets.argtypes = [P, P, P, P, I64, D, P, P, P]
+    L.sft_surrogate_targets.restype = I32
+    L.sft_surrogate_loss_grad.argtypes = [P, P, P, I64, P, P, P]
+    L.sft_surrogate_loss_grad.restype = I32
+    L.sft_surrogate_adam.argtypes = [P, F32, P]
+    L.sft_surrogate_adam.restype = I32
+    L.sft_surrogate_train.argtypes = [P, P, P, I64, I32, I32, F32, F32, P, P]
+    L.sft_surrogate_train.restype = I32
+    L.sft_surrogate_infer.argtypes = [P, P, I64, P, P, P]
+    L.sft_surrogate_infer.restype = I32
     _lib = L
     return L
 
@@ -134,7 +166,7 @@ def _stream_ptr(stream) -> Optional[int]:
 
 
 def make_opts(K=8, kernel="auto", precision="fp32_kahan", waveform="newton", beta_switch=1e-7,
-              a_plus=1.0, a_cross=0.0, tsun=T_SUN, delta_max=0.0) -> Opts:
+              a_plus=1.0, a_cross=0.0, tsun=T_SUN, delta_max=0.0, surrogate=None) -> Opts:
     o = Opts()
     lib().sft_default_opts(ctypes.byref(o))
     o.K = int(K)
@@ -146,6 +178,9 @@ def make_opts(K=8, kernel="auto", precision="fp32_kahan", waveform="newton", bet
     o.a_cross = float(a_cross)
     o.tsun = float(tsun)
     o.delta_max = float(delta_max)
+    if surrogate is not None:
+        o.surrogate = surrogate.handle
+        o._surrogate_ref = surrogate   # keep the network alive with the options
     return o
 
 
@@ -208,14 +243,17 @@ def bank_to_device(bank: Dict[str, np.ndarray], device="cuda"):
     return out
 
 
-def alloc_out(n: int, device="cuda"):
+def alloc_out(n: int, device="cuda", mismatch=False):
     import torch
-    return {"zp": torch.empty((n, 2), dtype=torch.float64, device=device),
-            "zx": torch.empty((n, 2), dtype=torch.float64, device=device),
-            "hhp": torch.empty(n, dtype=torch.float64, device=device),
-            "hhx": torch.empty(n, dtype=torch.float64, device=device),
-            "rho": torch.empty(n, dtype=torch.float64, device=device),
-            "flags": torch.empty(n, dtype=torch.int32, device=device)}
+    out = {"zp": torch.empty((n, 2), dtype=torch.float64, device=device),
+           "zx": torch.empty((n, 2), dtype=torch.float64, device=device),
+           "hhp": torch.empty(n, dtype=torch.float64, device=device),
+           "hhx": torch.empty(n, dtype=torch.float64, device=device),
+           "rho": torch.empty(n, dtype=torch.float64, device=device),
+           "flags": torch.empty(n, dtype=torch.int32, device=device)}
+    if mismatch:
+        out["mismatch"] = torch.zeros(n, dtype=torch.float64, device=device)
+    return out
 
 
 def _tp(t):
@@ -232,7 +270,7 @@ def _bank_struct(bank_t):
 
 def _out_struct(out):
     return Out(_tp(out["zp"]), _tp(out["zx"]), _tp(out["hhp"]), _tp(out["hhx"]), _tp(out["rho"]),
-               _tp(out["flags"]))
+               _tp(out["flags"]), _tp(out.get("mismatch")))
 
 
 def template_bank_scan(data: SFTData, bank_t, opts: Opts, out=None, stream=None, n=None):
@@ -321,6 +359,87 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().sft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------------- surrogate
+def surrogate_param_count(hidden: int, layers: int) -> int:
+    return int(lib().sft_surrogate_param_count(int(hidden), int(layers)))
+
+
+class Surrogate:
+    """The learned-surrogate network (owns an sft_surrogate handle on the current device).
+
+    params: FP32 values (any float array) packed layer by layer, W [n_in][n_out] then b.
+    Ranges: mc, q and ln(tau) of the input normalisation; c_phi, c_amp output scales;
+    head = 1 adds the analytic 1PN + 1.5PN phase; judge_tol the mismatch tolerance."""
+
+    def __init__(self, params, hidden=128, layers=4, head=1, weights_bf16=0, mc=(1.19, 1.21), q=(1.0, 2.0),
+                 ln_tau=(6.39, 9.74), c_phi=1.0, c_amp=1.0, judge_tol=1e-4):
+        self.desc = SurrogateDesc(int(hidden), int(layers), int(head), int(weights_bf16), float(mc[0]),
+                                  float(mc[1]), float(q[0]), float(q[1]), float(ln_tau[0]), float(ln_tau[1]),
+                                  float(c_phi), float(c_amp), float(judge_tol))
+        self.P = surrogate_param_count(hidden, layers)
+        par = np.ascontiguousarray(params, dtype=np.float32)
+        if par.size != self.P:
+            raise ValueError("expected %d parameters, got %d" % (self.P, par.size))
+        h = ctypes.c_void_p()
+        _check(lib().sft_surrogate_create(ctypes.byref(self.desc), _p(par), ctypes.byref(h)))
+        self.handle = h
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.P, dtype=np.float32)
+        _check(lib().sft_surrogate_get_params(self.handle, _p(out)))
+        return out
+
+    def targets(self, mc_t, q_t, tau_t, tsun=T_SUN, stream=None):
+        """Device FP64 mc, q, tau -> device FP32 inputs u [n][3] and targets y [n][2]."""
+        import torch
+        n = int(mc_t.numel())
+        u = torch.empty((n, 3), dtype=torch.float32, device=mc_t.device)
+        y = torch.empty((n, 2), dtype=torch.float32, device=mc_t.device)
+        _check(lib().sft_surrogate_targets(self.handle, _tp(mc_t), _tp(q_t), _tp(tau_t), n, float(tsun), _tp(u),
+                                           _tp(y), _stream_ptr(stream)))
+        return u, y
+
+    def loss_grad(self, u, y, stream=None):
+        """FP32 loss (mean over rows of the squared residual norm) and gradient [P] (device)."""
+        import torch
+        n = int(u.shape[0])
+        loss = torch.empty(1, dtype=torch.float32, device=u.device)
+        grad = torch.empty(self.P, dtype=torch.float32, device=u.device)
+        _check(lib().sft_surrogate_loss_grad(self.handle, _tp(u), _tp(y), n, _tp(loss), _tp(grad),
+                                             _stream_ptr(stream)))
+        return loss, grad
+
+    def adam(self, lr, stream=None):
+        _check(lib().sft_surrogate_adam(self.handle, float(lr), _stream_ptr(stream)))
+
+    def train(self, u, y, batch=4096, epochs=1, lr=1e-3, lr_min=1e-5, stream=None) -> np.ndarray:
+        """Mini-batch Adam over device (u, y) in row order; returns the mean loss per epoch."""
+        buf = np.zeros(int(epochs), dtype=np.float32)
+        _check(lib().sft_surrogate_train(self.handle, _tp(u), _tp(y), int(u.shape[0]), int(batch), int(epochs),
+                                         float(lr), float(lr_min), _stream_ptr(stream), _p(buf)))
+        return buf
+
+    def infer(self, u64, stream=None):
+        """The scan's FP64 network evaluation: u [n][3] -> y [n][2], dy/du_tau [n][2] (device)."""
+        import torch
+        n = int(u64.shape[0])
+        y = torch.empty((n, 2), dtype=torch.float64, device=u64.device)
+        dy = torch.empty((n, 2), dtype=torch.float64, device=u64.device)
+        _check(lib().sft_surrogate_infer(self.handle, _tp(u64), n, _tp(y), _tp(dy), _stream_ptr(stream)))
+        return y, dy
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().sft_surrogate_free(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -33,7 +33,9 @@ def test_version_and_defaults():
     assert (o.K, o.kernel, o.precision, o.waveform) == (8, 2, 1, 0)
     assert o.beta_switch == 1e-7 and o.a_plus == 1.0 and o.a_cross == 0.0
     assert abs(o.tsun - 4.925490947641267e-6) < 1e-20
-    assert ctypes.sizeof(sft.DataDesc) == 32 and ctypes.sizeof(sft.Opts) == 56
+    assert o.surrogate is None
+    assert ctypes.sizeof(sft.DataDesc) == 32 and ctypes.sizeof(sft.Opts) == 64
+    assert ctypes.sizeof(sft.Out) == 56 and ctypes.sizeof(sft.SurrogateDesc) == 88
 
 
 def test_load_data_rejects_bad_descriptors():
@@ -65,3 +67,31 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(sft, "LIB_PATH", "/nonexistent/libsft.so")
     with pytest.raises(RuntimeError):
         sft.lib()
+
+
+def test_surrogate_host_validation(orc):
+    L = sft.lib()
+    assert sft.surrogate_param_count(128, 4) == 50306 == orc.mlp_param_count(128, 4)
+    assert sft.surrogate_param_count(32, 2) == orc.mlp_param_count(32, 2)
+    assert sft.surrogate_param_count(0, 4) == 0
+    h = ctypes.c_void_p()
+    par = (ctypes.c_float * 16)()
+    good = dict(hidden=32, layers=2, head=1, weights_bf16=0, mc_lo=1.0, mc_hi=2.0, q_lo=1.0, q_hi=2.0,
+                lt_lo=6.0, lt_hi=9.0, c_phi=1.0, c_amp=0.01, judge_tol=1e-4)
+    for bad, code in [(dict(hidden=4), -4), (dict(layers=9), -4), (dict(mc_hi=1.0), -1),
+                      (dict(lt_hi=5.0), -1), (dict(c_phi=0.0), -1), (dict(judge_tol=-1.0), -1)]:
+        d = sft.SurrogateDesc(**dict(good, **bad))
+        assert L.sft_surrogate_create(ctypes.byref(d), par, ctypes.byref(h)) == code, bad
+        assert sft.last_error().startswith("sft_surrogate_create")
+    assert L.sft_surrogate_create(None, par, ctypes.byref(h)) == -1
+    assert L.sft_surrogate_targets(None, None, None, None, 1, 1.0, None, None, None) == -1
+    assert L.sft_surrogate_infer(None, None, 1, None, None, None) == -1
+    assert L.sft_surrogate_loss_grad(None, None, None, 1, None, None, None) == -1
+    assert L.sft_surrogate_train(None, None, None, 1, 16, 1, 1e-3, 1e-5, None, None) == -1
+    assert L.sft_surrogate_adam(None, 1e-3, None) == -1
+    # a surrogate scan without a network is rejected before any device work
+    opts = sft.make_opts(waveform="surrogate")
+    b, o = sft.Bank(), sft.Out()
+    fake = ctypes.c_void_p(1)
+    assert L.sft_template_bank_scan(fake, ctypes.byref(b), 1, ctypes.byref(opts), ctypes.byref(o), None) == -1
+    assert "surrogate" in sft.last_error()
