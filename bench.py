@@ -104,6 +104,11 @@ def parse():
                    help="block,chunk_groups,persistent: use this launch shape instead of autotuning")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only a plain device copy of known size (counter calibration)")
+    p.add_argument("--surrogate-templates", type=int, default=1_000_000,
+                   help="templates of the learned-surrogate leg (0 = skip the leg)")
+    p.add_argument("--surrogate-samples", type=int, default=10_000_000)
+    p.add_argument("--surrogate-epochs", type=int, default=8)
+    p.add_argument("--surrogate-only", action="store_true", help="run only the surrogate leg")
     return p.parse_args()
 
 
@@ -130,6 +135,10 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+
+    if args.surrogate_only:
+        print(json.dumps(surrogate_leg(args)), flush=True)
         return
 
     t0 = time.time()
@@ -216,7 +225,87 @@ def main():
 
     if not args.no_cpu_baseline and args.cpu_sample > 0:
         res["cpu_baseline"] = cpu_baseline(w, out, args.cpu_sample, K, kernel)
+    del out, bank, data
+    if args.surrogate_templates > 0:
+        res["surrogate"] = surrogate_leg(args)
     print(json.dumps(res), flush=True)
+
+
+# the learned surrogate's domain on the tiny data: Mc in [1.19, 1.21], q in [1, 2],
+# tau in [600, 16984] s; phase scale 2 rad, log-amplitude scale 0.01, analytic head
+SUR_CFG = dict(mc=(1.19, 1.21), q=(1.0, 2.0), ln_tau=(float(np.log(600.0)), float(np.log(16984.0))),
+               c_phi=2.0, c_amp=0.01, head=1)
+
+
+def surrogate_leg(args):
+    """Learned-surrogate form on the tiny data (256 SFTs of 64 s, one detector, K = 4
+    Dirichlet): the network 3 -> 128 x 4 -> 2 is trained with the library's kernels on
+    3.5PN targets, then the bank (Mc ~ U[1.19, 1.21], q ~ U[1, 2]) is scanned with the
+    surrogate waveform (FP64 network evaluation, judge at 1e-4 with 3.5PN fallback) and,
+    for comparison, with the plain leading-order chirp and with the 3.5PN waveform."""
+    import torch
+    from paper_2502_11823_amd import sft, synth
+    hidden, layers = 128, 4
+    w = synth.tiny(seed=1, n_templates=1, noise_series=False)
+    n = args.surrogate_templates
+    bank = synth.uniform_bank(n, 1.19, 1.21, 16984.0, 501, q_lo=1.0, q_hi=2.0, random_phase=True,
+                              n_sft=w.n_sft)
+    data = sft.SFTData.from_workload(w, storage="f32")
+    bt = sft.bank_to_device(bank)
+    s = sft.Surrogate(synth.mlp_init(23, hidden, layers), hidden=hidden, layers=layers, judge_tol=1e-4,
+                      **SUR_CFG)
+    # training set on the device
+    t0 = time.perf_counter()
+    mc, q, tau = synth.surrogate_samples(args.surrogate_samples, 41, 1.19, 1.21, 1.0, 2.0, 600.0, 16984.0)
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
+    u, y = s.targets(dev(mc), dev(q), dev(tau))
+    del mc, q, tau
+    torch.cuda.synchronize()
+    t_targets = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = s.train(u, y, batch=4096, epochs=args.surrogate_epochs, lr=2e-3, lr_min=1e-5)
+    t_train = time.perf_counter() - t0
+    del u, y
+    print("surrogate training: %d samples x %d epochs in %.1f s, loss %s" % (
+        args.surrogate_samples, args.surrogate_epochs, t_train, np.array2string(hist, precision=2)),
+        file=sys.stderr, flush=True)
+
+    out = sft.alloc_out(n, mismatch=True)
+    steps = max(1, min(args.steps, 3))
+
+    def timed(opts):
+        sft.template_bank_scan(data, bt, opts, out=out)    # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            sft.template_bank_scan(data, bt, opts, out=out)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) / steps
+
+    common = dict(K=4, kernel="dirichlet", precision="fp32_kahan")
+    t_plain = timed(sft.make_opts(waveform="newton", **common))
+    t_pn = timed(sft.make_opts(waveform="pn35", **common))
+    t_sur = timed(sft.make_opts(waveform="surrogate", surrogate=s, **common))
+    flags = out["flags"].cpu().numpy()
+    mm = out["mismatch"].cpu().numpy()
+    fb = float(np.mean((flags & sft.FLAG_SURROGATE_FALLBACK) > 0))
+    evals = n * w.n_sft
+    mlp_flop = evals * 2 * 2 * (3 * hidden + (layers - 1) * hidden * hidden + hidden * 2)
+    res = {"workload": "tiny data (256 SFTs x 64 s, 1 detector, K=4 Dirichlet, FP32 Kahan sums), %d templates "
+                       "Mc~U[1.19,1.21] q~U[1,2]; MLP 3-%dx%d-2 SiLU trained on %d 3.5PN samples"
+                       % (n, hidden, layers, args.surrogate_samples),
+           "value": n / t_sur, "unit": "IP/s", "ms_per_step": 1e3 * t_sur, "steps": steps,
+           "plain_newton_value": n / t_plain, "pn35_value": n / t_pn,
+           "surrogate_over_plain": t_plain / t_sur, "surrogate_over_pn35": t_pn / t_sur,
+           "network_evals_per_step": evals, "network_fp64_tflop_per_step": mlp_flop / 1e12,
+           "fallback_frac": fb, "judge_tol": 1e-4,
+           "mismatch_median": float(np.median(mm)), "mismatch_p99": float(np.quantile(mm, 0.99)),
+           "train": {"samples": args.surrogate_samples, "epochs": args.surrogate_epochs, "batch": 4096,
+                     "targets_s": t_targets, "train_s": t_train, "epoch_loss": [float(v) for v in hist]}}
+    print("surrogate scan %.1f ms (plain %.2f ms, 3.5PN %.2f ms), fallback %.4f" % (
+        1e3 * t_sur, 1e3 * t_plain, 1e3 * t_pn, fb), file=sys.stderr, flush=True)
+    s.close()
+    return res
 
 
 def cpu_baseline(w, out, n_sample, K, kernel):

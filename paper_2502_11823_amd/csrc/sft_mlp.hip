@@ -261,9 +261,152 @@ __global__ void infer_output_kernel(const double* __restrict__ Z, const double* 
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// ---------------------------------------------------------------------------- fused inference
+// The whole network for 16 rows per wavefront (64 rows per workgroup), activations kept in
+// registers.  Hidden layers run on the FP64 matrix cores (v_mfma_f64_16x16x4f64) in
+// transposed form, D = W^T A: M = output units (16 per tile), N = the wavefront's 16 rows,
+// K = input units.  Operand layouts: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, and
+// D[i][j] in lane j + 16 (i % 4), element i / 4.  So lane l (row j = l % 16, group
+// g = l / 16) holds in its accumulators the units 16 m + g + 4 v (v = 0..3) of row j, and
+// those are exactly the B-operand values it must supply in the next layer when the K slots
+// of step s are the units 16 (s / 4) + g + 4 (s % 4) (a permutation of K, applied to the
+// weight operand too), so
+// activations pass from layer to layer without a transpose.  Value and tangent rows share
+// each weight fragment (two MFMAs per fragment).  Each hidden layer's weights are staged in
+// LDS once per workgroup.  The first layer (K = 3) and the output layer (2 units) use plain
+// FMAs, the latter with a reduction over the four lane groups.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void silu_tangent(double z, double zt, double& h, double& t)
+{
+  const double s = 1.0 / (1.0 + exp(-z));
+  h = z * s;
+  t = s * (1.0 + z * (1.0 - s)) * zt;
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void mlp_fused_kernel(const double* __restrict__ U, int64_t n,
+                                                        const double* __restrict__ par, int layers,
+                                                        double* __restrict__ Y, double* __restrict__ dY)
+{
+  constexpr int H = 16 * NT;
+  __shared__ double wl[H * H];   // the current hidden layer's W [H][H]
+  const int lane = threadIdx.x & 63;
+  const int j = lane & 15, g = lane >> 4;
+  const int64_t r = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + j;
+  const bool valid = r < n;
+  double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+  if (valid) {
+    u0 = U[3 * r];
+    u1 = U[3 * r + 1];
+    u2 = U[3 * r + 2];
+  }
+  double av[NT][4], at[NT][4];
+  {
+    const double* W = par;           // [3][H]
+    const double* b = par + 3 * H;   // [H]
+#pragma unroll
+    for (int m = 0; m < NT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int u = 16 * m + g + 4 * v;
+        const double z = fma(W[2 * H + u], u2, fma(W[H + u], u1, fma(W[u], u0, b[u])));
+        silu_tangent(z, W[2 * H + u], av[m][v], at[m][v]);
+      }
+  }
+  int64_t off = 4 * H;
+  for (int l = 1; l < layers; ++l) {
+    const double* W = par + off;     // [H][H]
+    const double* b = W + H * H;     // [H]
+    __syncthreads();                 // every wavefront is done with the previous layer's weights
+    // direct global -> LDS copies (16 bytes per lane; a wavefront fills 1 KiB at the
+    // wave-uniform LDS base, lane i at base + 16 i), no registers in between
+    constexpr int PER = (H * H + 511) / 512;
+#pragma unroll
+    for (int c = 0; c < PER; ++c) {
+      const int i = 2 * threadIdx.x + 512 * c;
+      if (i < H * H)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(W + i),
+                                         (__attribute__((address_space(3))) void*)(wl + 512 * c + 128 * (threadIdx.x >> 6)),
+                                         16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    double nv[NT][4], nt[NT][4];
+#pragma unroll
+    for (int mo = 0; mo < NT; ++mo) {
+      dbl4 cv = {0.0, 0.0, 0.0, 0.0}, ct = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4 * NT; ++s) {
+        const int kin = 16 * (s >> 2) + g + 4 * (s & 3);
+        const double a = wl[kin * H + 16 * mo + j];
+        cv = __builtin_amdgcn_mfma_f64_16x16x4f64(a, av[s >> 2][s & 3], cv, 0, 0, 0);
+        ct = __builtin_amdgcn_mfma_f64_16x16x4f64(a, at[s >> 2][s & 3], ct, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) silu_tangent(cv[v] + b[16 * mo + g + 4 * v], ct[v], nv[mo][v], nt[mo][v]);
+    }
+#pragma unroll
+    for (int m = 0; m < NT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        av[m][v] = nv[m][v];
+        at[m][v] = nt[m][v];
+      }
+    off += (int64_t)H * H + H;
+  }
+  const double* W = par + off;   // [H][2]
+  const double* b = W + 2 * H;
+  double y0 = 0.0, y1 = 0.0, t0 = 0.0, t1 = 0.0;
+#pragma unroll
+  for (int m = 0; m < NT; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int u = 16 * m + g + 4 * v;
+      y0 = fma(W[2 * u], av[m][v], y0);
+      y1 = fma(W[2 * u + 1], av[m][v], y1);
+      t0 = fma(W[2 * u], at[m][v], t0);
+      t1 = fma(W[2 * u + 1], at[m][v], t1);
+    }
+  y0 += __shfl_xor(y0, 16);
+  y1 += __shfl_xor(y1, 16);
+  t0 += __shfl_xor(t0, 16);
+  t1 += __shfl_xor(t1, 16);
+  y0 += __shfl_xor(y0, 32);
+  y1 += __shfl_xor(y1, 32);
+  t0 += __shfl_xor(t0, 32);
+  t1 += __shfl_xor(t1, 32);
+  if (g == 0 && valid) {
+    Y[2 * r] = y0 + b[0];
+    Y[2 * r + 1] = y1 + b[1];
+    dY[2 * r] = t0;
+    dY[2 * r + 1] = t1;
+  }
+}
+
+static bool mlp_fused_ok(int hidden) { return hidden % 16 == 0 && hidden >= 16 && hidden <= 128; }
+
+static hipError_t mlp_fused(const sft_surrogate* s, const double* U, int64_t n, double* Y, double* dY, hipStream_t st)
+{
+  const dim3 grid((unsigned)((n + 63) / 64)), block(256);
+  const int L = s->d.layers;
+  switch (s->d.hidden / 16) {
+  case 1: hipLaunchKernelGGL(mlp_fused_kernel<1>, grid, block, 0, st, U, n, s->par_inf, L, Y, dY); break;
+  case 2: hipLaunchKernelGGL(mlp_fused_kernel<2>, grid, block, 0, st, U, n, s->par_inf, L, Y, dY); break;
+  case 3: hipLaunchKernelGGL(mlp_fused_kernel<3>, grid, block, 0, st, U, n, s->par_inf, L, Y, dY); break;
+  case 4: hipLaunchKernelGGL(mlp_fused_kernel<4>, grid, block, 0, st, U, n, s->par_inf, L, Y, dY); break;
+  case 5: hipLaunchKernelGGL(mlp_fused_kernel<5>, grid, block, 0, st, U, n, s->par_inf, L, Y, dY); break;
+  case 6: hipLaunchKernelGGL(mlp_fused_kernel<6>, grid, block, 0, st, U, n, s->par_inf, L, Y, dY); break;
+  case 7: hipLaunchKernelGGL(mlp_fused_kernel<7>, grid, block, 0, st, U, n, s->par_inf, L, Y, dY); break;
+  default: hipLaunchKernelGGL(mlp_fused_kernel<8>, grid, block, 0, st, U, n, s->par_inf, L, Y, dY); break;
+  }
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------- inference
 size_t mlp_infer_scratch_bytes(int hidden, int64_t chunk)
 {
+  if (mlp_fused_ok(hidden)) return 256;
   return 2 * (size_t)(2 * chunk) * (size_t)std::max(hidden, 3) * sizeof(double) + 256;
 }
 
@@ -271,6 +414,7 @@ hipError_t mlp_infer(const sft_surrogate* s, const double* U, int64_t n, double*
                      int64_t chunk, hipStream_t st)
 {
   const int H = s->d.hidden, L = s->d.layers;
+  if (mlp_fused_ok(H)) return n > 0 ? mlp_fused(s, U, n, Y, dY, st) : hipSuccess;
   double* b0 = (double*)scratch;
   double* b1 = b0 + (size_t)(2 * chunk) * std::max(H, 3);
   for (int64_t r0 = 0; r0 < n; r0 += chunk) {

@@ -54,9 +54,11 @@ def dev(a, dtype=torch.float64):
 
 
 # ----------------------------------------------------------------------------- network evaluation
-@pytest.mark.parametrize("hidden,layers,n,bf16", [(32, 2, 1000, 0), (128, 4, 70000, 0), (128, 4, 3000, 1)])
+@pytest.mark.parametrize("hidden,layers,n,bf16", [(32, 2, 1000, 0), (128, 4, 70000, 0), (128, 4, 3000, 1),
+                                                 (24, 2, 70000, 0), (16, 1, 77, 0)])
 def test_fp64_inference_matches_oracle_forward(hidden, layers, n, bf16):
-    """n = 70000 crosses the 65536-row chunk of the scan's evaluation."""
+    """Widths that are multiples of 16 up to 128 take the fused matrix-core kernel, others the
+    layer-by-layer GEMM path (n = 70000 crosses its 65536-row chunk)."""
     par = synth.mlp_init(7, hidden, layers)
     u = synth.rng(11).uniform(-1.0, 1.0, (n, 3))
     s = make_surrogate(par, hidden, layers, bf16=bf16)
