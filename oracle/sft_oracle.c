@@ -628,7 +628,7 @@ int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
       long lo = a_first ? a_first[m] : 0, hi = a_last ? a_last[m] : n_sft - 1;
       int wfm = wf;
       if (wf == ORC_WF_SURROGATE) {
-        /* surrogate judge (reading R22): match of the surrogate against the 3.5PN
+        /* surrogate judge (reading R23): match of the surrogate against the 3.5PN
          * waveform in the SFT framework, |sum_a w_a e^{i dphi_a} sinc(T df_a)| / sum_a w_a,
          * w_a = A_PN,a^2 over the template's SFTs; mismatch above the tolerance selects
          * the 3.5PN waveform for this template. */

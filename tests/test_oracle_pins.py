@@ -477,3 +477,34 @@ def test_p14_surrogate_limits(orc):
         orc.set_pn_order(7)
     y7 = orc.surrogate_targets([1.2], [1.6], [5e3], head=True, c_phi=1.0, c_amp=1.0)
     assert abs(y7[0, 0]) > 1e-3
+
+
+def test_p14_judge_special_cases(orc):
+    """P14c: the judge's mismatch is 0 when the surrogate and the 3.5PN waveform coincide (a
+    zero network without the head is the Newtonian chirp, and so is the 3.5PN waveform kept at
+    order 0), is positive when they differ, and a template with no SFT before coalescence has
+    no weight: mismatch 0, no fallback."""
+    w = synth.tiny(seed=3, n_templates=4, n_sft=16, noise_series=False)
+    od = orc.SFTData(w.t_start, w.n_samples, w.t_sft, w.k_lo, w.x_bins, w.psd)
+    n = orc.mlp_param_count(16, 2)
+    cfg = dict(mc_lo=1.19, mc_hi=1.21, q_lo=1.0, q_hi=2.0, lt_lo=np.log(100.0), lt_hi=np.log(2e4),
+               c_phi=1.0, c_amp=1.0, judge_tol=1e-4, head=False)
+    mc = np.array([1.195, 1.2, 1.205, 1.2])
+    q = np.array([1.0, 1.3, 1.9, 1.5])
+    tc = np.array([1100.0, 1100.0, 1100.0, 10.0])     # the last template coalesces before the data
+    try:
+        orc.set_surrogate(np.zeros(n), cfg, hidden=16, layers=2)
+        orc.set_pn_order(0)
+        r = orc.scan(od, mc, tc, q=q, K=4, kernel=orc.K_DIRICHLET, wf=orc.WF_SURROGATE)
+        assert np.all(np.abs(r["mismatch"][:3]) < 1e-12), r["mismatch"]
+        assert not np.any(r["flags"][:3] & orc.F_SURROGATE_FALLBACK)
+        orc.set_pn_order(7)
+        r7 = orc.scan(od, mc, tc, q=q, K=4, kernel=orc.K_DIRICHLET, wf=orc.WF_SURROGATE)
+        assert np.all(r7["mismatch"][:3] > 1e-4)
+        assert np.all(r7["flags"][:3] & orc.F_SURROGATE_FALLBACK)
+        for res in (r, r7):
+            assert res["mismatch"][3] == 0.0
+            assert not (res["flags"][3] & orc.F_SURROGATE_FALLBACK)
+            assert res["flags"][3] & orc.F_TAU_NONPOSITIVE
+    finally:
+        orc.set_pn_order(7)
