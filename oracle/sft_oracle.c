@@ -524,6 +524,11 @@ static void orc_template_sum(const orc_data *D, const orc_opts *o,
       double dres = 0.5 * fddot[a] * lever * lever * T;
       if (dres > o->delta_max) fl |= ORC_F_TAYLOR_INVALID;
     }
+    /* reading R6: an SFT whose window centre lies outside [0, n/2] (instantaneous
+     * frequency below DC or above Nyquist) has no representation in the data; it
+     * contributes nothing and is flagged (the reflections of the footnote of
+     * Sec. III.C serve windows whose centre is in range and spill over an edge) */
+    if (o->K >= 0 && !(kc >= 0.0 && kc <= (double)(D->n / 2))) { fl |= ORC_F_OUT_OF_BAND; continue; }
     long jlo = -o->K, jhi = o->K;
     if (o->K < 0) { jlo = -D->n / 2; jhi = D->n / 2 - 1; }
     double complex C = 0;

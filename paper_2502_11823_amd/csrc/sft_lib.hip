@@ -357,6 +357,7 @@ struct ScanArgs {
   const double* fp;
   const double* fx;
   int32_t n_groups, n_ext, k_ext_lo, n_bins, k_lo, K;
+  int32_t k_nyq;            // n / 2: window centres outside [0, k_nyq] have no data
   double T, beta_switch, tsun, delta_max;
   const double* mc;
   const double* q;
@@ -533,6 +534,12 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
     const double kr = floor(ch.kappa + 0.5);
     const double delta = ch.kappa - kr;
     const int k0 = (int)kr;
+    if (k0 < 0 || k0 > a.k_nyq) {
+      // frequency below DC or above Nyquist: no representation in the data (its norm bins
+      // are outside the band too)
+      fl |= kFlagOOB;
+      continue;
+    }
     const int i0 = k0 - K - a.k_ext_lo;
     const bool inband = (i0 >= 0) && (i0 + 2 * K < a.n_ext);
     const Bin* rp[ND];
@@ -913,6 +920,7 @@ static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t 
   a.n_bins = d->n_bins;
   a.k_lo = d->k_lo;
   a.K = o->K;
+  a.k_nyq = d->n / 2;
   a.T = d->T;
   // the FRESNEL kernel uses the Dirichlet limit only at beta == 0
   a.beta_switch = o->kernel == SFT_KERNEL_AUTO ? o->beta_switch : 0.0;

@@ -704,9 +704,10 @@ extern "C" sft_status sft_surrogate_train(sft_surrogate* s, const float* u, cons
 extern "C" sft_status sft_surrogate_infer(const sft_surrogate* s, const double* u, int64_t n, double* y, double* dy,
                                           void* hip_stream)
 {
-  if (!s || !u || !y || !dy) return mlp_fail(SFT_E_INVALID, "sft_surrogate_infer: null argument");
+  if (!s) return mlp_fail(SFT_E_INVALID, "sft_surrogate_infer: null network");
   if (n < 0) return mlp_fail(SFT_E_INVALID, "sft_surrogate_infer: negative n");
   if (n == 0) return SFT_OK;
+  if (!u || !y || !dy) return mlp_fail(SFT_E_INVALID, "sft_surrogate_infer: null argument");
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t chunk = std::min<int64_t>(n, 1 << 16);
   void* ws = nullptr;

@@ -54,6 +54,11 @@ def compare(g, o, idx=None, tol_z=1e-6, tol_rho=1e-5, tol_hh=1e-6, label="", noi
     er = np.abs(g["rho"] - o["rho"]) / np.maximum(o["rho"], 1.0)
     print("%s: n=%d max e(z+)=%.3e e(zx)=%.3e e(hh)=%.3e e(rho)=%.3e ties=%d"
           % (label, len(ok), ep[ok].max(), ex[ok].max(), eh[ok].max(), er[ok].max(), n_tie))
+    w = int(np.argmax(np.where(ok, np.maximum(ep, er), -1.0)))
+    if max(ep[w], er[w]) > tol_z:
+        print("  worst template %d: flags gpu %d orc %d, z+ gpu %r orc %r, hh+ gpu %r orc %r, rho gpu %r orc %r"
+              % (w, g["flags"][w], o["flags"][w], g["zp"][w], o["zp"][w], g["hhp"][w], o["hhp"][w],
+                 g["rho"][w], o["rho"][w]))
     assert np.array_equal(g["flags"][ok], o["flags"][ok]), (g["flags"][ok], o["flags"][ok])
     assert ep[ok].max() <= tol_z
     assert ex[ok].max() <= tol_z

@@ -239,6 +239,62 @@ def test_surrogate_scan_all_accepted_and_inner_product(tiny_q):
     s.close()
 
 
+def test_surrogate_scan_ragged_ranges_coalescence_and_bf16_weights():
+    """Per-template SFT ranges, templates that coalesce inside the data (their later SFTs are
+    skipped and flagged, and carry no judge weight), and the BF16-rounded network."""
+    w = synth.tiny(seed=4, n_templates=1, n_sft=96, noise_series=False)
+    g = synth.rng(12)
+    n = 200
+    bank = synth.uniform_bank(n, 1.19, 1.21, 0.0, 31, q_lo=1.0, q_hi=2.0, random_phase=True, n_sft=w.n_sft)
+    bank["t_c"] = g.uniform(2000.0, 7000.0, n)          # data span 6144 s: many coalesce inside
+    af = g.integers(0, 60, n)
+    bank["a_first"] = af.astype(np.int32)
+    bank["a_last"] = (af + g.integers(0, 40, n)).astype(np.int32)
+    hidden, layers = 64, 3
+    par = synth.mlp_init(29, hidden, layers)
+    cfg = dict(CFG, lt_lo=float(np.log(10.0)), lt_hi=float(np.log(8000.0)), c_phi=0.05, judge_tol=2.0)
+    kw = dict(K=4, kernel="dirichlet", waveform="surrogate")
+    data = sft.SFTData.from_workload(w, storage="f64")
+    for bf16 in (0, 1):
+        ref = bf16_round(par) if bf16 else par
+        oracle.set_surrogate(ref, cfg, hidden, layers)
+        o0 = orc_scan(w, bank, **kw)
+        tol = _judge_split(o0["mismatch"][o0["mismatch"] > 0], 0.3)
+        cfg_t = dict(cfg, judge_tol=tol)
+        oracle.set_surrogate(ref, cfg_t, hidden, layers)
+        o = orc_scan(w, bank, **kw)
+        s = make_surrogate(par, hidden, layers, tol=tol, bf16=bf16, cfg=cfg_t)
+        gr = gpu_scan(data, bank, mismatch=True, precision="fp64", surrogate=s, **kw)
+        ntau = int(np.sum(o["flags"] & oracle.F_TAU_NONPOSITIVE > 0))
+        nfb = int(np.sum(o["flags"] & oracle.F_SURROGATE_FALLBACK > 0))
+        print("ragged bf16=%d: %d templates with SFTs after coalescence, %d fallbacks" % (bf16, ntau, nfb))
+        assert ntau > 10 and 0 < nfb < n
+        assert np.max(np.abs(gr["mismatch"] - o["mismatch"])) < 1e-10
+        e = np.abs(gr["zp"] - o["zp"]) / np.maximum(np.abs(o["zp"]), np.sqrt(np.maximum(o["hhp"], 1e-300)))
+        for m in np.argsort(-e)[:3]:
+            print("  e=%.2e template %d: mc %.5f q %.3f t_c %.1f sfts %d..%d flags %d mismatch %.3e"
+                  % (e[m], m, bank["mc"][m], bank["q"][m], bank["t_c"][m], bank["a_first"][m], bank["a_last"][m],
+                     o["flags"][m], o["mismatch"][m]))
+        compare(gr, o, label="surrogate ragged bf16=%d" % bf16)
+        s.close()
+
+
+def test_surrogate_empty_calls():
+    s = make_surrogate(synth.mlp_init(2, 32, 2), 32, 2)
+    y, dy = s.infer(torch.empty((0, 3), dtype=torch.float64, device="cuda"))
+    assert y.shape == (0, 2)
+    w = synth.tiny(seed=1, n_templates=1, n_sft=8, noise_series=False)
+    data = sft.SFTData.from_workload(w, storage="f32")
+    empty = {k: v[:0] for k, v in w.bank.items()}
+    g = gpu_scan(data, empty, K=4, kernel="dirichlet", waveform="surrogate", surrogate=s)
+    assert g["rho"].size == 0
+    with pytest.raises(sft.SFTError):   # the surrogate waveform is not captured into graphs
+        sft.Plan(data, sft.bank_to_device(w.bank), sft.make_opts(waveform="surrogate", surrogate=s))
+    with pytest.raises(sft.SFTError):   # nor autotuned
+        sft.autotune(data, sft.bank_to_device(w.bank), sft.make_opts(waveform="surrogate", surrogate=s))
+    s.close()
+
+
 def test_surrogate_scan_batches_and_multidetector():
     """Several surrogate batches (more than 2^23 / groups templates) on three-detector data
     with gaps; checked on a sample of templates."""
