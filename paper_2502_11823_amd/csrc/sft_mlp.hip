@@ -277,9 +277,15 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 // FMAs, the latter with a reduction over the four lane groups.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// SiLU and its derivative times the tangent, FP64.  The sigmoid's reciprocal is the
+// hardware FP64 estimate refined by two Newton steps (within an ulp of the quotient); the
+// exponent is capped so that 1 + e^-z stays finite.
 __device__ inline void silu_tangent(double z, double zt, double& h, double& t)
 {
-  const double s = 1.0 / (1.0 + exp(-z));
+  const double d = 1.0 + exp(fmin(-z, 700.0));
+  double s = __builtin_amdgcn_rcp(d);
+  s = fma(s, fma(-d, s, 1.0), s);
+  s = fma(s, fma(-d, s, 1.0), s);
   h = z * s;
   t = s * (1.0 + z * (1.0 - s)) * zt;
 }
