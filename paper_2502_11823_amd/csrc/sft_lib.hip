@@ -610,6 +610,9 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       float smr[ND], smi[ND], spr[ND], spi[ND], ssr[ND], ssi[ND];
 #pragma unroll
       for (int d = 0; d < ND; ++d) smr[d] = smi[d] = spr[d] = spi[d] = ssr[d] = ssi[d] = 0.f;
+      // E-+ / 2 pi with the imaginary parts of the beta < 0 mirror
+      const float eqr = kInvTwoPiF * emr, eqy = kInvTwoPiF * (neg ? -emi : emi);
+      const float fqr = kInvTwoPiF * epr, fqy = kInvTwoPiF * (neg ? -epi : epi);
       auto run = [&](auto negc, auto checked) {
         constexpr bool NEG = decltype(negc)::value;
         constexpr bool CHK = decltype(checked)::value;
@@ -639,6 +642,21 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
             hre = sg * (cr + sr);
             him = NEG ? -sg * (cr - sr) : sg * (cr - sr);
           }
+          if constexpr (ND >= 2) {
+            // several rows share the weights: form the bin's complex weight once,
+            // H = (E- e(p-) - E+ e(p+)) / 2 pi + stationary term, then one complex MAC per row
+            const float hr = (eqr * em.x - eqy * emy) - (fqr * ep.x - fqy * epy) + hre;
+            const float hi = (eqr * emy + eqy * em.x) - (fqr * epy + fqy * ep.x) + him;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+              if (rows[d] < 0) continue;
+              float bre, bim;
+              BinIO<Bin>::load(rp[d] + idx, bre, bim);
+              cre[d] = fmaf(bre, hr, fmaf(-bim, hi, cre[d]));
+              cim[d] = fmaf(bre, hi, fmaf(bim, hr, cim[d]));
+            }
+            continue;
+          }
 #pragma unroll
           for (int d = 0; d < ND; ++d) {
             if (rows[d] < 0) continue;
@@ -662,11 +680,10 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
         if (neg) run(std::true_type{}, std::true_type{});
         else run(std::false_type{}, std::true_type{});
       }
-      const float emy = neg ? -emi : emi, epy = neg ? -epi : epi;
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        cre[d] = fmaf(kInvTwoPiF, (emr * smr[d] - emy * smi[d]) - (epr * spr[d] - epy * spi[d]), ssr[d]);
-        cim[d] = fmaf(kInvTwoPiF, (emr * smi[d] + emy * smr[d]) - (epr * spi[d] + epy * spr[d]), ssi[d]);
+      if constexpr (ND == 1) {
+        // one row: the bins accumulated b e(p-) and b e(p+); apply the phasors once
+        cre[0] = (eqr * smr[0] - eqy * smi[0]) - (fqr * spr[0] - fqy * spi[0]) + ssr[0];
+        cim[0] = (eqr * smi[0] + eqy * smr[0]) - (fqr * spi[0] + fqy * spr[0]) + ssi[0];
       }
     }
     // term_d = (-1)^{k0} A exp(i phi) C_d

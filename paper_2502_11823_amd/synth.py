@@ -212,3 +212,29 @@ def surrogate_samples(n: int, seed: int, mc_lo: float, mc_hi: float, q_lo: float
     q = g.uniform(q_lo, q_hi, n)
     tau = np.exp(g.uniform(np.log(tau_lo), np.log(tau_hi), n))
     return mc, q, tau
+
+
+def paper_shape(name: str, seed: int = 5, n_templates: int = 1000) -> Workload:
+    """Context workloads shaped like the paper's timing runs (Sec. V.C): one detector, white
+    noise drawn in the SFT domain (unit PSD), every bin of each SFT stored, and a bank of
+    templates whose chirp mass lies within 0.5% of the nominal system; t_c puts the end of
+    the data where the nominal chirp reaches its upper frequency.
+      * ``bns``  : 1.4 + 1.4 Msun, 1 -> 10 Hz, fs = 40 Hz, 6384 SFTs of 73 s, K = 50.
+      * ``mbbh`` : 1e6 + 1e6 Msun, 1e-4 -> 1.9e-3 Hz, fs = 2 Hz, 1540 SFTs of 2502 s, K = 15."""
+    if name == "bns":
+        fs, t_sft, n_sft, m1, f_hi, K = 40.0, 73.0, 6384, 1.4, 10.0, 50
+    elif name == "mbbh":
+        fs, t_sft, n_sft, m1, f_hi, K = 2.0, 2502.0, 1540, 1.0e6, 1.9e-3, 15
+    else:
+        raise ValueError(name)
+    n = int(round(fs * t_sft))
+    mc0 = (m1 * m1) ** 0.6 / (2.0 * m1) ** 0.2
+    M = mc0 * 4.925490947641267e-6
+    tau_end = 5.0 * M * (8.0 * np.pi * M * f_hi) ** (-8.0 / 3.0)   # leading-order time to coalescence
+    t_start = np.arange(n_sft) * t_sft
+    psd = np.ones((n_sft, n // 2 + 1))
+    xb = sft_domain_noise(psd, t_sft, seed + 17)
+    bank = uniform_bank(n_templates, 0.995 * mc0, 1.005 * mc0, n_sft * t_sft + tau_end, seed + 1000, n_sft=n_sft)
+    return Workload("paper-" + name, t_start, np.zeros(n_sft, np.int32), n, t_sft, 0, xb, psd, None, None,
+                    bank, dict(K=K, kernel="auto", precision="fp32_kahan"))
+
