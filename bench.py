@@ -26,9 +26,12 @@ if ROOT not in sys.path:
 METRIC = "template inner products/s at ≤1e-6 rel err; surrogate+FP32 vs plain path"
 
 # --------------------------------------------------------------------------------------
-# Algorithmic VALU work of the scan, in lane-operation slots: an FP32/FP64 add, mul or
-# FMA = 1 slot, a transcendental (v_rcp, v_rsq, v_log, v_exp) = 4 slots (quarter rate);
-# compares, selects, conversions of loop indices and address arithmetic are not counted.
+# Algorithmic VALU work of the scan, in lane operations: every FP32/FP64 add, mul or FMA and
+# every transcendental (rcp, rsqrt, log, exp) of the formulas counts once; compares, selects,
+# conversions of loop indices and address arithmetic are not counted.  (An issue-rate probe on
+# the MI355X: FMA/MUL streams sustain 0.97 wave-instructions per clock per CU, a v_rcp_f32
+# interleaved with FMAs takes ~1.7 issue slots, and 32-bit integer instructions issue beside
+# the floating-point ones; the peak below is the FP32 VALU issue rate.)
 # Counted from the formulas the kernel evaluates (Fresnel kernel, asymptotic endpoint
 # branch, which is the dominant one):
 #   per (template, timestamp group), shared by the detectors of the group:
@@ -52,7 +55,7 @@ METRIC = "template inner products/s at ≤1e-6 rel err; surrogate+FP32 vs plain 
 # The Dirichlet kernel replaces the Fresnel set-up by sin(pi delta) (22) and the per-bin
 # group work by x = delta - j and x^-1 (1 + T), and the per-row MACs by 2 FMAs.
 # --------------------------------------------------------------------------------------
-SLOT_T = 4
+SLOT_T = 1
 
 
 def alg_slots(K: int, kernel: str, n_groups: int, n_rows: int, nd: int = 1) -> float:
@@ -231,10 +234,10 @@ def main():
                                "FP64 phase + FP32 Kahan sums" % (w.n_sft, w.n_bins, w.n_templates, K, kernel),
                    "n_templates": w.n_templates, "n_sft": w.n_sft, "K": K, "kernel": kernel,
                    "precision": "fp32_kahan", "storage": "f32"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
                      "frac": achieved / peak, "traffic": measured_traffic(),
                      "kernel": "scan_kernel", "kernel_ms": k_ms,
-                     "alg_slots_per_template": slots / w.n_templates,
+                     "alg_lane_ops_per_template": slots / w.n_templates,
                      "units": {"templates": w.n_templates, "timestamp_groups": n_groups, "sft_rows": w.n_sft}},
         "tuning": best.as_dict(),
         "graph_ms_per_step": graph_ms,
@@ -288,9 +291,9 @@ def space_leg(args):
                         % (w.n_templates, K),
             "value": w.n_templates * args.steps / elapsed, "unit": "IP/s", "ms_per_step": 1e3 * elapsed / args.steps,
             "template_sfts": float(np.sum(n_use)),
-            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tlane-op/s",
                          "frac": achieved / (PEAK_SLOTS / 1e12), "kernel": "scan_kernel", "kernel_ms": k_ms,
-                         "alg_slots_per_template_sft": alg_slots(K, "fresnel", 1, 1)},
+                         "alg_lane_ops_per_template_sft": alg_slots(K, "fresnel", 1, 1)},
             "tuning": best.as_dict(), "flagged_templates": int(np.sum(flags != 0))}
 
 

@@ -544,6 +544,9 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
     const bool inband = (i0 >= 0) && (i0 + 2 * K < a.n_ext);
     const Bin* rp[ND];
 #pragma unroll
+    // an absent row of the group reads row 0 instead: its contraction is computed (keeping the
+    // bin loop free of per-row branches, so the loads of all rows are issued together) and
+    // never accumulated
     for (int d = 0; d < ND; ++d) rp[d] = bins + (int64_t)(rows[d] >= 0 ? rows[d] : 0) * a.n_ext;
 
     R cre[ND], cim[ND];
@@ -575,7 +578,6 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
         else h = (x == (R)0) ? (R)1 : (R)(sp * fast_rcp((float)x));
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-          if (rows[d] < 0) continue;
           R bre, bim;
           BinIO<Bin>::load(rp[d] + idx, bre, bim);
           cre[d] = fma(bre, h, cre[d]);
@@ -649,8 +651,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
             const float hi = (eqr * emy + eqy * em.x) - (fqr * epy + fqy * ep.x) + him;
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
-              if (rows[d] < 0) continue;
-              float bre, bim;
+                  float bre, bim;
               BinIO<Bin>::load(rp[d] + idx, bre, bim);
               cre[d] = fmaf(bre, hr, fmaf(-bim, hi, cre[d]));
               cim[d] = fmaf(bre, hi, fmaf(bim, hr, cim[d]));
@@ -659,8 +660,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
           }
 #pragma unroll
           for (int d = 0; d < ND; ++d) {
-            if (rows[d] < 0) continue;
-            float bre, bim;
+              float bre, bim;
             BinIO<Bin>::load(rp[d] + idx, bre, bim);
             smr[d] = fmaf(bre, em.x, fmaf(-bim, emy, smr[d]));
             smi[d] = fmaf(bre, emy, fmaf(bim, em.x, smi[d]));
