@@ -248,17 +248,21 @@ __device__ inline void phasor(double phi, float& s, float& c)
 //   fs = 1 - 3 W + 105 W^2 - 10395 W^3,  gs = 1 - 15 W + 945 W^2 - 135135 W^3,  W = w^2.
 // Below, G(v) from the LDS table (interval width 1/2, Horner in v - centre), scaled
 // by tsc = 2 pi / sqrt(2 beta).  bq = beta / (2 pi).
+// the asymptotic form alone (valid for v = |p| sqrt(2/beta) >= SFT_G_VASYM)
+__device__ inline float2 fres_endpoint_asym(float p, float bq)
+{
+  const float r = __builtin_amdgcn_rcpf(p);
+  const float w = bq * (r * r);
+  const float W = w * w;
+  const float fs = fmaf(W, fmaf(W, fmaf(W, -10395.0f, 105.0f), -3.0f), 1.0f);
+  const float gs = fmaf(W, fmaf(W, fmaf(W, -135135.0f, 945.0f), -15.0f), 1.0f);
+  return make_float2((r * w) * gs, r * fs);
+}
+
 __device__ inline float2 fres_endpoint2(float p, float bq, float sq2ob, float tsc, const float2* tab)
 {
   const float v = fabsf(p) * sq2ob;
-  if (v >= SFT_G_VASYM) {
-    const float r = __builtin_amdgcn_rcpf(p);
-    const float w = bq * (r * r);
-    const float W = w * w;
-    const float fs = fmaf(W, fmaf(W, fmaf(W, -10395.0f, 105.0f), -3.0f), 1.0f);
-    const float gs = fmaf(W, fmaf(W, fmaf(W, -135135.0f, 945.0f), -15.0f), 1.0f);
-    return make_float2((r * w) * gs, r * fs);
-  }
+  if (v >= SFT_G_VASYM) return fres_endpoint_asym(p, bq);
   int i = (int)(v * (1.0f / SFT_G_WIDTH));
   i = i < SFT_G_NINT - 1 ? i : SFT_G_NINT - 1;
   i = i > 0 ? i : 0;

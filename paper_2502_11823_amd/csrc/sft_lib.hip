@@ -381,6 +381,11 @@ enum { KERN_DIRICHLET = 0, KERN_FRESNEL = 1 };
 // surrogate path fills it); an internal value, never accepted from the caller
 enum { WF_NEWTON = SFT_WF_NEWTON, WF_PN35 = SFT_WF_PN35, WF_TABLE = 100 };
 
+// smallest window half-width for which the Fresnel loop separates the outer bins
+#ifndef SFT_OUTER_MIN_K
+#define SFT_OUTER_MIN_K 4
+#endif
+
 // unroll factor of the bin loops (4 keeps the Fresnel kernel at 5 waves per SIMD)
 #ifndef SFT_BIN_UNROLL
 #define SFT_BIN_UNROLL 4
@@ -415,6 +420,31 @@ template <> struct PrecTraits<SFT_PREC_FP32_KAHAN> { using R = float; using Acc 
 template <> struct PrecTraits<SFT_PREC_FP32_NAIVE> { using R = float; using Acc = AccNaive; };
 
 __device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Order of the window bins in the FP32 contraction.  Wide windows (K >= SFT_WIDE_K) go from
+// the outside in (-K, K, -K+1, K-1, ..., 0), so that the running sum stays small until the
+// dominant central bins arrive and the rounding of the many small far-bin terms is not taken
+// against the full sum; narrow windows go left to right (same accuracy at that length, and
+// faster: consecutive bins share the loads' address arithmetic).
+#ifndef SFT_WIDE_K
+#define SFT_WIDE_K 16
+#endif
+__device__ inline int bin_order(int t, int K)
+{
+  return K >= SFT_WIDE_K ? ((t & 1) ? K - (t >> 1) : (t >> 1) - K) : t - K;
+}
+
+// Largest x over the active lanes of the wavefront, for x in [lo, hi] (wave-uniform bounds):
+// a binary search on lane votes (a compare's lane mask holds bits of active lanes only).
+__device__ inline int wave_max_active(int x, int lo, int hi)
+{
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (__ballot(x >= mid)) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // One lane per template, one grid row per chunk of timestamp groups.  The SFT rows of
 // a group (one per detector) share the SFT midpoint, hence the chirp, the window and
@@ -566,7 +596,8 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
         sp = s_ * kInvPiF;
       }
 #pragma unroll SFT_BIN_UNROLL
-      for (int j = -K; j <= K; ++j) {
+      for (int t = 0; t <= 2 * K; ++t) {
+        const int j = bin_order(t, K);
         const int idx = i0 + j + K;
         if (!inband && (idx < 0 || idx >= a.n_ext)) {
           fl |= kFlagOOB;
@@ -612,6 +643,20 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       float smr[ND], smi[ND], spr[ND], spi[ND], ssr[ND], ssi[ND];
 #pragma unroll
       for (int d = 0; d < ND; ++d) smr[d] = smi[d] = spr[d] = spi[d] = ssr[d] = ssi[d] = 0.f;
+      // Outer bins: jj >= jup or jj <= jdn puts both endpoints of a lane at least one bin
+      // beyond the asymptotic threshold |p| = SFT_G_VASYM sqrt(beta / 2), with no stationary
+      // point inside the SFT (p- and p+ of one sign).  With the bounds taken over the active
+      // lanes of the wavefront, those bins take the asymptotic form directly, without the
+      // per-lane range test.  Lane bounds are clamped to the window, [-K-1, K+1].
+      // Used for windows of SFT_OUTER_MIN_K bins or more a side (jup > K and jdn < -K disable it).
+      int jup = K + 1, jdn = -K - 1;
+      if (K >= SFT_OUTER_MIN_K) {
+        const float pa = SFT_G_VASYM * (bp * isq2b);   // sqrt(beta / 2) = beta / sqrt(2 beta)
+        const float fup = fminf(fmaxf(ceilf(dp + pa) + 1.0f, (float)(-K - 1)), (float)(K + 1));
+        const float fdn = fminf(fmaxf(floorf(dm - pa) - 1.0f, (float)(-K - 1)), (float)(K + 1));
+        jup = wave_max_active((int)fup, -K - 1, K + 1);
+        jdn = -wave_max_active(-(int)fdn, -K - 1, K + 1);
+      }
       // E-+ / 2 pi with the imaginary parts of the beta < 0 mirror
       const float eqr = kInvTwoPiF * emr, eqy = kInvTwoPiF * (neg ? -emi : emi);
       const float fqr = kInvTwoPiF * epr, fqy = kInvTwoPiF * (neg ? -epi : epi);
@@ -619,7 +664,8 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
         constexpr bool NEG = decltype(negc)::value;
         constexpr bool CHK = decltype(checked)::value;
 #pragma unroll SFT_BIN_UNROLL
-        for (int j = -K; j <= K; ++j) {
+        for (int t = 0; t <= 2 * K; ++t) {
+          const int j = bin_order(t, K);
           const int idx = i0 + j + K;
           if constexpr (CHK) {
             if (idx < 0 || idx >= a.n_ext) {
@@ -629,6 +675,30 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
           }
           const int jj = NEG ? -j : j;
           const float pm = dm - (float)jj, pp = dp - (float)jj;
+          if (jj >= jup || jj <= jdn) {
+            const float2 em = fres_endpoint_asym(pm, bq);
+            const float2 ep = fres_endpoint_asym(pp, bq);
+            const float emy = NEG ? -em.y : em.y, epy = NEG ? -ep.y : ep.y;
+            if constexpr (ND >= 2) {
+              const float hr = (eqr * em.x - eqy * emy) - (fqr * ep.x - fqy * epy);
+              const float hi = (eqr * emy + eqy * em.x) - (fqr * epy + fqy * ep.x);
+#pragma unroll
+              for (int d = 0; d < ND; ++d) {
+                float bre, bim;
+                BinIO<Bin>::load(rp[d] + idx, bre, bim);
+                cre[d] = fmaf(bre, hr, fmaf(-bim, hi, cre[d]));
+                cim[d] = fmaf(bre, hi, fmaf(bim, hr, cim[d]));
+              }
+            } else {
+              float bre, bim;
+              BinIO<Bin>::load(rp[0] + idx, bre, bim);
+              smr[0] = fmaf(bre, em.x, fmaf(-bim, emy, smr[0]));
+              smi[0] = fmaf(bre, emy, fmaf(bim, em.x, smi[0]));
+              spr[0] = fmaf(bre, ep.x, fmaf(-bim, epy, spr[0]));
+              spi[0] = fmaf(bre, epy, fmaf(bim, ep.x, spi[0]));
+            }
+            continue;
+          }
           const float2 em = fres_endpoint2(pm, bq, sq2ob, tsc, tab);
           const float2 ep = fres_endpoint2(pp, bq, sq2ob, tsc, tab);
           const float emy = NEG ? -em.y : em.y, epy = NEG ? -ep.y : ep.y;

@@ -340,3 +340,20 @@ def test_pn35_fp64_tiny(tiny):
     kw = dict(K=4, kernel="dirichlet", precision="fp64", waveform="pn35")
     e = compare(gpu_scan(data, bank, **kw), orc_scan(tiny, bank, **kw), label="pn35 tiny fp64")
     assert e < 1e-8
+
+
+# ----------------------------------------------------------------------------- paper-shaped banks
+@pytest.mark.parametrize("name", ["bns", "mbbh"])
+def test_paper_shaped_banks_sampled(name):
+    """Banks shaped like the paper's timing runs: BNS (6384 SFTs of 73 s, K = 50, drift up to
+    a few bins near 10 Hz) and MBBH (1540 SFTs of 2502 s, K = 15, windows centred a quarter bin
+    above DC so that most bins reflect through DC).  Full bank on the GPU, a seeded sample of
+    templates against the oracle."""
+    w = synth.paper_shape(name, n_templates=1000)
+    K = int(w.opts["K"])
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=K, kernel="auto", precision="fp32_kahan")
+    g = gpu_scan(data, w.bank, **kw)
+    idx = np.sort(synth.rng(21).choice(w.n_templates, 24, replace=False))
+    o = orc_scan(w, w.subset(idx), **kw)
+    compare(g, o, idx=idx, label="paper-shaped " + name)
