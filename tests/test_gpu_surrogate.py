@@ -359,3 +359,30 @@ def test_trained_surrogate_recovers_pn35_signal():
     assert rho_newton < 0.8 * rho_pn
     assert mm < 1e-2
     s.close()
+
+
+def test_surrogate_full_size_bank_sampled():
+    """The benchmark's surrogate configuration at full size: tiny data, 1e6 templates with
+    Mc ~ U[1.19, 1.21], q ~ U[1, 2], network 3 -> 128 x 4 -> 2 (seeded, not trained), FP32
+    Kahan sums, 31 template batches in one scan; a seeded sample (batch edges included) against
+    the oracle."""
+    w = synth.tiny(seed=1, n_templates=1, noise_series=False)
+    n = 1_000_000
+    bank = synth.uniform_bank(n, 1.19, 1.21, 16984.0, 501, q_lo=1.0, q_hi=2.0, random_phase=True,
+                              n_sft=w.n_sft)
+    hidden, layers = 128, 4
+    par = synth.mlp_init(23, hidden, layers)
+    cfg = dict(CFG, c_phi=0.05, judge_tol=2.0)
+    s = make_surrogate(par, hidden, layers, tol=2.0, cfg=cfg)
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=4, kernel="dirichlet", waveform="surrogate")
+    g = gpu_scan(data, bank, mismatch=True, precision="fp32_kahan", surrogate=s, **kw)
+    idx = np.sort(synth.rng(44).choice(n, 14, replace=False))
+    idx = np.unique(np.concatenate([idx, [0, 32767, 32768, n - 1]]))
+    sub = {k: np.ascontiguousarray(v[idx]) for k, v in bank.items()}
+    oracle.set_surrogate(par, cfg, hidden, layers)
+    o = orc_scan(w, sub, **kw)
+    assert np.max(np.abs(g["mismatch"][idx] - o["mismatch"])) < 1e-10
+    assert not np.any(g["flags"] & sft.FLAG_SURROGATE_FALLBACK)
+    compare(g, o, idx=idx, label="surrogate full size")
+    s.close()
