@@ -60,7 +60,9 @@ enum { SFT_WF_NEWTON = 0, SFT_WF_PN35 = 1, SFT_WF_SURROGATE = 2 };
 
 /* per-template flag bits */
 enum {
-  SFT_FLAG_OUT_OF_BAND = 1u,      /* a window bin, or a PSD bin of the norm, lies outside the stored band */
+  SFT_FLAG_OUT_OF_BAND = 1u,      /* a window bin, or a PSD bin of the norm, lies outside the stored band,
+                                     or a window centre lies below DC or above Nyquist (that SFT
+                                     then contributes nothing) */
   SFT_FLAG_TAU_NONPOSITIVE = 2u,  /* an SFT of the template's range starts its midpoint at or after t_c; skipped */
   SFT_FLAG_TAYLOR_INVALID = 4u,   /* fddot T^3 / 8 > delta_max in some SFT (Eq. max_tsft, midpoint lever arm) */
   SFT_FLAG_NONFINITE = 8u,        /* an output is not finite */
@@ -166,6 +168,10 @@ typedef struct {
  * about 56 bytes per template and SFT chunk is taken from the stream-ordered
  * allocator and returned on the same stream.  Results are bitwise deterministic
  * for a given bank, data and options.  n_templates == 0 is a no-op.
+ * With SFT_WF_SURROGATE the scan runs in template batches of about
+ * 2^23 / (timestamp groups) templates, each with a workspace of about 1 GiB (network
+ * inputs and outputs, the chirp table) on the same stream; the network must not be
+ * trained or freed while such a scan is in flight.
  * Errors: SFT_E_INVALID (null pointers), SFT_E_RANGE (K), SFT_E_UNSUPPORTED
  * (precision/storage or kernel combinations), SFT_E_NOMEM, SFT_E_DEVICE.
  */
@@ -270,6 +276,8 @@ int64_t sft_surrogate_param_count(int32_t hidden, int32_t layers);
  * [sft_surrogate_param_count] (copied).  Errors: SFT_E_INVALID (null pointer, empty
  * ranges, zero scales), SFT_E_RANGE (hidden, layers), SFT_E_NOMEM, SFT_E_DEVICE. */
 sft_status sft_surrogate_create(const sft_surrogate_desc* desc, const float* params, sft_surrogate** out);
+/* Release a network (NULL is a no-op).  Calls on one network are not thread-safe, and a
+ * network must outlive the scans and training calls enqueued with it. */
 void sft_surrogate_free(sft_surrogate* s);
 /* Copy the current FP32 parameters to host memory (synchronous). */
 sft_status sft_surrogate_get_params(const sft_surrogate* s, float* params);
