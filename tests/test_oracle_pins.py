@@ -256,6 +256,30 @@ def test_p8_invariants(orc, small_ground):
     assert np.array_equal(rp["zp"], r0["zp"][p]) and np.array_equal(rp["rho"], r0["rho"][p])
 
 
+def test_p8b_window_beyond_nyquist_contributes_nothing(orc):
+    """P8b (Eq. efficient; reading R6): an SFT whose window centre lies beyond the Nyquist
+    bin adds nothing to z or <h,h> and raises the out-of-band flag, so a template chirping
+    past n/2 equals the same template cut at its last in-band SFT, bit for bit."""
+    w = synth.tiny(seed=2, n_templates=1, n_sft=24, noise_series=False)
+    data = orc.SFTData(w.t_start, w.n_samples, w.t_sft, w.k_lo, w.x_bins, w.psd)
+    T = w.t_sft
+    m = 1.2 * orc.T_SUN
+    tau_nyq = 5 * m * (8 * np.pi * m * 16.0) ** (-8 / 3)   # Newtonian time to reach 16 Hz
+    tc = w.t_start[-1] + 0.5 * T + 0.5 * tau_nyq
+    mid = w.t_start + 0.5 * T
+    f_mid = (5 * m / (tc - mid)) ** (3 / 8) / (8 * np.pi * m)
+    inband = np.nonzero(np.floor(f_mid * T + 0.5) <= w.n_samples // 2)[0]
+    last = int(inband[-1])
+    assert 0 < last < w.n_sft - 2 and np.array_equal(inband, np.arange(last + 1))
+    kw = dict(K=6, kernel=orc.K_AUTO)
+    full = orc.scan(data, [1.2, 1.2], [tc, tc + 5000.0], **kw)
+    cut = orc.scan(data, [1.2], [tc], a_last=[last], **kw)
+    assert full["flags"][0] & orc.F_OUT_OF_BAND and full["flags"][1] == 0
+    assert cut["flags"][0] == 0
+    for key in ("zp", "zx", "hhp", "hhx", "rho"):
+        assert full[key][0] == cut[key][0], key
+
+
 # --------------------------------------------------------------------------- P9
 def test_p9_sft_length_tables(orc):
     """P9 (Eq. max_tsft, Tables 1 and 2)."""
