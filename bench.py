@@ -26,55 +26,118 @@ if ROOT not in sys.path:
 METRIC = "template inner products/s at ≤1e-6 rel err; surrogate+FP32 vs plain path"
 
 # --------------------------------------------------------------------------------------
-# Algorithmic VALU work of the scan, in lane operations: every FP32/FP64 add, mul or FMA and
-# every transcendental (rcp, rsqrt, log, exp) of the formulas counts once; compares, selects,
-# conversions of loop indices and address arithmetic are not counted.  (An issue-rate probe on
-# the MI355X: FMA/MUL streams sustain 0.97 wave-instructions per clock per CU, a v_rcp_f32
-# interleaved with FMAs takes ~1.7 issue slots, and 32-bit integer instructions issue beside
-# the floating-point ones; the peak below is the FP32 VALU issue rate.)
-# Counted from the formulas the kernel evaluates (Fresnel kernel, asymptotic endpoint
-# branch, which is the dominant one):
-#   per (template, timestamp group), shared by the detectors of the group:
-#     FP64 chirp at the SFT midpoint (tau, y, s = y^(-1/8) from log2/exp2 and two
-#       Newton steps, kappa, phase, A, beta, Taylor residual)          34 + 2 T
-#     window split kappa -> k0, delta                                    4
-#     Fresnel set-up: 1/sqrt(beta), scales, endpoint offsets, the two
-#       phasors exp(i pi beta/4), exp(i pi delta), E-+, 1/beta (FP64)   63 + 2 T
-#     per bin: p-+ (2) and two endpoint terms (|p| sqrt(2/beta), 1/p,
-#       r^2, w, w^2, two 3-FMA series, three products)                  28 + 2 T
-#     phase phasor exp(i phi) and the signed amplitude                   24
-#     norm set-up (floor, weight, A^2 T)                                  6
-#   per (template, SFT row):
-#     per bin: two complex MACs into S-, S+                              8
-#     C = (E- S- - E+ S+) / 2 pi + S_stat                                12
-#     term, projector and four Kahan-compensated sums                    26
-#     norm term A^2 T / S(f) with interpolation, two Kahan sums          18 + T
-# When a group has several detector rows (the kernel's ND >= 2) the Fresnel weights are
-# combined per bin once per group, H = (E- e(p-) - E+ e(p+)) / 2 pi + stationary term   12
-# per bin, and each row then takes one complex MAC per bin (4) and no final combination.
-# The Dirichlet kernel replaces the Fresnel set-up by sin(pi delta) (22) and the per-bin
-# group work by x = delta - j and x^-1 (1 + T), and the per-row MACs by 2 FMAs.
-# --------------------------------------------------------------------------------------
-SLOT_T = 1
+# Algorithmic VALU work of the scan, in FP32 lane-operation slots: every FP32 add, mul or FMA
+# and every transcendental (rcp, rsqrt, log2, exp2) of the formulas counts 1 and every FP64
+# add, mul or FMA counts 2 (the FP64 vector rate is half the FP32 one); compares, selects,
+# conversions, index and address arithmetic are not counted.
+# Peak: the FP32 vector rate, 157.3 TFLOP/s with an FMA as two flops, i.e. 256 CUs x 2.4 GHz
+# x 128 lanes per clock = 78.6e12 slots/s.  Packed FP32 is disabled at compile time; plain
+# wave64 FP32 instructions still issue faster than one per clock per CU: an issue-rate probe
+# with 16 independent FMA chains per lane sustains 1.37 wave-instructions per clock per CU,
+# MUL 1.46, FMA interleaved with 32-bit integer ops 1.58, of the 2.0 this peak implies.
+#
+# Per (template, timestamp group), shared by the detector rows of the group:
+OPS_CHIRP = 2 * 34 + 2      # Newtonian chirp at the SFT midpoint in FP64 (tau, y, s = y^(-1/8)
+                            # from log2/exp2 seeds and two Newton steps, kappa, phase, A, beta)
+OPS_SPLIT = 2 * 2           # kappa -> k0, delta (FP64)
+OPS_TAIL = 24 + 2 * 2 + 2 + 4 + 6 * 4
+                            # exp(i phi) (FP64 reduction + series), norm set-up (FP64 floor and
+                            # weight, A^2 T), signed amplitude, six Kahan-compensated additions
+OPS_FRESNEL = 2 * 22 + 7 + 9 + 18 + 6 * 5
+                            # exp(i pi beta/4), exp(i pi delta), 1/sqrt(beta) and scales, 1/beta
+                            # (FP64 Newton), E-+, E-/2pi, E+/2pi and rho = E+/E-, and the six
+                            # wave-uniform series-tier bounds
+OPS_DIRICHLET = 23          # sin(pi delta) / pi
+# Fresnel weights per bin and lane, by the series length the bin's endpoints need (two
+# endpoints each; p-+ = delta -+ beta/2 - j is 2): both endpoints at v = |p| sqrt(2/beta) >= 76
+# (no W term: 1/p, r^2, w, r w), >= 11 (one W term: 5 more), >= 4.5 (three W terms: 4 more),
+# else the 9-interval degree-8 table (|p|, the interval, two Horner chains, sign and scale)
+OPS_BIN = {"w0": 2 + 2 * (1 + 3), "w1": 2 + 2 * (1 + 8), "w3": 2 + 2 * (1 + 12), "table": 2 + 2 * 23 + 2}
+OPS_BIN_STAT = 2 * 3 + 2 * 3 + 16 + 5 + 6   # stationary point inside the SFT: x^2/beta and its
+                                            # reduction (FP64), the phasor, the term, folded into e(p-)
+OPS_BIN_DIR = 3                             # x = delta - j, 1/x, sin(pi delta)/pi x
+OPS_BIN_SHARED = 4                          # several rows: H' = e(p-) - rho e(p+) once per bin
+# Per (template, SFT row):
+OPS_ROW_MAC = 4             # complex MAC per bin (Fresnel); Dirichlet: 2 (real weight)
+OPS_ROW_EQ = 4              # several rows: E-/2pi applied to the row's sum
+OPS_ROW_TAIL = 4 + 4 + 3 + 1 + 1 + 2 + 2
+                            # the term, four projector products, the PSD at f interpolated,
+                            # 1/S, A^2 T/S, F+^2 and Fx^2, two norm products
+OPS_ROW1_MAC = 8            # one-row kernel: b e(p-) and b e(p+) per bin (no H'), then
+OPS_ROW1_COMB = 10          # C = E-/2pi S- - E+/2pi S+ once
+SERIES_V = (76.0, 11.0, 4.5)
+OUTER_MIN_K = 4             # narrower windows use the table for every bin
 
 
-def alg_slots(K: int, kernel: str, n_groups: int, n_rows: int, nd: int = 1) -> float:
+def scan_census(mc, t_c, g_tmid, g_rows, T, K, beta_switch, tsun, g_first=None, g_last=None, multi_row=True,
+                stride=64, chunk=256):
+    """Algorithmic slots of one scan (the counts above), from the Newtonian chirp of every
+    stride-th template at every timestamp group it uses, scaled to the whole bank.  g_rows:
+    SFT rows present per group; g_first/g_last: the template's group range (ragged banks)."""
+    mc = np.asarray(mc, np.float64)
+    n = mc.size
+    pick = np.arange(0, n, stride)
+    total = 0.0
+    census = {"pairs": 0, "w0": 0, "w1": 0, "w3": 0, "table": 0, "stat": 0, "dirichlet_pairs": 0}
     nb = 2 * K + 1
-    if kernel == "dirichlet":
-        per_group = (34 + 2 * SLOT_T) + 4 + 22 + nb * (1 + SLOT_T) + 24 + 6
-        per_row = nb * 2 + 26 + (18 + SLOT_T)
-    elif nd >= 2:
-        per_group = (34 + 2 * SLOT_T) + 4 + (63 + 2 * SLOT_T) + nb * (28 + 2 * SLOT_T + 12) + 24 + 6
-        per_row = nb * 4 + 26 + (18 + SLOT_T)
-    else:
-        per_group = (34 + 2 * SLOT_T) + 4 + (63 + 2 * SLOT_T) + nb * (28 + 2 * SLOT_T) + 24 + 6
-        per_row = nb * 8 + 12 + 26 + (18 + SLOT_T)
-    return per_group * n_groups + per_row * n_rows
+    for i0 in range(0, pick.size, chunk):
+        idx = pick[i0:i0 + chunk]
+        M = mc[idx, None] * tsun
+        tau = np.asarray(t_c, np.float64)[idx, None] - np.asarray(g_tmid, np.float64)[None, :]
+        use = tau > 0
+        if g_first is not None:
+            gi = np.arange(len(g_tmid))[None, :]
+            use &= (gi >= np.asarray(g_first)[idx, None]) & (gi <= np.asarray(g_last)[idx, None])
+        taus = np.where(use, tau, 1.0)
+        f = (5.0 * M / taus) ** 0.375 / (8.0 * np.pi * M)
+        fdot = 96.0 / 5.0 * np.pi ** (8.0 / 3.0) * M ** (5.0 / 3.0) * f ** (11.0 / 3.0)
+        kap = f * T
+        beta = fdot * T * T
+        delta = kap - np.floor(kap + 0.5)
+        rows = np.broadcast_to(np.asarray(g_rows, np.float64)[None, :], use.shape)
+        fres = use & (np.abs(beta) > beta_switch)
+        dirp = use & ~fres
+        b = np.where(fres, np.abs(beta), 1.0)
+        ds = np.where(beta < 0, -delta, delta)
+        dm, dp = ds - 0.5 * b, ds + 0.5 * b
+        s2b = np.sqrt(2.0 / b)
+        n_pairs = float(use.sum())
+        n_rows = float((rows * use).sum())
+        ops = n_pairs * (OPS_CHIRP + OPS_SPLIT + OPS_TAIL) + float(fres.sum()) * OPS_FRESNEL
+        ops += float(dirp.sum()) * (OPS_DIRICHLET + nb * OPS_BIN_DIR) + float((rows * dirp).sum()) * nb * 2
+        ops += n_rows * OPS_ROW_TAIL
+        for jj in range(-K, K + 1):
+            pm, pp = dm - jj, dp - jj
+            v = np.minimum(np.abs(pm), np.abs(pp)) * s2b
+            same = pm * pp > 0
+            if K >= OUTER_MIN_K:
+                w0 = fres & same & (v >= SERIES_V[0])
+                w1 = fres & same & (v >= SERIES_V[1]) & ~w0
+                w3 = fres & same & (v >= SERIES_V[2]) & ~w0 & ~w1
+            else:
+                w0 = w1 = w3 = np.zeros_like(fres)
+            tab = fres & ~w0 & ~w1 & ~w3
+            stat = tab & (pm < 0) & (pp >= 0)
+            for key, msk in (("w0", w0), ("w1", w1), ("w3", w3), ("table", tab)):
+                c_ = float(msk.sum())
+                census[key] += c_
+                ops += c_ * OPS_BIN[key]
+            census["stat"] += float(stat.sum())
+            ops += float(stat.sum()) * OPS_BIN_STAT
+        if multi_row:
+            ops += float(fres.sum()) * nb * OPS_BIN_SHARED + float((rows * fres).sum()) * (nb * OPS_ROW_MAC + OPS_ROW_EQ)
+        else:
+            ops += float(fres.sum()) * (nb * OPS_ROW1_MAC + OPS_ROW1_COMB)
+        census["pairs"] += n_pairs
+        census["dirichlet_pairs"] += float(dirp.sum())
+        total += ops
+    scale = n / pick.size
+    census = {k: v * scale for k, v in census.items()}
+    return total * scale, census
 
 
-# peak VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (FP32 and FP64 FMA both
-# full rate without packed FP32; = 78.6 TFLOP/s FP64 counting an FMA as 2 flops)
-PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# peak FP32 VALU rate in lane-operation slots per second (see above)
+PEAK_SLOTS = 256 * 128 * 2.4e9
 
 
 KERNEL_SOURCES = ["paper_2502_11823_amd/csrc/sft_lib.hip", "paper_2502_11823_amd/csrc/sft_device.h",
@@ -199,9 +262,10 @@ def main():
     value = w.n_templates * args.steps / elapsed
     ms_step = 1e3 * elapsed / args.steps
     k_ms = float(np.mean(ktimes)) if ktimes.size else float("nan")
-    n_groups = int(np.unique(w.t_start).size)
-    nd = int(np.max(np.unique(w.t_start, return_counts=True)[1]))   # rows per timestamp group (at most)
-    slots = w.n_templates * alg_slots(K, kernel, n_groups, w.n_sft, nd)
+    g_t, g_rows = np.unique(w.t_start, return_counts=True)
+    n_groups = int(g_t.size)
+    slots, census = scan_census(w.bank["mc"], w.bank["t_c"], g_t + 0.5 * w.t_sft, g_rows, w.t_sft, K, 1e-7,
+                                sft.T_SUN, multi_row=True)
     achieved = slots / (k_ms * 1e-3) / 1e12
     peak = PEAK_SLOTS / 1e12
 
@@ -234,11 +298,12 @@ def main():
                                "FP64 phase + FP32 Kahan sums" % (w.n_sft, w.n_bins, w.n_templates, K, kernel),
                    "n_templates": w.n_templates, "n_sft": w.n_sft, "K": K, "kernel": kernel,
                    "precision": "fp32_kahan", "storage": "f32"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
                      "frac": achieved / peak, "traffic": measured_traffic(),
                      "kernel": "scan_kernel", "kernel_ms": k_ms,
-                     "alg_lane_ops_per_template": slots / w.n_templates,
-                     "units": {"templates": w.n_templates, "timestamp_groups": n_groups, "sft_rows": w.n_sft}},
+                     "alg_slots_per_launch": slots, "alg_slots_per_template_group": slots / census["pairs"],
+                     "units": {"templates": w.n_templates, "timestamp_groups": n_groups, "sft_rows": w.n_sft},
+                     "bins_by_series": {k: census[k] / census["pairs"] for k in ("w0", "w1", "w3", "table", "stat")}},
         "tuning": best.as_dict(),
         "graph_ms_per_step": graph_ms,
     }
@@ -281,7 +346,10 @@ def space_leg(args):
     k_ms = float(np.mean(sft.kernel_times(args.steps)))
     sft.kernel_timing(0)
     n_use = (w.bank["a_last"] - w.bank["a_first"] + 1).astype(np.float64)
-    slots = float(np.sum(n_use)) * alg_slots(K, "fresnel", 1, 1)   # one group and one row per SFT
+    # one row per timestamp group (one detector): group index = SFT index
+    slots, census = scan_census(w.bank["mc"], w.bank["t_c"], w.t_start + 0.5 * w.t_sft, np.ones(w.n_sft), w.t_sft,
+                                K, 1e-7, sft.T_SUN, g_first=w.bank["a_first"], g_last=w.bank["a_last"],
+                                multi_row=False, stride=16)
     achieved = slots / (k_ms * 1e-3) / 1e12
     flags = out["flags"].cpu().numpy()
     print("space: %.3f ms/step (kernel %.3f ms), %.3e IP/s" % (1e3 * elapsed / args.steps, k_ms,
@@ -291,9 +359,10 @@ def space_leg(args):
                         % (w.n_templates, K),
             "value": w.n_templates * args.steps / elapsed, "unit": "IP/s", "ms_per_step": 1e3 * elapsed / args.steps,
             "template_sfts": float(np.sum(n_use)),
-            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tlane-op/s",
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
                          "frac": achieved / (PEAK_SLOTS / 1e12), "kernel": "scan_kernel", "kernel_ms": k_ms,
-                         "alg_lane_ops_per_template_sft": alg_slots(K, "fresnel", 1, 1)},
+                         "alg_slots_per_launch": slots, "alg_slots_per_template_sft": slots / census["pairs"],
+                         "bins_by_series": {k: census[k] / census["pairs"] for k in ("w0", "w1", "w3", "table", "stat")}},
             "tuning": best.as_dict(), "flagged_templates": int(np.sum(flags != 0))}
 
 

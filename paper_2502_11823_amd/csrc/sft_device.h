@@ -36,6 +36,7 @@ constexpr double kInvTwoPi = 0.15915494309189533577;
 constexpr float kPiF = 3.14159265358979323846f;
 constexpr float kInvPiF = 0.318309886183790671538f;
 constexpr float kInvTwoPiF = 0.159154943091895335769f;
+constexpr float kFourPiSqF = 39.4784176043574344753f;   // 4 pi^2
 
 enum : uint32_t {
   kFlagOOB = 1u,
@@ -248,21 +249,38 @@ __device__ inline void phasor(double phi, float& s, float& c)
 //   fs = 1 - 3 W + 105 W^2 - 10395 W^3,  gs = 1 - 15 W + 945 W^2 - 135135 W^3,  W = w^2.
 // Below, G(v) from the LDS table (interval width 1/2, Horner in v - centre), scaled
 // by tsc = 2 pi / sqrt(2 beta).  bq = beta / (2 pi).
-// the asymptotic form alone (valid for v = |p| sqrt(2/beta) >= SFT_G_VASYM)
+// The asymptotic form alone, with the series cut after NW powers of W.  Relative to |e|,
+// the first dropped term is below 1e-8 for v = |p| sqrt(2/beta) of at least
+//   NW = 3: SFT_G_VASYM (4.5),  NW = 1: SFT_VASYM_W1,  NW = 0: SFT_VASYM_W0
+// (w = 1 / (pi v^2), W = w^2; the dropped terms 2027025 W^4, 105 W^2 and 3 W).
+#define SFT_VASYM_W1 11.0f
+#define SFT_VASYM_W0 76.0f
+template <int NW>
 __device__ inline float2 fres_endpoint_asym(float p, float bq)
 {
   const float r = __builtin_amdgcn_rcpf(p);
   const float w = bq * (r * r);
-  const float W = w * w;
-  const float fs = fmaf(W, fmaf(W, fmaf(W, -10395.0f, 105.0f), -3.0f), 1.0f);
-  const float gs = fmaf(W, fmaf(W, fmaf(W, -135135.0f, 945.0f), -15.0f), 1.0f);
-  return make_float2((r * w) * gs, r * fs);
+  if constexpr (NW == 0) {
+    return make_float2(r * w, r);
+  } else {
+    const float W = w * w;
+    float fs, gs;
+    if constexpr (NW == 3) {
+      fs = fmaf(W, fmaf(W, fmaf(W, -10395.0f, 105.0f), -3.0f), 1.0f);
+      gs = fmaf(W, fmaf(W, fmaf(W, -135135.0f, 945.0f), -15.0f), 1.0f);
+    } else {
+      static_assert(NW == 1, "series cut after 0, 1 or 3 powers of W");
+      fs = fmaf(W, -3.0f, 1.0f);
+      gs = fmaf(W, -15.0f, 1.0f);
+    }
+    return make_float2((r * w) * gs, r * fs);
+  }
 }
 
 __device__ inline float2 fres_endpoint2(float p, float bq, float sq2ob, float tsc, const float2* tab)
 {
   const float v = fabsf(p) * sq2ob;
-  if (v >= SFT_G_VASYM) return fres_endpoint_asym(p, bq);
+  if (v >= SFT_G_VASYM) return fres_endpoint_asym<3>(p, bq);
   int i = (int)(v * (1.0f / SFT_G_WIDTH));
   i = i < SFT_G_NINT - 1 ? i : SFT_G_NINT - 1;
   i = i > 0 ? i : 0;

@@ -434,10 +434,15 @@ __device__ inline int bin_order(int t, int K)
   return K >= SFT_WIDE_K ? ((t & 1) ? K - (t >> 1) : (t >> 1) - K) : t - K;
 }
 
-// Largest x over the active lanes of the wavefront, for x in [lo, hi] (wave-uniform bounds):
-// a binary search on lane votes (a compare's lane mask holds bits of active lanes only).
+// Largest x over the active lanes of the wavefront, for x in [lo, hi] (wave-uniform bounds).
+// The first active lane's value is the answer when no active lane exceeds it (the usual
+// case: neighbouring templates share their windows); otherwise a binary search on lane
+// votes above it (a compare's lane mask holds bits of active lanes only).
 __device__ inline int wave_max_active(int x, int lo, int hi)
 {
+  const int c = __builtin_amdgcn_readfirstlane(x);
+  if (!__ballot(x > c)) return c;
+  lo = c + 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (__ballot(x >= mid)) lo = mid;
@@ -446,15 +451,69 @@ __device__ inline int wave_max_active(int x, int lo, int hi)
   return lo;
 }
 
+// [lo, hi] of x over the active lanes, when every active lane is within span of the first
+// active lane's value; false otherwise.
+__device__ inline bool wave_range(int x, int span, int& lo, int& hi)
+{
+  const int c = __builtin_amdgcn_readfirstlane(x);
+  if (__ballot(x < c - span || x > c + span)) return false;
+  hi = c + wave_max_active(x - c, 0, span);
+  lo = c - wave_max_active(c - x, 0, span);
+  return true;
+}
+
+// LDS stage of one timestamp group's bins for a wavefront: ND rows of stage_width bins from
+// a wave-uniform start.  Compile-time windows (2K+1 bins) leave room for lanes whose windows
+// start up to ~47 bins apart; the run-time K kernel holds K up to 64 with ~63 bins of spread.
+template <int KC>
+__host__ __device__ constexpr int stage_width()
+{
+  return KC >= 0 ? (2 * KC + 1 + 47 + 63) / 64 * 64 : 192;
+}
+
+// The active lanes copy bins [sb, sb + wl) of each row into the wavefront's stage, bin p by
+// the lane of rank p mod (active lanes) (coalesced; any exec mask).  The fences keep the
+// previous group's LDS reads before these writes and the bin loops' reads after them (a
+// wavefront's LDS instructions execute in order).
+template <typename Bin, int ND, int WST>
+__device__ inline void stage_window(Bin* sw, const Bin* const* rp, int sb, int wl)
+{
+  const uint64_t ex = __builtin_amdgcn_read_exec();
+  const int nact = __builtin_popcountll(ex);
+  const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ex >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ex, 0u));
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int p = rank; p < wl; p += nact) {
+    Bin v[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) v[d] = rp[d][sb + p];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) sw[d * WST + p] = v[d];
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One lane per template, one grid row per chunk of timestamp groups.  The SFT rows of
 // a group (one per detector) share the SFT midpoint, hence the chirp, the window and
 // all 2K+1 kernel weights: those are evaluated once per group and contracted with the
 // bins of each of the ND rows (the projector Lambda carries the detector dependence).
 template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
-__device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab);
+__device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab,
+                                          Bin* sw);
+
+// Register budget: the FP32 Fresnel kernels with a compile-time window for groups of 2 or 3
+// rows with the Newtonian chirp fit 96 VGPRs without spilling, i.e. 5 wavefronts per SIMD
+// instead of 4; the others are left to the compiler (1 = no constraint).
+template <int PREC, int KERN, int KC, int ND, int WF>
+constexpr int scan_min_waves()
+{
+  return (PREC != SFT_PREC_FP64 && KERN == KERN_FRESNEL && KC >= 0 && WF == WF_NEWTON && (ND == 2 || ND == 3)) ? 5 : 1;
+}
 
 template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
-__global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_min_waves<PREC, KERN, KC, ND, WF>())))
+void scan_kernel(ScanArgs a)
 {
   __shared__ float2 tab[SFT_G_NINT * (SFT_G_DEG + 1)];
   if (KERN == KERN_FRESNEL) {
@@ -465,6 +524,9 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
   }
 
   __shared__ int s_item;
+  // per wavefront (at most 4 per workgroup): the bins of the current timestamp group
+  constexpr int WST = stage_width<KC>();
+  __shared__ Bin stage[4 * ND * WST];
   const int K = KC >= 0 ? KC : a.K;
   // A work item is (template tile, chunk of timestamp groups), chunk-major so that
   // concurrently running blocks share the data rows of one chunk in L2.  A plain grid
@@ -482,14 +544,16 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs a)
     const int tile = item % a.n_tiles;
     const int c = item / a.n_tiles;
     const int64_t m = (int64_t)tile * blockDim.x + threadIdx.x;
-    if (m < a.n_tmpl) scan_item<Bin, PREC, KERN, KC, ND, WF>(a, K, m, c, tab);
+    if (m < a.n_tmpl) scan_item<Bin, PREC, KERN, KC, ND, WF>(a, K, m, c, tab, stage + (threadIdx.x >> 6) * (ND * WST));
     if (!a.persistent) break;
   }
 }
 
 template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
-__device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab)
+__device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab,
+                                          Bin* sw)
 {
+  constexpr int WST = stage_width<KC>();
   using R = typename PrecTraits<PREC>::R;
   using Acc = typename PrecTraits<PREC>::Acc;
   using PS = typename std::conditional<PREC == SFT_PREC_FP64, double, float>::type;
@@ -525,18 +589,34 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
   Acc zpr, zpi, zxr, zxi, hp, hx;
   uint32_t fl = 0;
 
+  // the group's rows and midpoint time are loaded one group ahead, so that their latency
+  // overlaps the previous group's work
+  int nrows[ND];
+  double ntmid = 0.0;
+  if (g0 <= g1) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) nrows[d] = a.g_rows[g0 * SFT_GROUP_MAX + d];
+    ntmid = a.g_tmid[g0];
+  }
   for (int g = g0; g <= g1; ++g) {
     int rows[ND];
     bool act[ND];
     bool any = false;
 #pragma unroll
+    for (int d = 0; d < ND; ++d) rows[d] = nrows[d];
+    const double tmid = ntmid;
+    if (g < g1) {
+#pragma unroll
+      for (int d = 0; d < ND; ++d) nrows[d] = a.g_rows[(g + 1) * SFT_GROUP_MAX + d];
+      ntmid = a.g_tmid[g + 1];
+    }
+#pragma unroll
     for (int d = 0; d < ND; ++d) {
-      rows[d] = a.g_rows[g * SFT_GROUP_MAX + d];
       act[d] = rows[d] >= 0 && rows[d] >= lo && rows[d] <= hi;
       any = any || act[d];
     }
     if (!any) continue;
-    const double tau = tc - a.g_tmid[g];
+    const double tau = tc - tmid;
     if (!(tau > 0.0)) {
       fl |= kFlagTau;
       continue;
@@ -578,6 +658,20 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
     // bin loop free of per-row branches, so the loads of all rows are issued together) and
     // never accumulated
     for (int d = 0; d < ND; ++d) rp[d] = bins + (int64_t)(rows[d] >= 0 ? rows[d] : 0) * a.n_ext;
+    // Neighbouring templates share most of their windows: when every active lane of the
+    // wavefront is in band and the union of the windows fits the stage, the lanes load the
+    // union once, coalesced, into LDS and the bin loops read it there (stg); otherwise each
+    // lane gathers its bins from global memory with range checks.
+    bool stg = false;
+    int sb = 0;
+    if (!__ballot(!inband)) {
+      int wlo, whi;
+      if (wave_range(i0, WST, wlo, whi) && whi - wlo + 2 * K + 1 <= WST) {
+        stg = true;
+        sb = wlo;
+        stage_window<Bin, ND, WST>(sw, rp, sb, whi - wlo + 2 * K + 1);
+      }
+    }
 
     R cre[ND], cim[ND];
 #pragma unroll
@@ -595,26 +689,32 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
         phasor(kPi * delta, s_, c_);
         sp = s_ * kInvPiF;
       }
+      auto drun = [&](auto stgc) {
+        constexpr bool STG = decltype(stgc)::value;
 #pragma unroll SFT_BIN_UNROLL
-      for (int t = 0; t <= 2 * K; ++t) {
-        const int j = bin_order(t, K);
-        const int idx = i0 + j + K;
-        if (!inband && (idx < 0 || idx >= a.n_ext)) {
-          fl |= kFlagOOB;
-          continue;
-        }
-        const R x = dl - (R)j;
-        R h;
-        if constexpr (PREC == SFT_PREC_FP64) h = (x == (R)0) ? (R)1 : sp / x;
-        else h = (x == (R)0) ? (R)1 : (R)(sp * fast_rcp((float)x));
+        for (int t = 0; t <= 2 * K; ++t) {
+          const int j = bin_order(t, K);
+          const int idx = i0 + j + K;
+          if (!STG && !inband && (idx < 0 || idx >= a.n_ext)) {
+            fl |= kFlagOOB;
+            continue;
+          }
+          const R x = dl - (R)j;
+          R h;
+          if constexpr (PREC == SFT_PREC_FP64) h = (x == (R)0) ? (R)1 : sp / x;
+          else h = (x == (R)0) ? (R)1 : (R)(sp * fast_rcp((float)x));
 #pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          R bre, bim;
-          BinIO<Bin>::load(rp[d] + idx, bre, bim);
-          cre[d] = fma(bre, h, cre[d]);
-          cim[d] = fma(bim, h, cim[d]);
+          for (int d = 0; d < ND; ++d) {
+            R bre, bim;
+            if constexpr (STG) BinIO<Bin>::load(sw + d * WST + (idx - sb), bre, bim);
+            else BinIO<Bin>::load(rp[d] + idx, bre, bim);
+            cre[d] = fma(bre, h, cre[d]);
+            cim[d] = fma(bim, h, cim[d]);
+          }
         }
-      }
+      };
+      if (stg) drun(std::true_type{});
+      else drun(std::false_type{});
     } else if constexpr (KERN == KERN_FRESNEL) {
       // Fresnel weights; beta < 0 through F(x, beta) = conj F(-x, -beta).  The endpoint
       // phasors E-+ are common to all bins, so the bins accumulate b e(p-) and b e(p+)
@@ -640,71 +740,80 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       double ib = (double)fast_rcp(bp);
       ib = ib * fma(-bpos, ib, 2.0);
       ib = ib * fma(-bpos, ib, 2.0);
-      float smr[ND], smi[ND], spr[ND], spi[ND], ssr[ND], ssi[ND];
-#pragma unroll
-      for (int d = 0; d < ND; ++d) smr[d] = smi[d] = spr[d] = spi[d] = ssr[d] = ssi[d] = 0.f;
+      // one row: sums of b e(p-) and b e(p+) (unused with several rows)
+      float smr = 0.f, smi = 0.f, spr = 0.f, spi = 0.f;
       // Outer bins: jj >= jup or jj <= jdn puts both endpoints of a lane at least one bin
       // beyond the asymptotic threshold |p| = SFT_G_VASYM sqrt(beta / 2), with no stationary
       // point inside the SFT (p- and p+ of one sign).  With the bounds taken over the active
       // lanes of the wavefront, those bins take the asymptotic form directly, without the
       // per-lane range test.  Lane bounds are clamped to the window, [-K-1, K+1].
-      // Used for windows of SFT_OUTER_MIN_K bins or more a side (jup > K and jdn < -K disable it).
-      int jup = K + 1, jdn = -K - 1;
+      // The same bounds for the larger thresholds at which the series may stop after one or
+      // no power of W (ju1/jd1, ju0/jd0) nest outside jup/jdn:
+      //   jd0 <= jd1 <= jdn < 0 < jup <= ju1 <= ju0.
+      // Used for windows of SFT_OUTER_MIN_K bins or more a side (otherwise every bin takes
+      // the table path).
+      int jup = K + 1, jdn = -K - 1, ju1 = K + 1, jd1 = -K - 1, ju0 = K + 1, jd0 = -K - 1;
       if (K >= SFT_OUTER_MIN_K) {
-        const float pa = SFT_G_VASYM * (bp * isq2b);   // sqrt(beta / 2) = beta / sqrt(2 beta)
-        const float fup = fminf(fmaxf(ceilf(dp + pa) + 1.0f, (float)(-K - 1)), (float)(K + 1));
-        const float fdn = fminf(fmaxf(floorf(dm - pa) - 1.0f, (float)(-K - 1)), (float)(K + 1));
-        jup = wave_max_active((int)fup, -K - 1, K + 1);
-        jdn = -wave_max_active(-(int)fdn, -K - 1, K + 1);
+        const float shb = bp * isq2b;   // sqrt(beta / 2) = beta / sqrt(2 beta)
+        auto up = [&](float vt) {
+          return (int)fminf(fmaxf(ceilf(fmaf(vt, shb, dp)) + 1.0f, (float)(-K - 1)), (float)(K + 1));
+        };
+        auto dn = [&](float vt) {
+          return -(int)fminf(fmaxf(floorf(fmaf(-vt, shb, dm)) - 1.0f, (float)(-K - 1)), (float)(K + 1));
+        };
+        jup = wave_max_active(up(SFT_G_VASYM), -K - 1, K + 1);
+        jdn = -wave_max_active(dn(SFT_G_VASYM), -K - 1, K + 1);
+        ju1 = wave_max_active(up(SFT_VASYM_W1), jup, K + 1);
+        jd1 = -wave_max_active(dn(SFT_VASYM_W1), -jdn, K + 1);
+        ju0 = wave_max_active(up(SFT_VASYM_W0), ju1, K + 1);
+        jd0 = -wave_max_active(dn(SFT_VASYM_W0), -jd1, K + 1);
       }
       // E-+ / 2 pi with the imaginary parts of the beta < 0 mirror
       const float eqr = kInvTwoPiF * emr, eqy = kInvTwoPiF * (neg ? -emi : emi);
       const float fqr = kInvTwoPiF * epr, fqy = kInvTwoPiF * (neg ? -epi : epi);
-      auto run = [&](auto negc, auto checked) {
+      // rho = E+ / E- (with the mirror): the bin weight is (E- / 2 pi) (e(p-) - rho e(p+));
+      // 1 / (E- / 2 pi) = 4 pi^2 conj(E- / 2 pi) as |E-| = 1
+      const float rhr = kFourPiSqF * fmaf(fqr, eqr, fqy * eqy), rhi = kFourPiSqF * fmaf(fqy, eqr, -fqr * eqy);
+      // One bin jj (jj = -j for beta < 0) of series tier TR: 0, 1 or 3 the asymptotic form cut
+      // after TR powers of W, 4 the table with the stationary-point check.
+      auto bin = [&](auto negc, auto checked, auto stgc, auto tierc, int jj) {
         constexpr bool NEG = decltype(negc)::value;
         constexpr bool CHK = decltype(checked)::value;
-#pragma unroll SFT_BIN_UNROLL
-        for (int t = 0; t <= 2 * K; ++t) {
-          const int j = bin_order(t, K);
-          const int idx = i0 + j + K;
-          if constexpr (CHK) {
-            if (idx < 0 || idx >= a.n_ext) {
-              fl |= kFlagOOB;
-              continue;
-            }
+        constexpr bool STG = decltype(stgc)::value;
+        constexpr int TR = decltype(tierc)::value;
+        const int j = NEG ? -jj : jj;
+        const int idx = i0 + j + K;
+        if constexpr (CHK) {
+          if (idx < 0 || idx >= a.n_ext) {
+            fl |= kFlagOOB;
+            return;
           }
-          const int jj = NEG ? -j : j;
-          const float pm = dm - (float)jj, pp = dp - (float)jj;
-          if (jj >= jup || jj <= jdn) {
-            const float2 em = fres_endpoint_asym(pm, bq);
-            const float2 ep = fres_endpoint_asym(pp, bq);
-            const float emy = NEG ? -em.y : em.y, epy = NEG ? -ep.y : ep.y;
-            if constexpr (ND >= 2) {
-              const float hr = (eqr * em.x - eqy * emy) - (fqr * ep.x - fqy * epy);
-              const float hi = (eqr * emy + eqy * em.x) - (fqr * epy + fqy * ep.x);
+        }
+        // the bins first, so that their loads are in flight while the weights are formed
+        float bre[ND], bim[ND];
 #pragma unroll
-              for (int d = 0; d < ND; ++d) {
-                float bre, bim;
-                BinIO<Bin>::load(rp[d] + idx, bre, bim);
-                cre[d] = fmaf(bre, hr, fmaf(-bim, hi, cre[d]));
-                cim[d] = fmaf(bre, hi, fmaf(bim, hr, cim[d]));
-              }
-            } else {
-              float bre, bim;
-              BinIO<Bin>::load(rp[0] + idx, bre, bim);
-              smr[0] = fmaf(bre, em.x, fmaf(-bim, emy, smr[0]));
-              smi[0] = fmaf(bre, emy, fmaf(bim, em.x, smi[0]));
-              spr[0] = fmaf(bre, ep.x, fmaf(-bim, epy, spr[0]));
-              spi[0] = fmaf(bre, epy, fmaf(bim, ep.x, spi[0]));
-            }
-            continue;
+        for (int d = 0; d < ND; ++d) {
+          if constexpr (STG) BinIO<Bin>::load(sw + d * WST + (idx - sb), bre[d], bim[d]);
+          else BinIO<Bin>::load(rp[d] + idx, bre[d], bim[d]);
+        }
+        const float pm = dm - (float)jj, pp = dp - (float)jj;
+        float2 em, ep;
+        float hre = 0.f, him = 0.f;
+        if constexpr (TR < 4) {
+          em = fres_endpoint_asym<TR>(pm, bq);
+          ep = fres_endpoint_asym<TR>(pp, bq);
+          if (NEG) {
+            em.y = -em.y;
+            ep.y = -ep.y;
           }
-          const float2 em = fres_endpoint2(pm, bq, sq2ob, tsc, tab);
-          const float2 ep = fres_endpoint2(pp, bq, sq2ob, tsc, tab);
-          const float emy = NEG ? -em.y : em.y, epy = NEG ? -ep.y : ep.y;
-          const bool stat = pm < 0.0f && pp >= 0.0f;
-          float hre = 0.f, him = 0.f;
-          if (stat) {
+        } else {
+          em = fres_endpoint2(pm, bq, sq2ob, tsc, tab);
+          ep = fres_endpoint2(pp, bq, sq2ob, tsc, tab);
+          if (NEG) {
+            em.y = -em.y;
+            ep.y = -ep.y;
+          }
+          if (pm < 0.0f && pp >= 0.0f) {
             // stationary point inside the SFT: (-1)^j (1+i) exp(-i pi x^2 / beta) / sqrt(2 beta)
             const double x64 = ds64 - (double)jj;
             const double hq = x64 * x64 * ib;
@@ -713,47 +822,63 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
             const float sg = (jj & 1) ? -isq2b : isq2b;
             hre = sg * (cr + sr);
             him = NEG ? -sg * (cr - sr) : sg * (cr - sr);
-          }
-          if constexpr (ND >= 2) {
-            // several rows share the weights: form the bin's complex weight once,
-            // H = (E- e(p-) - E+ e(p+)) / 2 pi + stationary term, then one complex MAC per row
-            const float hr = (eqr * em.x - eqy * emy) - (fqr * ep.x - fqy * epy) + hre;
-            const float hi = (eqr * emy + eqy * em.x) - (fqr * epy + fqy * ep.x) + him;
-#pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                  float bre, bim;
-              BinIO<Bin>::load(rp[d] + idx, bre, bim);
-              cre[d] = fmaf(bre, hr, fmaf(-bim, hi, cre[d]));
-              cim[d] = fmaf(bre, hi, fmaf(bim, hr, cim[d]));
-            }
-            continue;
-          }
-#pragma unroll
-          for (int d = 0; d < ND; ++d) {
-              float bre, bim;
-            BinIO<Bin>::load(rp[d] + idx, bre, bim);
-            smr[d] = fmaf(bre, em.x, fmaf(-bim, emy, smr[d]));
-            smi[d] = fmaf(bre, emy, fmaf(bim, em.x, smi[d]));
-            spr[d] = fmaf(bre, ep.x, fmaf(-bim, epy, spr[d]));
-            spi[d] = fmaf(bre, epy, fmaf(bim, ep.x, spi[d]));
-            if (stat) {
-              ssr[d] = fmaf(bre, hre, fmaf(-bim, him, ssr[d]));
-              ssi[d] = fmaf(bre, him, fmaf(bim, hre, ssi[d]));
-            }
+            // carry the term inside e(p-), which the sums multiply by E- / 2 pi
+            em.x = fmaf(kFourPiSqF, fmaf(hre, eqr, him * eqy), em.x);
+            em.y = fmaf(kFourPiSqF, fmaf(him, eqr, -hre * eqy), em.y);
           }
         }
+        if constexpr (ND >= 2) {
+          // several rows share the bin's weight H' = e(p-) - rho e(p+): one complex MAC per
+          // row, E- / 2 pi applied once per row after the loop
+          const float hr = fmaf(-rhr, ep.x, fmaf(rhi, ep.y, em.x));
+          const float hi = fmaf(-rhr, ep.y, fmaf(-rhi, ep.x, em.y));
+#pragma unroll
+          for (int d = 0; d < ND; ++d) {
+            cre[d] = fmaf(bre[d], hr, fmaf(-bim[d], hi, cre[d]));
+            cim[d] = fmaf(bre[d], hi, fmaf(bim[d], hr, cim[d]));
+          }
+        } else {
+          // one row: the bins accumulate b e(p-) and b e(p+)
+          smr = fmaf(bre[0], em.x, fmaf(-bim[0], em.y, smr));
+          smi = fmaf(bre[0], em.y, fmaf(bim[0], em.x, smi));
+          spr = fmaf(bre[0], ep.x, fmaf(-bim[0], ep.y, spr));
+          spi = fmaf(bre[0], ep.y, fmaf(bim[0], ep.x, spi));
+        }
       };
-      if (inband) {
-        if (neg) run(std::true_type{}, std::false_type{});
-        else run(std::false_type{}, std::false_type{});
+      // The bins as segments of one series tier each (bounds wave-uniform, so no per-bin
+      // tier test), from the window's edges inwards: the smallest terms enter the FP32 sums
+      // first and the central table bins last.
+      auto run = [&](auto negc, auto checked, auto stgc) {
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I3 = std::integral_constant<int, 3>;
+        using I4 = std::integral_constant<int, 4>;
+        for (int jj = -K; jj <= jd0; ++jj) bin(negc, checked, stgc, I0{}, jj);
+        for (int jj = K; jj >= ju0; --jj) bin(negc, checked, stgc, I0{}, jj);
+        for (int jj = jd0 + 1; jj <= jd1; ++jj) bin(negc, checked, stgc, I1{}, jj);
+        for (int jj = ju0 - 1; jj >= ju1; --jj) bin(negc, checked, stgc, I1{}, jj);
+        for (int jj = jd1 + 1; jj <= jdn; ++jj) bin(negc, checked, stgc, I3{}, jj);
+        for (int jj = ju1 - 1; jj >= jup; --jj) bin(negc, checked, stgc, I3{}, jj);
+        for (int jj = jdn + 1; jj < jup; ++jj) bin(negc, checked, stgc, I4{}, jj);
+      };
+      if (stg) {
+        if (neg) run(std::true_type{}, std::false_type{}, std::true_type{});
+        else run(std::false_type{}, std::false_type{}, std::true_type{});
       } else {
-        if (neg) run(std::true_type{}, std::true_type{});
-        else run(std::false_type{}, std::true_type{});
+        if (neg) run(std::true_type{}, std::true_type{}, std::false_type{});
+        else run(std::false_type{}, std::true_type{}, std::false_type{});
       }
       if constexpr (ND == 1) {
         // one row: the bins accumulated b e(p-) and b e(p+); apply the phasors once
-        cre[0] = (eqr * smr[0] - eqy * smi[0]) - (fqr * spr[0] - fqy * spi[0]) + ssr[0];
-        cim[0] = (eqr * smi[0] + eqy * smr[0]) - (fqr * spi[0] + fqy * spr[0]) + ssi[0];
+        cre[0] = (eqr * smr - eqy * smi) - (fqr * spr - fqy * spi);
+        cim[0] = (eqr * smi + eqy * smr) - (fqr * spi + fqy * spr);
+      } else {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          const R cr = cre[d];
+          cre[d] = eqr * cr - eqy * cim[d];
+          cim[d] = eqr * cim[d] + eqy * cr;
+        }
       }
     }
     // term_d = (-1)^{k0} A exp(i phi) C_d
@@ -779,6 +904,9 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
     const bool psd_in = ip >= 0 && ip + 1 < a.n_bins;
     const R w = (R)(ch.kappa - kfl);
     const R a2t = amp * amp * (R)T;
+    // the rows of the group are summed plainly, then the group enters the running
+    // (compensated) sums once
+    R gzpr = 0, gzpi = 0, gzxr = 0, gzxi = 0, ghp = 0, ghx = 0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       if (!act[d]) continue;
@@ -786,10 +914,10 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       const R tim = apc * cim[d] + aps * cre[d];
       const R fpa = (R)a.fp[rows[d]];
       const R fxa = (R)a.fx[rows[d]];
-      zpr.add(fpa * tre);
-      zpi.add(fpa * tim);
-      zxr.add(fxa * tre);
-      zxi.add(fxa * tim);
+      gzpr = fma(fpa, tre, gzpr);
+      gzpi = fma(fpa, tim, gzpi);
+      gzxr = fma(fxa, tre, gzxr);
+      gzxi = fma(fxa, tim, gzxi);
       if (!psd_in) {
         fl |= kFlagOOB;
         continue;
@@ -804,9 +932,15 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       R hterm;
       if constexpr (PREC == SFT_PREC_FP64) hterm = a2t / S;
       else hterm = a2t * (R)fast_rcp((float)S);
-      hp.add(fpa * fpa * hterm);
-      hx.add(fxa * fxa * hterm);
+      ghp = fma(fpa * fpa, hterm, ghp);
+      ghx = fma(fxa * fxa, hterm, ghx);
     }
+    zpr.add(gzpr);
+    zpi.add(gzpi);
+    zxr.add(gzxr);
+    zxi.add(gzxi);
+    hp.add(ghp);
+    hx.add(ghx);
   }
 
   const int64_t n = a.n_tmpl;
