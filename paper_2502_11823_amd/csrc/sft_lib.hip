@@ -503,12 +503,14 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
                                           Bin* sw);
 
 // Register budget: the FP32 Fresnel kernels with a compile-time window for groups of 2 or 3
-// rows with the Newtonian chirp fit 96 VGPRs without spilling, i.e. 5 wavefronts per SIMD
-// instead of 4; the others are left to the compiler (1 = no constraint).
+// rows, and the one-row K = 32 kernel, with the Newtonian chirp fit 96 VGPRs without
+// spilling, i.e. 5 wavefronts per SIMD instead of 4; the others are left to the compiler
+// (1 = no constraint).
 template <int PREC, int KERN, int KC, int ND, int WF>
 constexpr int scan_min_waves()
 {
-  return (PREC != SFT_PREC_FP64 && KERN == KERN_FRESNEL && KC >= 0 && WF == WF_NEWTON && (ND == 2 || ND == 3)) ? 5 : 1;
+  return (PREC != SFT_PREC_FP64 && KERN == KERN_FRESNEL && KC >= 0 && WF == WF_NEWTON &&
+          (ND == 2 || ND == 3 || (ND == 1 && KC == 32))) ? 5 : 1;
 }
 
 template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
@@ -1019,6 +1021,9 @@ template <typename Bin, int PREC, int KERN, int WF>
 static ScanFn pick_k(int K, int nd)
 {
   if (PREC == SFT_PREC_FP64) return K == 4 ? pick_nd<Bin, PREC, KERN, 4, WF>(nd) : pick_nd<Bin, PREC, KERN, -1, WF>(nd);
+  // one-row Fresnel scans with K = 32 (space-like banks) get a compile-time window too
+  if constexpr (KERN == KERN_FRESNEL && WF == WF_NEWTON)
+    if (K == 32 && nd == 1) return scan_kernel<Bin, PREC, KERN, 32, 1, WF>;
   return K == 8 ? pick_nd<Bin, PREC, KERN, 8, WF>(nd) : pick_nd<Bin, PREC, KERN, -1, WF>(nd);
 }
 
