@@ -36,7 +36,6 @@ constexpr double kInvTwoPi = 0.15915494309189533577;
 constexpr float kPiF = 3.14159265358979323846f;
 constexpr float kInvPiF = 0.318309886183790671538f;
 constexpr float kInvTwoPiF = 0.159154943091895335769f;
-constexpr float kFourPiSqF = 39.4784176043574344753f;   // 4 pi^2
 
 enum : uint32_t {
   kFlagOOB = 1u,

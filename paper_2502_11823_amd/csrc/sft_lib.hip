@@ -773,9 +773,9 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       // E-+ / 2 pi with the imaginary parts of the beta < 0 mirror
       const float eqr = kInvTwoPiF * emr, eqy = kInvTwoPiF * (neg ? -emi : emi);
       const float fqr = kInvTwoPiF * epr, fqy = kInvTwoPiF * (neg ? -epi : epi);
-      // rho = E+ / E- (with the mirror): the bin weight is (E- / 2 pi) (e(p-) - rho e(p+));
-      // 1 / (E- / 2 pi) = 4 pi^2 conj(E- / 2 pi) as |E-| = 1
-      const float rhr = kFourPiSqF * fmaf(fqr, eqr, fqy * eqy), rhi = kFourPiSqF * fmaf(fqy, eqr, -fqr * eqy);
+      // rho = E+ / E- = exp(2 pi i delta) = (cd + i sd)^2 (conjugated by the mirror): the bin
+      // weight is (E- / 2 pi) (e(p-) - rho e(p+))
+      const float rhr = fmaf(cd, cd, -sd * sd), rhi = neg ? -2.0f * cd * sd : 2.0f * cd * sd;
       // One bin jj (jj = -j for beta < 0) of series tier TR: 0, 1 or 3 the asymptotic form cut
       // after TR powers of W, 4 the table with the stationary-point check.
       auto bin = [&](auto negc, auto checked, auto stgc, auto tierc, int jj) {
@@ -800,7 +800,6 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
         }
         const float pm = dm - (float)jj, pp = dp - (float)jj;
         float2 em, ep;
-        float hre = 0.f, him = 0.f;
         if constexpr (TR < 4) {
           em = fres_endpoint_asym<TR>(pm, bq);
           ep = fres_endpoint_asym<TR>(pp, bq);
@@ -816,17 +815,17 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
             ep.y = -ep.y;
           }
           if (pm < 0.0f && pp >= 0.0f) {
-            // stationary point inside the SFT: (-1)^j (1+i) exp(-i pi x^2 / beta) / sqrt(2 beta)
+            // stationary point inside the SFT: h = (-1)^j (1+i) exp(-i pi x^2 / beta) / sqrt(2 beta),
+            // carried inside e(p-), which the sums multiply by E- / 2 pi:
+            //   h / (E- / 2 pi) = 2 pi (-1)^j (1+i) exp(-i (pi x^2 / beta - pi delta + pi beta / 4)) / sqrt(2 beta)
+            // with the whole phase reduced in FP64 (one phasor, as for h alone)
             const double x64 = ds64 - (double)jj;
             const double hq = x64 * x64 * ib;
             float sr, cr;
-            phasor(kPi * (hq - 2.0 * rint(0.5 * hq)), sr, cr);
-            const float sg = (jj & 1) ? -isq2b : isq2b;
-            hre = sg * (cr + sr);
-            him = NEG ? -sg * (cr - sr) : sg * (cr - sr);
-            // carry the term inside e(p-), which the sums multiply by E- / 2 pi
-            em.x = fmaf(kFourPiSqF, fmaf(hre, eqr, him * eqy), em.x);
-            em.y = fmaf(kFourPiSqF, fmaf(him, eqr, -hre * eqy), em.y);
+            phasor(kPi * (hq - 2.0 * rint(0.5 * hq)) - kPi * ds64 + 0.25 * kPi * bpos, sr, cr);
+            const float g = (jj & 1) ? -tsc : tsc;   // 2 pi (-1)^j / sqrt(2 beta)
+            em.x += g * (cr + sr);
+            em.y += NEG ? -g * (cr - sr) : g * (cr - sr);
           }
         }
         if constexpr (ND >= 2) {
