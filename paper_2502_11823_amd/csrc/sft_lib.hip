@@ -738,10 +738,11 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       phasor(kPi * ds64, sd, cd);
       const float epr = cd * ct - sd * st, epi = sd * ct + cd * st;   // E+
       const float emr = cd * ct + sd * st, emi = cd * st - sd * ct;   // E-
-      // 1 / beta in FP64 for the stationary phase: FP32 estimate + two Newton steps
+      // 1 / beta and p- of bin 0 in FP64 for the stationary phase: FP32 estimate + two Newton steps
       double ib = (double)fast_rcp(bp);
       ib = ib * fma(-bpos, ib, 2.0);
       ib = ib * fma(-bpos, ib, 2.0);
+      const double dm64 = ds64 - 0.5 * bpos;
       // one row: sums of b e(p-) and b e(p+) (unused with several rows)
       float smr = 0.f, smi = 0.f, spr = 0.f, spi = 0.f;
       // Outer bins: jj >= jup or jj <= jdn puts both endpoints of a lane at least one bin
@@ -816,16 +817,16 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
           }
           if (pm < 0.0f && pp >= 0.0f) {
             // stationary point inside the SFT: h = (-1)^j (1+i) exp(-i pi x^2 / beta) / sqrt(2 beta),
-            // carried inside e(p-), which the sums multiply by E- / 2 pi:
-            //   h / (E- / 2 pi) = 2 pi (-1)^j (1+i) exp(-i (pi x^2 / beta - pi delta + pi beta / 4)) / sqrt(2 beta)
-            // with the whole phase reduced in FP64 (one phasor, as for h alone)
-            const double x64 = ds64 - (double)jj;
-            const double hq = x64 * x64 * ib;
+            // x = delta - j, carried inside e(p-), which the sums multiply by E- / 2 pi.  As
+            // x^2 - delta beta + beta^2 / 4 = (p-)^2 + j beta with j an integer,
+            //   h / (E- / 2 pi) = 2 pi (1+i) exp(-i pi (p-)^2 / beta) / sqrt(2 beta),
+            // with p- = delta - beta/2 - j and its phase reduced in FP64
+            const double p64 = dm64 - (double)jj;
+            const double hq = p64 * p64 * ib;
             float sr, cr;
-            phasor(kPi * (hq - 2.0 * rint(0.5 * hq)) - kPi * ds64 + 0.25 * kPi * bpos, sr, cr);
-            const float g = (jj & 1) ? -tsc : tsc;   // 2 pi (-1)^j / sqrt(2 beta)
-            em.x += g * (cr + sr);
-            em.y += NEG ? -g * (cr - sr) : g * (cr - sr);
+            phasor(kPi * (hq - 2.0 * rint(0.5 * hq)), sr, cr);
+            em.x += tsc * (cr + sr);
+            em.y += NEG ? -tsc * (cr - sr) : tsc * (cr - sr);
           }
         }
         if constexpr (ND >= 2) {
