@@ -465,10 +465,12 @@ __device__ inline bool wave_range(int x, int span, int& lo, int& hi)
 // LDS stage of one timestamp group's bins for a wavefront: ND rows of stage_width bins from
 // a wave-uniform start.  Compile-time windows (2K+1 bins) leave room for lanes whose windows
 // start up to ~47 bins apart; the run-time K kernel holds K up to 64 with ~63 bins of spread.
-template <int KC>
+// The 3.5PN kernels (two wavefronts per SIMD for their registers) gather instead: the stage's
+// load -> LDS -> read chain per group costs them more latency than the gathers it replaces.
+template <int KC, int WF>
 __host__ __device__ constexpr int stage_width()
 {
-  return KC >= 0 ? (2 * KC + 1 + 47 + 63) / 64 * 64 : 192;
+  return WF == WF_PN35 ? 0 : KC >= 0 ? (2 * KC + 1 + 47 + 63) / 64 * 64 : 192;
 }
 
 // The active lanes copy bins [sb, sb + wl) of each row into the wavefront's stage, bin p by
@@ -504,13 +506,17 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
 
 // Register budget: the FP32 Fresnel kernels with a compile-time window for groups of 2 or 3
 // rows, and the one-row K = 32 kernel, with the Newtonian chirp fit 96 VGPRs without
-// spilling, i.e. 5 wavefronts per SIMD instead of 4; the others are left to the compiler
-// (1 = no constraint).
+// spilling, i.e. 5 wavefronts per SIMD instead of 4; the FP32 Dirichlet kernels with the
+// 3.5PN chirp fit 168, i.e. 3 instead of 2.  The others are left to the compiler (1 = no
+// constraint).
 template <int PREC, int KERN, int KC, int ND, int WF>
 constexpr int scan_min_waves()
 {
-  return (PREC != SFT_PREC_FP64 && KERN == KERN_FRESNEL && KC >= 0 && WF == WF_NEWTON &&
-          (ND == 2 || ND == 3 || (ND == 1 && KC == 32))) ? 5 : 1;
+  if (PREC != SFT_PREC_FP64 && KERN == KERN_FRESNEL && KC >= 0 && WF == WF_NEWTON &&
+      (ND == 2 || ND == 3 || (ND == 1 && KC == 32)))
+    return 5;
+  if (PREC != SFT_PREC_FP64 && KERN == KERN_DIRICHLET && WF == WF_PN35) return 3;
+  return 1;
 }
 
 template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
@@ -527,8 +533,8 @@ void scan_kernel(ScanArgs a)
 
   __shared__ int s_item;
   // per wavefront (at most 4 per workgroup): the bins of the current timestamp group
-  constexpr int WST = stage_width<KC>();
-  __shared__ Bin stage[4 * ND * WST];
+  constexpr int WST = stage_width<KC, WF>();
+  __shared__ Bin stage[4 * ND * (WST > 0 ? WST : 1)];
   const int K = KC >= 0 ? KC : a.K;
   // A work item is (template tile, chunk of timestamp groups), chunk-major so that
   // concurrently running blocks share the data rows of one chunk in L2.  A plain grid
@@ -555,7 +561,7 @@ template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
 __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab,
                                           Bin* sw)
 {
-  constexpr int WST = stage_width<KC>();
+  constexpr int WST = stage_width<KC, WF>();
   using R = typename PrecTraits<PREC>::R;
   using Acc = typename PrecTraits<PREC>::Acc;
   using PS = typename std::conditional<PREC == SFT_PREC_FP64, double, float>::type;
@@ -666,7 +672,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
     // lane gathers its bins from global memory with range checks.
     bool stg = false;
     int sb = 0;
-    if (!__ballot(!inband)) {
+    if (WST > 0 && !__ballot(!inband)) {
       int wlo, whi;
       if (wave_range(i0, WST, wlo, whi) && whi - wlo + 2 * K + 1 <= WST) {
         stg = true;
