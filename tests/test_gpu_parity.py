@@ -89,6 +89,25 @@ def test_ground_small_multidetector(ground_small, K, kernel):
     compare(gpu_scan(data, w.bank, **kw), orc_scan(w, w.bank, **kw), label="ground-small K=%d %s" % (K, kernel))
 
 
+@pytest.mark.parametrize("K,kernel", [(8, "auto"), (32, "fresnel")])
+def test_shuffled_bank_mixes_staged_and_gathered_windows(ground_small, K, kernel):
+    """The bank in a seeded random order: the lanes of a wavefront hold chirp masses across
+    [1.0, 1.5], so their windows spread over tens of bins.  Groups whose window union exceeds
+    the wavefront's LDS stage take the checked gather path, the others the stage, and the
+    series-tier bounds are set by the widest lanes."""
+    w = ground_small
+    p = np.random.default_rng(17).permutation(w.n_templates)
+    bank = {k: np.ascontiguousarray(v[p]) for k, v in w.bank.items()}
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=K, kernel=kernel, precision="fp32_kahan", a_plus=1.0, a_cross=1.0)
+    g = gpu_scan(data, bank, **kw)
+    compare(g, orc_scan(w, bank, **kw), label="shuffled K=%d %s" % (K, kernel))
+    # the same templates in bank order give the same results up to FP32 summation order
+    gs = gpu_scan(data, w.bank, **kw)
+    e = np.abs(g["zp"] - gs["zp"][p]) / np.maximum(np.abs(gs["zp"][p]), np.sqrt(gs["hhp"][p]))
+    assert e.max() < 1e-6
+
+
 def test_fresnel_large_drift():
     """Templates close to merger: beta = fdot T^2 up to tens of bins, K = 32."""
     w = synth.ground(seed=8, n_templates=300, n_slots=40, n_det=1, k_lo=20, k_hi=1500,
