@@ -51,8 +51,9 @@ OPS_DIRICHLET = 23          # sin(pi delta) / pi
 # Fresnel weights per bin and lane, by the series length the bin's endpoints need (two
 # endpoints each; p-+ = delta -+ beta/2 - j is 2): both endpoints at v = |p| sqrt(2/beta) >= 76
 # (no W term: 1/p, r^2, w, r w), >= 11 (one W term: 5 more), >= 4.5 (three W terms: 4 more),
-# else the 9-interval degree-8 table (|p|, the interval, two Horner chains, sign and scale)
-OPS_BIN = {"w0": 2 + 2 * (1 + 3), "w1": 2 + 2 * (1 + 8), "w3": 2 + 2 * (1 + 12), "table": 2 + 2 * 23 + 2}
+# else the 90-interval cubic table (|p| sqrt(2/beta), the offset in the interval, two Horner
+# chains of 3, the scale) and the stationary-point test
+OPS_BIN = {"w0": 2 + 2 * (1 + 3), "w1": 2 + 2 * (1 + 8), "w3": 2 + 2 * (1 + 12), "table": 2 + 2 * 11 + 2}
 OPS_BIN_STAT = 2 * 3 + 2 * 3 + 16 + 5 + 6   # stationary point inside the SFT: x^2/beta and its
                                             # reduction (FP64), the phasor, the term, folded into e(p-)
 OPS_BIN_DIR = 3                             # x = delta - j, 1/x, sin(pi delta)/pi x

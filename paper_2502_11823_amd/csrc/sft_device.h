@@ -246,7 +246,8 @@ __device__ inline void phasor(double phi, float& s, float& c)
 // asymptotic range (v >= 4.5) with r = 1/p and w = beta r^2 / (2 pi):
 //   2 pi e(p) = r w gs(w^2) + i r fs(w^2),
 //   fs = 1 - 3 W + 105 W^2 - 10395 W^3,  gs = 1 - 15 W + 945 W^2 - 135135 W^3,  W = w^2.
-// Below, G(v) from the LDS table (interval width 1/2, Horner in v - centre), scaled
+// Below, G(v) from the LDS table (SFT_G_NINT intervals of width SFT_G_WIDTH, Horner of degree
+// SFT_G_DEG in v - centre), scaled
 // by tsc = 2 pi / sqrt(2 beta).  bq = beta / (2 pi).
 // The asymptotic form alone, with the series cut after NW powers of W.  Relative to |e|,
 // the first dropped term is below 1e-8 for v = |p| sqrt(2/beta) of at least
