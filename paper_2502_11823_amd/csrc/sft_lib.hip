@@ -381,12 +381,12 @@ enum { KERN_DIRICHLET = 0, KERN_FRESNEL = 1 };
 // surrogate path fills it); an internal value, never accepted from the caller
 enum { WF_NEWTON = SFT_WF_NEWTON, WF_PN35 = SFT_WF_PN35, WF_TABLE = 100 };
 
-// smallest window half-width for which the Fresnel loop separates the outer bins
+// smallest window half-width for which the Fresnel loop splits the bins into series segments
 #ifndef SFT_OUTER_MIN_K
 #define SFT_OUTER_MIN_K 4
 #endif
 
-// unroll factor of the bin loops (4 keeps the Fresnel kernel at 5 waves per SIMD)
+// unroll factor of the Dirichlet bin loop
 #ifndef SFT_BIN_UNROLL
 #define SFT_BIN_UNROLL 4
 #endif
@@ -421,11 +421,12 @@ template <> struct PrecTraits<SFT_PREC_FP32_NAIVE> { using R = float; using Acc 
 
 __device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Order of the window bins in the FP32 contraction.  Wide windows (K >= SFT_WIDE_K) go from
-// the outside in (-K, K, -K+1, K-1, ..., 0), so that the running sum stays small until the
+// Order of the window bins in the Dirichlet contraction.  Wide windows (K >= SFT_WIDE_K) go
+// from the outside in (-K, K, -K+1, K-1, ..., 0), so that the running sum stays small until the
 // dominant central bins arrive and the rounding of the many small far-bin terms is not taken
 // against the full sum; narrow windows go left to right (same accuracy at that length, and
-// faster: consecutive bins share the loads' address arithmetic).
+// faster: consecutive bins share the loads' address arithmetic).  The Fresnel loop orders its
+// series segments from the edges inwards instead.
 #ifndef SFT_WIDE_K
 #define SFT_WIDE_K 16
 #endif
