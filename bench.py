@@ -51,9 +51,13 @@ OPS_DIRICHLET = 23          # sin(pi delta) / pi
 # Fresnel weights per bin and lane, by the series length the bin's endpoints need (two
 # endpoints each; p-+ = delta -+ beta/2 - j is 2): both endpoints at v = |p| sqrt(2/beta) >= 76
 # (no W term: 1/p, r^2, w, r w), >= 11 (one W term: 5 more), >= 4.5 (three W terms: 4 more),
-# else the 90-interval cubic table (|p| sqrt(2/beta), the offset in the interval, two Horner
-# chains of 3, the scale) and the stationary-point test
-OPS_BIN = {"w0": 2 + 2 * (1 + 3), "w1": 2 + 2 * (1 + 8), "w3": 2 + 2 * (1 + 12), "table": 2 + 2 * 11 + 2}
+# else the 90-interval quartic table (|p| sqrt(2/beta), the offset in the interval, two Horner
+# chains of 4, the scale) and the stationary-point test
+OPS_BIN = {"w0": 2 + 2 * (1 + 3), "w1": 2 + 2 * (1 + 8), "w3": 2 + 2 * (1 + 12), "table": 2 + 2 * 13 + 2}
+OPS_BIN_SERIES = 36         # central bin with |beta| <= 0.04 and |delta| <= 0.125: F(delta, beta)
+                            # from its series (two 7-term Horner chains in (pi delta)^2 with
+                            # beta-folded coefficients)
+SERIES_BETA, SERIES_DELTA = 0.04, 0.125
 OPS_BIN_STAT = 2 * 3 + 2 * 3 + 16 + 5 + 6   # stationary point inside the SFT: x^2/beta and its
                                             # reduction (FP64), the phasor, the term, folded into e(p-)
 OPS_BIN_DIR = 3                             # x = delta - j, 1/x, sin(pi delta)/pi x
@@ -79,7 +83,7 @@ def scan_census(mc, t_c, g_tmid, g_rows, T, K, beta_switch, tsun, g_first=None, 
     n = mc.size
     pick = np.arange(0, n, stride)
     total = 0.0
-    census = {"pairs": 0, "w0": 0, "w1": 0, "w3": 0, "table": 0, "stat": 0, "dirichlet_pairs": 0}
+    census = {"pairs": 0, "w0": 0, "w1": 0, "w3": 0, "table": 0, "stat": 0, "series": 0, "dirichlet_pairs": 0}
     nb = 2 * K + 1
     for i0 in range(0, pick.size, chunk):
         idx = pick[i0:i0 + chunk]
@@ -118,6 +122,11 @@ def scan_census(mc, t_c, g_tmid, g_rows, T, K, beta_switch, tsun, g_first=None, 
             else:
                 w0 = w1 = w3 = np.zeros_like(fres)
             tab = fres & ~w0 & ~w1 & ~w3
+            if jj == 0:
+                ser = fres & (b <= SERIES_BETA) & (np.abs(delta) <= SERIES_DELTA)
+                census["series"] += float(ser.sum())
+                ops += float(ser.sum()) * OPS_BIN_SERIES
+                w0, w1, w3, tab = w0 & ~ser, w1 & ~ser, w3 & ~ser, tab & ~ser
             stat = tab & (pm < 0) & (pp >= 0)
             for key, msk in (("w0", w0), ("w1", w1), ("w3", w3), ("table", tab)):
                 c_ = float(msk.sum())
@@ -304,7 +313,7 @@ def main():
                      "kernel": "scan_kernel", "kernel_ms": k_ms,
                      "alg_slots_per_launch": slots, "alg_slots_per_template_group": slots / census["pairs"],
                      "units": {"templates": w.n_templates, "timestamp_groups": n_groups, "sft_rows": w.n_sft},
-                     "bins_by_series": {k: census[k] / census["pairs"] for k in ("w0", "w1", "w3", "table", "stat")}},
+                     "bins_by_series": {k: census[k] / census["pairs"] for k in ("w0", "w1", "w3", "table", "stat", "series")}},
         "tuning": best.as_dict(),
         "graph_ms_per_step": graph_ms,
     }
@@ -363,7 +372,7 @@ def space_leg(args):
             "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
                          "frac": achieved / (PEAK_SLOTS / 1e12), "kernel": "scan_kernel", "kernel_ms": k_ms,
                          "alg_slots_per_launch": slots, "alg_slots_per_template_sft": slots / census["pairs"],
-                         "bins_by_series": {k: census[k] / census["pairs"] for k in ("w0", "w1", "w3", "table", "stat")}},
+                         "bins_by_series": {k: census[k] / census["pairs"] for k in ("w0", "w1", "w3", "table", "stat", "series")}},
             "tuning": best.as_dict(), "flagged_templates": int(np.sum(flags != 0))}
 
 

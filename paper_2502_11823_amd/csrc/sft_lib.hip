@@ -739,17 +739,21 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       const float tsc = 6.28318530717958648f * isq2b;         // 2 pi / sqrt(2 beta)
       const float bq = bp * kInvTwoPiF;                       // beta / (2 pi)
       const float dm = ds - 0.5f * bp, dp = ds + 0.5f * bp;   // p-+ of bin j are dm - j, dp - j
-      // E-+ = exp(i(-+pi delta + pi beta / 4))
-      float st, ct, sd, cd;
-      phasor(0.25 * kPi * bpos, st, ct);
+      // E- = exp(i(-pi delta + pi beta / 4)) from its own FP64-reduced phase (it scales every
+      // term of the SFT, the stationary ones included), exp(i pi delta), rho = exp(2 pi i delta)
+      // = E+ / E-, and E+ = E- rho
+      float emi, emr, sd, cd;
+      phasor(0.25 * kPi * bpos - kPi * ds64, emi, emr);
       phasor(kPi * ds64, sd, cd);
-      const float epr = cd * ct - sd * st, epi = sd * ct + cd * st;   // E+
-      const float emr = cd * ct + sd * st, emi = cd * st - sd * ct;   // E-
+      const float rr = fmaf(cd, cd, -sd * sd), ri = 2.0f * cd * sd;
+      const float epr = fmaf(emr, rr, -emi * ri), epi = fmaf(emr, ri, emi * rr);   // E+
       // 1 / beta and p- of bin 0 in FP64 for the stationary phase: FP32 estimate + two Newton steps
       double ib = (double)fast_rcp(bp);
       ib = ib * fma(-bpos, ib, 2.0);
       ib = ib * fma(-bpos, ib, 2.0);
       const double dm64 = ds64 - 0.5 * bpos;
+      // central bin from its direct series (small drift and small delta)
+      const bool cser = bp <= SFT_SERIES_BETA && fabsf(ds) <= SFT_SERIES_DELTA;
       // one row: sums of b e(p-) and b e(p+) (unused with several rows)
       float smr = 0.f, smi = 0.f, spr = 0.f, spi = 0.f;
       // Outer bins: jj >= jup or jj <= jdn puts both endpoints of a lane at least one bin
@@ -781,11 +785,11 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       // E-+ / 2 pi with the imaginary parts of the beta < 0 mirror
       const float eqr = kInvTwoPiF * emr, eqy = kInvTwoPiF * (neg ? -emi : emi);
       const float fqr = kInvTwoPiF * epr, fqy = kInvTwoPiF * (neg ? -epi : epi);
-      // rho = E+ / E- = exp(2 pi i delta) = (cd + i sd)^2 (conjugated by the mirror): the bin
-      // weight is (E- / 2 pi) (e(p-) - rho e(p+))
-      const float rhr = fmaf(cd, cd, -sd * sd), rhi = neg ? -2.0f * cd * sd : 2.0f * cd * sd;
+      // rho (conjugated by the mirror): the bin weight is (E- / 2 pi) (e(p-) - rho e(p+))
+      const float rhr = rr, rhi = neg ? -ri : ri;
       // One bin jj (jj = -j for beta < 0) of series tier TR: 0, 1 or 3 the asymptotic form cut
-      // after TR powers of W, 4 the table with the stationary-point check.
+      // after TR powers of W, 4 the table with the stationary-point check (nothing for the
+      // central bin of a small-drift lane, which is added after the loop).
       auto bin = [&](auto negc, auto checked, auto stgc, auto tierc, int jj) {
         constexpr bool NEG = decltype(negc)::value;
         constexpr bool CHK = decltype(checked)::value;
@@ -834,6 +838,11 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
             phasor(kPi * (hq - 2.0 * rint(0.5 * hq)), sr, cr);
             em.x += tsc * (cr + sr);
             em.y += NEG ? -tsc * (cr - sr) : tsc * (cr - sr);
+          }
+          if (jj == 0 && cser) {
+            // central bin of a small-drift lane: added after the loop from its series
+            em = make_float2(0.f, 0.f);
+            ep = make_float2(0.f, 0.f);
           }
         }
         if constexpr (ND >= 2) {
@@ -887,6 +896,22 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
           const R cr = cre[d];
           cre[d] = eqr * cr - eqy * cim[d];
           cim[d] = eqr * cim[d] + eqy * cr;
+        }
+      }
+      // Central bin of a lane with small drift and small delta: its weight F(delta, beta) from
+      // the direct series (the two endpoint terms are large there and cancel to a weight near
+      // 1), evaluated here, outside the bin loops, and contracted with each row's bin k0.
+      const int i_c = i0 + K;
+      if (cser && (stg || (i_c >= 0 && i_c < a.n_ext))) {
+        const float dl = (float)dm64 + 0.5f * bp;   // delta (mirrored for beta < 0)
+        const float2 F = fres_central_series(neg ? -dl : dl, neg ? -bp : bp);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          float bre, bim;
+          if (stg) BinIO<Bin>::load(sw + d * WST + (i_c - sb), bre, bim);
+          else BinIO<Bin>::load(rp[d] + i_c, bre, bim);
+          cre[d] = fmaf(bre, F.x, fmaf(-bim, F.y, cre[d]));
+          cim[d] = fmaf(bre, F.y, fmaf(bim, F.x, cim[d]));
         }
       }
     }

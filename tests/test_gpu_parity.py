@@ -108,6 +108,22 @@ def test_shuffled_bank_mixes_staged_and_gathered_windows(ground_small, K, kernel
     assert e.max() < 1e-6
 
 
+@pytest.mark.parametrize("n_det,pad", [(3, 1.5e5), (1, 1.5e5), (3, 100.0), (1, 100.0)])
+def test_largest_window_full_band(n_det, pad):
+    """K = 64 (the largest window), band from DC to Nyquist.  Far from merger (pad 1.5e5 s,
+    k0 ~ 43-49, drift ~0.004 bins) the windows reach below DC and take the mirrored bins, and
+    the central bin takes the small-drift series; near merger (pad 100 s, k0 ~ 250-725, drifts
+    up to 75 bins, inside beta/2 + 8 <= K) the lanes of a wavefront spread by tens of bins, so
+    some groups fit the LDS stage and others fall back to gathers."""
+    with np.errstate(divide="ignore"):   # the coloured PSD is infinite at DC: that bin is masked
+        w = synth.ground(seed=12, n_templates=300, n_slots=40, n_det=n_det, k_lo=0, k_hi=2049,
+                         t_end_pad=pad, mc_lo=1.2, mc_hi=1.5)
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=sft.K_MAX, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0)
+    compare(gpu_scan(data, w.bank, **kw), orc_scan(w, w.bank, **kw),
+            label="K=64 full band, %d det, pad %g s" % (n_det, pad))
+
+
 def test_fresnel_large_drift():
     """Templates close to merger: beta = fdot T^2 up to tens of bins, K = 32."""
     w = synth.ground(seed=8, n_templates=300, n_slots=40, n_det=1, k_lo=20, k_hi=1500,
