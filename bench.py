@@ -54,8 +54,8 @@ OPS_DIRICHLET = 23          # sin(pi delta) / pi
 # else the 90-interval quartic table (|p| sqrt(2/beta), the offset in the interval, two Horner
 # chains of 4, the scale) and the stationary-point test
 OPS_BIN = {"w0": 2 + 2 * (1 + 3), "w1": 2 + 2 * (1 + 8), "w3": 2 + 2 * (1 + 12), "table": 2 + 2 * 13 + 2}
-OPS_BIN_SERIES = 36         # central bin with |beta| <= 0.04 and |delta| <= 0.125: F(delta, beta)
-                            # from its series (two 7-term Horner chains in (pi delta)^2 with
+OPS_BIN_SERIES = 24         # central bin with |beta| <= 0.04 and |delta| <= 0.125: F(delta, beta)
+                            # from its series (two 4-term Horner chains in (pi delta)^2 with
                             # beta-folded coefficients)
 SERIES_BETA, SERIES_DELTA = 0.04, 0.125
 OPS_BIN_STAT = 2 * 3 + 2 * 3 + 16 + 5 + 6   # stationary point inside the SFT: x^2/beta and its

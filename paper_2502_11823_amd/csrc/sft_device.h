@@ -298,12 +298,12 @@ __device__ inline float2 fres_endpoint2(float p, float bq, float sq2ob, float ts
 }
 
 // ---------------------------------------------------------------- central bin, small drift
-// For |x| <= 1/2 and |beta| <= SFT_SERIES_BETA the kernel
+// For |x| <= SFT_SERIES_DELTA and |beta| <= SFT_SERIES_BETA the kernel
 //   F(x, beta) = int_{-1/2}^{1/2} exp(i (2 pi x s + pi beta s^2)) ds
 // is summed directly as sum_{n <= 3} (i pi beta)^n / n! M_2n(x), with the real moments
 //   M_2n(x) = int s^2n cos(2 pi x s) ds = 4^-n sum_k (-1)^k (pi x)^2k / ((2k)! (2n + 2k + 1))
-// (k <= 6; the dropped terms are below 1e-8 relative).  There, and for |x| <= SFT_SERIES_DELTA,
-// the two endpoint terms of the central bin grow as min(1 / (2 pi |x|), 0.7 / sqrt(2 beta)) and
+// (k <= 3; the dropped terms in beta and x together are below 6e-9 relative).  There the two
+// endpoint terms of the central bin grow as min(1 / (2 pi |x|), 0.7 / sqrt(2 beta)) and
 // cancel to a weight near 1, which would amplify their FP32 rounding up to tenfold at
 // beta ~ 0.005; the series has no such cancellation.  Beyond those bounds the amplification
 // stays below ~2.5 and the endpoint form is kept.
@@ -311,20 +311,20 @@ __device__ inline float2 fres_endpoint2(float p, float bq, float sq2ob, float ts
 #define SFT_SERIES_DELTA 0.125f
 __device__ inline float2 fres_central_series(float x, float beta)
 {
-  constexpr float c[4][7] = {
-    {1.000000000e+00f, -1.666666667e-01f, 8.333333333e-03f, -1.984126984e-04f, 2.755731922e-06f, -2.505210839e-08f, 1.605904384e-10f},
-    {8.333333333e-02f, -2.500000000e-02f, 1.488095238e-03f, -3.858024691e-05f, 5.636724387e-07f, -5.299484466e-09f, 3.479459498e-11f},
-    {1.250000000e-02f, -4.464285714e-03f, 2.893518519e-04f, -7.891414141e-06f, 1.192384005e-07f, -1.148221634e-09f, 7.675278304e-12f},
-    {2.232142857e-03f, -8.680555556e-04f, 5.918560606e-05f, -1.669337607e-06f, 2.583498677e-08f, -2.532841840e-10f, 1.716838568e-12f}};
+  constexpr float c[4][4] = {
+    {1.000000000e+00f, -1.666666667e-01f, 8.333333333e-03f, -1.984126984e-04f},
+    {8.333333333e-02f, -2.500000000e-02f, 1.488095238e-03f, -3.858024691e-05f},
+    {1.250000000e-02f, -4.464285714e-03f, 2.893518519e-04f, -7.891414141e-06f},
+    {2.232142857e-03f, -8.680555556e-04f, 5.918560606e-05f, -1.669337607e-06f}};
   const float px = kPiF * x;
   const float u = px * px;
   const float pb = kPiF * beta;
   // M0 + i pi beta M2 - (pi beta)^2 / 2 M4 - i (pi beta)^3 / 6 M6, as two Horner chains in u
   // whose coefficients take the beta terms on the fly (few live registers)
   const float h4 = -0.5f * pb * pb, h6 = pb * pb * (-1.0f / 6.0f);
-  float re = fmaf(h4, c[2][6], c[0][6]), im = fmaf(h6, c[3][6], c[1][6]);
+  float re = fmaf(h4, c[2][3], c[0][3]), im = fmaf(h6, c[3][3], c[1][3]);
 #pragma unroll
-  for (int k = 5; k >= 0; --k) {
+  for (int k = 2; k >= 0; --k) {
     re = fmaf(re, u, fmaf(h4, c[2][k], c[0][k]));
     im = fmaf(im, u, fmaf(h6, c[3][k], c[1][k]));
   }
