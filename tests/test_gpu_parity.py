@@ -124,6 +124,20 @@ def test_largest_window_full_band(n_det, pad):
             label="K=64 full band, %d det, pad %g s" % (n_det, pad))
 
 
+@pytest.mark.parametrize("K,n_det", [(8, 3), (8, 1), (32, 1), (32, 3)])
+def test_small_drift_central_bin(K, n_det):
+    """Far from merger (pad 1.5e5 s: drift ~0.004 bins, k0 ~ 43-49) every lane with
+    |delta| <= 1/8 takes its central bin from the small-drift series; K = 8 and K = 32 run
+    the compile-time windows (the one-row K = 32 kernel among them), with one and three rows
+    per timestamp group."""
+    w = synth.ground(seed=13, n_templates=300, n_slots=40, n_det=n_det, k_lo=1, k_hi=400,
+                     t_end_pad=1.5e5, mc_lo=1.2, mc_hi=1.5)
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=K, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0)
+    compare(gpu_scan(data, w.bank, **kw), orc_scan(w, w.bank, **kw),
+            label="small drift K=%d, %d det" % (K, n_det))
+
+
 def test_fresnel_large_drift():
     """Templates close to merger: beta = fdot T^2 up to tens of bins, K = 32."""
     w = synth.ground(seed=8, n_templates=300, n_slots=40, n_det=1, k_lo=20, k_hi=1500,
