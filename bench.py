@@ -183,7 +183,8 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=160, help="templates in the oracle sample (0 = skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--tuning", default="",
-                   help="block,chunk_groups,persistent: use this launch shape instead of autotuning")
+                   help="block,chunk_groups,persistent: use this launch shape instead of autotuning "
+                        "(the ground scan; with --space-only, the space scan)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only a plain device copy of known size (counter calibration)")
     p.add_argument("--surrogate-templates", type=int, default=1_000_000,
@@ -342,7 +343,13 @@ def space_leg(args):
     bank = sft.bank_to_device(w.bank)
     opts = sft.make_opts(K=K, kernel=kernel, precision="fp32_kahan", a_plus=1.0, a_cross=1.0)
     out = sft.alloc_out(w.n_templates)
-    best, best_ms = sft.autotune(data, bank, opts, out=out, reps=2)
+    if args.tuning and args.space_only:
+        b, c, p = (int(v) for v in args.tuning.split(","))
+        sft.set_tuning(data, block=b, chunk_groups=c, persistent=p)
+        best = sft.get_tuning(data)
+        print("fixed tuning %s" % best.as_dict(), file=sys.stderr, flush=True)
+    else:
+        best, best_ms = sft.autotune(data, bank, opts, out=out, reps=2)
     for _ in range(args.warmup):
         sft.template_bank_scan(data, bank, opts, out=out)
     torch.cuda.synchronize()
