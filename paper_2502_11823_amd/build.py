@@ -1,22 +1,56 @@
-"""Build libsft.so for gfx950 with hipcc (in-tree, next to this file)."""
+"""Build libsft.so for gfx950 with hipcc (in-tree, next to this file).
+
+Every .hip file of csrc/ is compiled to an object in parallel (the scan-kernel
+instantiations are spread over several translation units), then the objects are
+linked into one shared library.
+"""
+import glob
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsft.so")
-SOURCES = [os.path.join(CSRC, "sft_lib.hip"), os.path.join(CSRC, "sft_mlp.hip")]
+OBJ_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled on purpose (-packed-fp32-ops).
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
 
 
-def build_library(verbose: bool = False) -> str:
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def build_library(verbose: bool = False, jobs: int = 0) -> str:
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    srcs = sources()
+    objs = [os.path.join(OBJ_DIR, os.path.basename(s)[:-4] + ".o") for s in srcs]
+
+    def compile_one(so):
+        s, o = so
+        cmd = [HIPCC] + FLAGS + ["-c", "-o", o, s]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, cwd=CSRC, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
+        return s, r.returncode, out
+
+    failed = []
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for s, rc, out in ex.map(compile_one, zip(srcs, objs)):
+            if out.strip():
+                print(out, flush=True)
+            if rc != 0:
+                failed.append(s)
+    if failed:
+        raise RuntimeError("hipcc failed for %s" % ", ".join(os.path.basename(f) for f in failed))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + SOURCES
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, cwd=CSRC)
