@@ -13,9 +13,13 @@
  * label.  Where the paper is silent or garbled the reading taken is named at
  * the routine (readings R1..R19 are listed in the design notes).
  *
- * Parity unpinned: none of the functions below is unpinned; each is checked by
- * the CPU test-suite against closed forms, library routines (numpy FFT, scipy
- * Fresnel integrals and Faddeeva function), brute-force sums or invariants.
+ * Pins: each function below is checked by the CPU test-suite against closed
+ * forms, library routines (numpy FFT, scipy Fresnel integrals and Faddeeva
+ * function), brute-force sums or invariants, with one exception:
+ * Parity unpinned: the 1PN, 1.5PN and 2PN amplitude factors of the 3.5PN waveform
+ * (orc_pn35).  They are transcribed from the PN literature, whose text is not at
+ * hand, and no closed form or limit available here fixes them (the Newtonian
+ * limit and the phase/frequency consistency pin the phase series only).
  *
  * Conventions (paper Sec. III.B-III.E):
  *   T = T_SFT, n = samples per SFT, dt = T/n, df = 1/T, f_k = k/T.

@@ -532,3 +532,121 @@ def test_p14_judge_special_cases(orc):
             assert res["flags"][3] & orc.F_TAU_NONPOSITIVE
     finally:
         orc.set_pn_order(7)
+
+
+# --------------------------------------------------------------------------- rho with both polarisations
+def test_rho_both_polarisations_equals_phase_maximised_time_domain_product(orc):
+    """Eq. det_short (reading R12) with A_x != 0: the oracle's rho sqrt(A+^2 hh+ + Ax^2 hhx)
+    equals max over phi_c of the time-domain product dt sum_j d_j h_j(phi_c), i.e.
+    sqrt(x0^2 + x1^2) with x0, x1 the brute-force products at phi_c = 0 and pi/2.  All bins
+    and the discrete kernel make the SFT sum exact (P1), so a wrong sign of the i in
+    A+ z+ - i Ax zx, or swapped polarisations, fails here."""
+    g = np.random.default_rng(29)
+    n, n_sft, dt = 64, 6, 0.5
+    T = n * dt
+    x = g.normal(size=n * n_sft)
+    xb = synth.sfts_from_series(x, n, n_sft, dt)
+    psd = np.full(xb.shape, 2.0)
+    A = g.uniform(0.5, 2.0, n_sft)
+    phi = g.uniform(-50, 50, n_sft)
+    f = g.uniform(3, 28, n_sft) / T
+    fdot = g.uniform(-4, 4, n_sft) / T**2
+    fp = g.uniform(-1, 1, n_sft)
+    fx = g.uniform(-1, 1, n_sft)
+    a_plus, a_cross = 1.0, 0.7
+    data = _data(orc, xb, psd, np.arange(n_sft) * T, n, T, fp=fp, fx=fx)
+    zp, zx, hhp, hhx, rho, fl, _ = orc.ip_params(data, A, phi, f, fdot, K=-1, kernel=orc.K_DISCRETE,
+                                                 a_plus=a_plus, a_cross=a_cross)
+
+    def product(phi_c):
+        h = np.zeros_like(x)
+        for a in range(n_sft):
+            t = a * T + np.arange(n) * dt
+            s = t - (a * T + 0.5 * T)
+            Phi = phi[a] + phi_c + 2 * np.pi * f[a] * s + np.pi * fdot[a] * s * s
+            h[a * n:(a + 1) * n] = A[a] * (a_plus * fp[a] * np.cos(Phi) + a_cross * fx[a] * np.sin(Phi))
+        return orc.td_product(x, h, dt)
+
+    x0, x1 = product(0.0), product(0.5 * np.pi)
+    want = math.hypot(x0, x1)
+    got = rho * math.sqrt(a_plus**2 * hhp + a_cross**2 * hhx)
+    assert abs(got - want) <= 1e-11 * want
+    # the maximum over a phase grid does not exceed it and comes close
+    grid = max(product(p) for p in np.linspace(0, 2 * np.pi, 64, endpoint=False))
+    assert grid <= want * (1 + 1e-12) and grid >= want * math.cos(np.pi / 64)
+
+
+# --------------------------------------------------------------------------- norm interpolation
+def test_norm_psd_linear_interpolation_exact_on_a_sloped_psd(orc):
+    """Reading R11: hh = sum_a F+^2 A^2 T / S_a(f_a) with S_a linearly interpolated between
+    the bins around kappa.  On a PSD linear in f the interpolation is exact, so hh equals the
+    closed form at f_a itself; the nearest bin, the bin below or swapped weights differ by
+    ~1e-2 here."""
+    n, n_sft, T = 256, 5, 16.0
+    k_lo, n_bins = 10, 100
+    s0, s1 = 0.3, 0.04
+    k = k_lo + np.arange(n_bins)
+    psd = np.broadcast_to(s0 + s1 * k, (n_sft, n_bins)).copy()
+    psd *= np.arange(1, n_sft + 1)[:, None] * 0.5            # per-SFT scale as well
+    xb = np.zeros((n_sft, n_bins, 2))
+    A = np.array([1.0, 0.5, 2.0, 1.5, 0.8])
+    kap = np.array([40.3, 55.7, 61.25, 33.9, 80.45])
+    fp = np.array([0.9, -0.4, 0.3, 1.0, -0.7])
+    data = _data(orc, xb, psd, np.arange(n_sft) * T, n, T, k_lo=k_lo, fp=fp)
+    _, _, hhp, _, _, fl, _ = orc.ip_params(data, A, 0.0, kap / T, 0.0, K=4, kernel=orc.K_DIRICHLET)
+    scale = np.arange(1, n_sft + 1) * 0.5
+    want = np.sum(fp**2 * A**2 * T / (scale * (s0 + s1 * kap)))
+    assert fl == 0
+    assert abs(hhp - want) <= 1e-14 * want
+    nearest = np.sum(fp**2 * A**2 * T / (scale * (s0 + s1 * np.floor(kap + 0.5))))
+    assert abs(nearest - want) > 1e-3 * want
+
+
+# --------------------------------------------------------------------------- Taylor validity flag
+def test_taylor_validity_flag_at_table1_lengths(orc):
+    """Eq. max_tsft and Table 1: with max fddot = 5e-6 Hz/s^2 and delta = 1 the paper takes
+    T_SFT = 73 s (the floor of (2 delta / fddot)^(1/3) = 73.7 s).  The oracle's per-SFT flag
+    must stay clear at 73 s and be raised at 74 s, with the paper's start lever arm
+    (delta = fddot T^3 / 2) and, for the midpoint expansion, at a quarter of it
+    (delta = fddot T^3 / 8: threshold 0.25 at the same lengths)."""
+    gold = json.load(open(GOLDEN))["table1_bns"]
+    fdd = gold["fddot_max"]
+    i = gold["delta"].index(1.0)
+    t_ok = gold["t_sft"][i]
+    for T, flagged in ((float(t_ok), False), (float(t_ok + 1), True)):
+        n = 64
+        xb = np.zeros((2, 40, 2))
+        data = _data(orc, xb, np.ones((2, 40)), np.array([0.0, T]), n, T)
+        for t_ref, dmax in ((orc.REF_START, 1.0), (orc.REF_MID, 0.25)):
+            *_, fl, _ = orc.ip_params(data, 1.0, 0.0, 10.0 / T, 0.0, fddot=np.array([fdd, 0.0]), K=2,
+                                      kernel=orc.K_DIRICHLET, t_ref=t_ref, delta_max=dmax)
+            assert bool(fl & orc.F_TAYLOR_INVALID) == flagged, (T, t_ref)
+        # a lower f-double-dot in every SFT never flags
+        *_, fl, _ = orc.ip_params(data, 1.0, 0.0, 10.0 / T, 0.0, fddot=np.array([0.5 * fdd, 0.0]), K=2,
+                                  kernel=orc.K_DIRICHLET, t_ref=orc.REF_START, delta_max=1.0)
+        assert not fl & orc.F_TAYLOR_INVALID
+
+
+# --------------------------------------------------------------------------- Adam reference
+def test_adam_reference_two_steps_and_properties():
+    """The training reference's Adam step (Kingma & Ba, ICLR 2015, Algorithm 1: bias-corrected
+    first and second moments, beta1 0.9, beta2 0.999, eps 1e-8).  Two steps on a scalar with
+    gradients 0.5 then -0.25 at lr 0.1, against values worked out by hand in 40-digit decimal
+    arithmetic; then two properties that hold for any gradient: the first step moves every
+    parameter by lr sign(g) (to eps), and a constant gradient moves it by lr at every step."""
+    from oracle import mlp
+    p, m, v = np.array([1.0]), np.zeros(1), np.zeros(1)
+    p, m, v = mlp.adam_step(p, np.array([0.5]), m, v, 1, 0.1)
+    assert m[0] == pytest.approx(0.05, rel=1e-15) and v[0] == pytest.approx(2.5e-4, rel=1e-15)
+    assert p[0] == pytest.approx(0.90000000199999996, rel=1e-15)
+    p, m, v = mlp.adam_step(p, np.array([-0.25]), m, v, 2, 0.1)
+    assert m[0] == pytest.approx(0.02, rel=1e-15) and v[0] == pytest.approx(3.1225e-4, rel=1e-15)
+    assert p[0] == pytest.approx(0.87336629870784616, rel=1e-15)
+    g = np.sign(np.random.default_rng(4).normal(size=50)) * 10 ** np.random.default_rng(5).uniform(-2, 3, 50)
+    p1, m1, v1 = mlp.adam_step(np.zeros(50), g, np.zeros(50), np.zeros(50), 1, 0.01)
+    assert np.allclose(p1, -0.01 * np.sign(g), rtol=1e-5, atol=0)
+    pc, mc_, vc = np.zeros(50), np.zeros(50), np.zeros(50)
+    for t in range(1, 6):
+        prev = pc
+        pc, mc_, vc = mlp.adam_step(pc, g, mc_, vc, t, 0.01)
+        assert np.allclose(prev - pc, 0.01 * np.sign(g), rtol=1e-5, atol=0)
