@@ -178,6 +178,36 @@ typedef struct {
 sft_status sft_template_bank_scan(const sft_data* data, const sft_bank* bank, int64_t n_templates,
                                   const sft_opts* opts, sft_out* out, void* hip_stream);
 
+/* Size of the library-owned device array that is the workspace of
+ * sft_template_bank_scan_noalloc, on every GPU the library runs on. */
+#define SFT_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+/*
+ * sft_template_bank_scan_noalloc -- the bank scan for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same kernels and arguments as sft_template_bank_scan; the
+ * workspace (partial sums per template and chunk of timestamp groups, flags, the
+ * work-queue counter) lives in a file-scope device array of SFT_NOALLOC_SCRATCH_BYTES
+ * instead of the stream-ordered allocator.  The call makes no hipMalloc, hipFree or
+ * allocating library call.  Its device address is resolved once per GPU, on the first
+ * call made with that GPU current; every GPU that runs the library holds its own copy
+ * until the process ends.
+ * Launch shape: the handle's tuning, with fewer (larger) chunks when its workspace
+ * would not fit; results then agree with sft_template_bank_scan to rounding (the FP64
+ * combination of the partial sums runs over other chunks), not bitwise.
+ * All calls on one GPU share the array, which keeps the last call's contents: calls
+ * that overlap in time on one GPU (different streams or host threads) race and must be
+ * serialised by the caller; calls on one stream are ordered.  Must be called with the
+ * data's device current.
+ * Errors: those of sft_template_bank_scan; SFT_E_INVALID (data on another device);
+ * SFT_E_RANGE when a single chunk's partial sums (52 bytes per template) do not fit
+ * the array (more than about 1.29e6 templates); SFT_E_UNSUPPORTED for
+ * SFT_WF_SURROGATE (its template batches need about 1 GiB of workspace);
+ * SFT_E_DEVICE when the array's address cannot be resolved or a launch fails.
+ */
+sft_status sft_template_bank_scan_noalloc(const sft_data* data, const sft_bank* bank, int64_t n_templates,
+                                          const sft_opts* opts, sft_out* out, void* hip_stream);
+
 /*
  * Launch shape of the bank scan, kept per data handle (fields equal to 0 select the
  * automatic choice).  block: templates per workgroup, 64, 128 or 256 (default 256).

@@ -880,6 +880,66 @@ extern "C" sft_status sft_template_bank_scan(const sft_data* d, const sft_bank* 
   return SFT_OK;
 }
 
+// ---------------------------------------------------------------------------- allocation-free scan
+// Workspace of sft_template_bank_scan_noalloc: one file-scope array per GPU, held until the
+// process ends.  In host code `scratch` only names the symbol; its address on a device comes
+// from hipGetSymbolAddress with that device current (each GPU has its own copy), resolved once
+// per device and kept in g_scratch_ptr.  Only that address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SFT_NOALLOC_SCRATCH_BYTES];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static sft_status scratch_address(int dev, void** out)
+{
+  if (dev < 0 || dev >= kMaxDevices) return fail(SFT_E_RANGE, "scan (no-alloc): device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SFT_E_DEVICE, "scan (no-alloc): hipGetSymbolAddress: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SFT_OK;
+}
+
+extern "C" sft_status sft_template_bank_scan_noalloc(const sft_data* d, const sft_bank* bank, int64_t n,
+                                                     const sft_opts* o, sft_out* out, void* hip_stream)
+{
+  sft_status s = validate_scan(d, o);
+  if (s != SFT_OK) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK || n == 0) return s;
+  if (o->waveform == SFT_WF_SURROGATE)
+    return fail(SFT_E_UNSUPPORTED, "scan (no-alloc): the surrogate waveform needs its batch workspace");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != d->device)
+    return fail(SFT_E_INVALID, "scan (no-alloc): the data live on device %d, not on the current device", d->device);
+  // the handle's launch shape, with fewer (larger) chunks when its partial sums would not fit
+  sft_tuning t = d->tune;
+  Prepared P;
+  if ((s = prepare_scan(d, bank, n, o, t, P)) != SFT_OK) return s;
+  if (P.ws_bytes > SFT_NOALLOC_SCRATCH_BYTES) {
+    const size_t per_chunk = (P.part_bytes + P.flag_bytes) / (size_t)P.a.n_chunks;   // bytes per chunk
+    const size_t room = SFT_NOALLOC_SCRATCH_BYTES - 512;   // counter slot and alignment
+    const int64_t nc_max = (int64_t)(room / per_chunk);
+    if (nc_max < 1)
+      return fail(SFT_E_RANGE, "scan (no-alloc): %lld templates need %zu bytes of partial sums, more than the %u-byte scratch",
+                  (long long)n, per_chunk, (unsigned)SFT_NOALLOC_SCRATCH_BYTES);
+    if (t.block == 0 && t.chunk_groups == 0 && t.persistent == 0) t.persistent = 1;   // keep the automatic grid
+    t.chunk_groups = (int32_t)((d->n_groups + nc_max - 1) / nc_max);
+    if ((s = prepare_scan(d, bank, n, o, t, P)) != SFT_OK) return s;
+    if (P.ws_bytes > SFT_NOALLOC_SCRATCH_BYTES)
+      return fail(SFT_E_RANGE, "scan (no-alloc): workspace of %zu bytes exceeds the scratch", P.ws_bytes);
+  }
+  void* ws = nullptr;
+  if ((s = scratch_address(dev, &ws)) != SFT_OK) return s;
+  hipError_t e = enqueue_scan(P, ws, out, (hipStream_t)hip_stream, false);
+  if (e != hipSuccess) return fail(SFT_E_DEVICE, "scan (no-alloc): launch failed: %s", hipGetErrorString(e));
+  return SFT_OK;
+}
+
 // ---------------------------------------------------------------------------- tuning
 extern "C" sft_status sft_get_tuning(const sft_data* d, sft_tuning* t)
 {

@@ -77,7 +77,8 @@ EXPORTS = ["sft_load_data", "sft_free_data", "sft_default_opts", "sft_template_b
            "sft_get_tuning", "sft_set_tuning", "sft_autotune", "sft_plan_create", "sft_plan_launch",
            "sft_plan_destroy", "sft_surrogate_param_count", "sft_surrogate_create", "sft_surrogate_free",
            "sft_surrogate_get_params", "sft_surrogate_targets", "sft_surrogate_loss_grad", "sft_surrogate_adam",
-           "sft_surrogate_train", "sft_surrogate_infer"]
+           "sft_surrogate_train", "sft_surrogate_infer", "sft_template_bank_scan_noalloc"]
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 _lib = None
 
@@ -100,6 +101,8 @@ def lib():
     L.sft_template_bank_scan.argtypes = [P, ctypes.POINTER(Bank), ctypes.c_int64, ctypes.POINTER(Opts),
                                          ctypes.POINTER(Out), P]
     L.sft_template_bank_scan.restype = ctypes.c_int32
+    L.sft_template_bank_scan_noalloc.argtypes = L.sft_template_bank_scan.argtypes
+    L.sft_template_bank_scan_noalloc.restype = ctypes.c_int32
     D = ctypes.c_double
     L.sft_inner_product.argtypes = [P, D, D, D, D, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Opts),
                                     P, P, P, P, P, P]
@@ -282,6 +285,17 @@ def template_bank_scan(data: SFTData, bank_t, opts: Opts, out=None, stream=None,
     o = _out_struct(out)
     _check(lib().sft_template_bank_scan(data.handle, ctypes.byref(b), n, ctypes.byref(opts),
                                         ctypes.byref(o), _stream_ptr(stream)))
+    return out
+
+
+def template_bank_scan_noalloc(data: SFTData, bank_t, opts: Opts, out, stream=None, n=None):
+    """Asynchronous bank scan whose workspace is the library's own device array (no device
+    allocation by the library; ``out`` must be given)."""
+    n = int(bank_t["mc"].numel()) if n is None else int(n)
+    b = _bank_struct(bank_t)
+    o = _out_struct(out)
+    _check(lib().sft_template_bank_scan_noalloc(data.handle, ctypes.byref(b), n, ctypes.byref(opts),
+                                                ctypes.byref(o), _stream_ptr(stream)))
     return out
 
 
