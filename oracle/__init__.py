@@ -25,6 +25,7 @@ REF_MID, REF_START = 0, 1
 WF_NEWTON, WF_PN35, WF_SURROGATE = 0, 1, 2
 F_OUT_OF_BAND, F_TAU_NONPOSITIVE, F_TAYLOR_INVALID, F_NONFINITE, F_EMPTY = 1, 2, 4, 8, 64
 F_SURROGATE_FALLBACK = 32
+F_FSTAT_DEGENERATE = 128
 
 # GM_sun / c^3 in seconds (IAU 2015 nominal solar mass parameter)
 T_SUN = 4.925490947641267e-6
@@ -63,10 +64,10 @@ def _load():
     lib.orc_waveform.argtypes = [Int, D, D, D, D, D, D, P]
     lib.orc_waveform_array.argtypes = [Int, D, D, D, D, P, L, D, P]
     lib.orc_ip_params.argtypes = [L, L, D, L, L, P, P, P, P, P, P, P, P, P, P,
-                                  Int, Int, Int, D, D, D, D, Int, P, P, P]
+                                  Int, Int, Int, D, D, D, D, Int, Int, P, P, P]
     lib.orc_scan.argtypes = [L, L, D, L, L, P, P, P, P, P,
                              L, Int, P, P, P, P, P, P,
-                             Int, Int, Int, D, D, D, D, D, Int, P, P, P, P]
+                             Int, Int, Int, D, D, D, D, D, Int, Int, P, P, P, P]
     lib.orc_set_surrogate.argtypes = [Int, Int, P, P]
     lib.orc_mlp_param_count.argtypes = [Int, Int]
     lib.orc_mlp_param_count.restype = L
@@ -202,31 +203,36 @@ class SFTData:
 
 def ip_params(data: SFTData, A, phi, f, fdot, use=None, fddot=None, K=4, kernel=K_AUTO,
               t_ref=REF_MID, beta_switch=1e-7, a_plus=1.0, a_cross=0.0, delta_max=0.0,
-              compensated=True):
+              compensated=True, fstat=False, full=False):
     """Coherent sum for one template from per-SFT waveform quantities (Eq. efficient).
 
-    Returns (z_plus, z_cross, hh_plus, hh_cross, rho, flags, tie)."""
+    Returns (z_plus, z_cross, hh_plus, hh_cross, rho, flags, tie); with full=True a dict
+    that also holds the cross norm hhpx and 2F (when fstat)."""
     n = data.n_sft
     use = np.ones(n, np.uint8) if use is None else np.ascontiguousarray(use, dtype=np.uint8)
     A, phi, f, fdot = (_f64(np.broadcast_to(v, (n,))) for v in (A, phi, f, fdot))
     fddot = None if fddot is None else _f64(np.broadcast_to(fddot, (n,)))
-    out = np.empty(7)
+    out = np.empty(9)
     fl = np.zeros(1, np.uint32)
     tie = np.zeros(1)
     _load().orc_ip_params(*data._args(), _ptr(data.x_bins), _ptr(data.psd), _ptr(data.fplus),
                           _ptr(data.fcross), _ptr(A), _ptr(phi), _ptr(f), _ptr(fdot), _ptr(fddot),
                           _ptr(use), int(K), int(kernel), int(t_ref), float(beta_switch),
                           float(a_plus), float(a_cross), float(delta_max), int(compensated),
-                          _ptr(out), _ptr(fl), _ptr(tie))
+                          int(bool(fstat)), _ptr(out), _ptr(fl), _ptr(tie))
+    if full:
+        return {"zp": out[0] + 1j * out[1], "zx": out[2] + 1j * out[3], "hhp": out[4], "hhx": out[5],
+                "rho": out[6], "hhpx": out[7], "twoF": out[8], "flags": int(fl[0]), "tie": float(tie[0])}
     return (out[0] + 1j * out[1], out[2] + 1j * out[3], out[4], out[5], out[6], int(fl[0]), float(tie[0]))
 
 
 def scan(data: SFTData, mc, t_c, phi_c=None, q=None, a_first=None, a_last=None, K=4,
          kernel=K_AUTO, t_ref=REF_MID, beta_switch=1e-7, a_plus=1.0, a_cross=0.0,
-         tsun=T_SUN, delta_max=0.0, compensated=True, wf=WF_NEWTON):
+         tsun=T_SUN, delta_max=0.0, compensated=True, wf=WF_NEWTON, fstat=False):
     """Template-bank SFT inner products (Eq. efficient), one template per entry.
 
-    Returns a dict of numpy arrays: zp, zx (complex), hhp, hhx, rho, flags, tie."""
+    Returns a dict of numpy arrays: zp, zx (complex), hhp, hhx, rho, flags, tie, mismatch,
+    and with fstat=True the cross norm hhpx and the F-statistic twoF (Sec. II.B)."""
     mc = _f64(np.atleast_1d(mc))
     m = mc.size
     t_c = _f64(np.broadcast_to(t_c, (m,)))
@@ -234,7 +240,7 @@ def scan(data: SFTData, mc, t_c, phi_c=None, q=None, a_first=None, a_last=None, 
     q = None if q is None else _f64(np.broadcast_to(q, (m,)))
     af = None if a_first is None else np.ascontiguousarray(np.broadcast_to(a_first, (m,)), dtype=np.int32)
     al = None if a_last is None else np.ascontiguousarray(np.broadcast_to(a_last, (m,)), dtype=np.int32)
-    out = np.empty((m, 7))
+    out = np.empty((m, 9))
     fl = np.zeros(m, np.uint32)
     tie = np.zeros(m)
     mm = np.zeros(m)
@@ -242,13 +248,17 @@ def scan(data: SFTData, mc, t_c, phi_c=None, q=None, a_first=None, a_last=None, 
                           _ptr(data.fplus), _ptr(data.fcross), m, int(wf), _ptr(mc), _ptr(q),
                           _ptr(t_c), _ptr(phi_c), _ptr(af), _ptr(al), int(K), int(kernel),
                           int(t_ref), float(beta_switch), float(a_plus), float(a_cross),
-                          float(tsun), float(delta_max), int(compensated),
+                          float(tsun), float(delta_max), int(compensated), int(bool(fstat)),
                           _ptr(out), _ptr(fl), _ptr(tie), _ptr(mm))
     if rc != 0:
         raise MemoryError("oracle scan failed")
-    return {"zp": out[:, 0] + 1j * out[:, 1], "zx": out[:, 2] + 1j * out[:, 3],
-            "hhp": out[:, 4], "hhx": out[:, 5], "rho": out[:, 6], "flags": fl, "tie": tie,
-            "mismatch": mm}
+    res = {"zp": out[:, 0] + 1j * out[:, 1], "zx": out[:, 2] + 1j * out[:, 3],
+           "hhp": out[:, 4], "hhx": out[:, 5], "rho": out[:, 6], "flags": fl, "tie": tie,
+           "mismatch": mm}
+    if fstat:
+        res["hhpx"] = out[:, 7]
+        res["twoF"] = out[:, 8]
+    return res
 
 
 # --------------------------------------------------------------------------- surrogate

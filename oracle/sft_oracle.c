@@ -36,6 +36,9 @@
  *       ([d,h]) = A+ Re z_+ + Ax Im z_x
  *   Norm (reading R11):  hh_+ = sum_a F+_a^2 A_a^2 T / S_a(f_a)  (hh_x likewise)
  *   SNR  (Eq. det_short, reading R12):  rho = |A+ z_+ - i Ax z_x| / sqrt(A+^2 hh_+ + Ax^2 hh_x)
+ *   F-statistic (Sec. II.B, Eq. det_long and the maximisation over c_nu that follows it),
+ *   with a = F+ and b = Fx of each SFT:  x_nu = <x, h_nu> = (Re z_+, Re z_x, Im z_+, Im z_x),
+ *   M_nu,mu = <h_nu, h_mu>, 2F = max_c 2 (c.x - c.M.c / 2) = x.M^{-1}.x (reading R25).
  */
 #define _GNU_SOURCE
 #include <complex.h>
@@ -60,7 +63,8 @@ enum {
   ORC_F_TAYLOR_INVALID = 4u,
   ORC_F_NONFINITE = 8u,
   ORC_F_SURROGATE_FALLBACK = 32u,
-  ORC_F_EMPTY = 64u
+  ORC_F_EMPTY = 64u,
+  ORC_F_FSTAT_DEGENERATE = 128u
 };
 
 /* ------------------------------------------------------------------------- */
@@ -499,15 +503,82 @@ typedef struct {
   double a_plus, a_cross;
   double delta_max;  /* Taylor-validity threshold (Eq. max_tsft), <= 0 disables */
   int compensated;
+  int fstat;         /* 1: also the cross norm and the F-statistic (flags FSTAT_DEGENERATE) */
 } orc_opts;
 
-/* Per-template result: out[0..6] = Re z+, Im z+, Re zx, Im zx, hh+, hhx, rho. */
+/* Resolvability threshold of the four amplitudes (reading R25): the F-statistic inverts M
+ * when det N >= ORC_FSTAT_EPS * A * B for the 2x2 block N = [[A, C], [C, B]] of M;
+ * below it the responses a and b are nearly parallel over the template's SFTs. */
+#define ORC_FSTAT_EPS 1e-2
+
+/* Solve the n x n system M c = x (row-major M, n <= 4) by Gaussian elimination with
+ * partial pivoting; returns 0, or -1 on a zero pivot. */
+static int orc_solve(int n, const double *Min, const double *xin, double *c)
+{
+  double M[4][5];
+  for (int i = 0; i < n; i++) {
+    for (int j = 0; j < n; j++) M[i][j] = Min[i * n + j];
+    M[i][n] = xin[i];
+  }
+  for (int k = 0; k < n; k++) {
+    int p = k;
+    for (int i = k + 1; i < n; i++)
+      if (fabs(M[i][k]) > fabs(M[p][k])) p = i;
+    if (M[p][k] == 0.0) return -1;
+    if (p != k)
+      for (int j = 0; j <= n; j++) { double t = M[k][j]; M[k][j] = M[p][j]; M[p][j] = t; }
+    for (int i = k + 1; i < n; i++) {
+      double f = M[i][k] / M[k][k];
+      for (int j = k; j <= n; j++) M[i][j] -= f * M[k][j];
+    }
+  }
+  for (int i = n - 1; i >= 0; i--) {
+    double v = M[i][n];
+    for (int j = i + 1; j < n; j++) v -= M[i][j] * c[j];
+    c[i] = v / M[i][i];
+  }
+  return 0;
+}
+
+/* 2F for amplitudes x_nu = <x, h_nu> and the norms A = sum a^2 w, B = sum b^2 w,
+ * C = sum a b w, w = A_a^2 T / S_a(f_a) (Sec. II.B).  The four functions of Eq. det_long
+ * are A a cos(phi), A b cos(phi), A a sin(phi), A b sin(phi); within an SFT the cos-sin
+ * products average out under the narrow-band norm of reading R11, so
+ *   M = [[A, C, 0, 0], [C, B, 0, 0], [0, 0, A, C], [0, 0, C, B]],
+ * and the maximum over c of c.x - c.M.c/2 is reached at M c = x, where 2F = x.c.
+ * Reading R25: when det N < ORC_FSTAT_EPS A B (a, b nearly proportional, e.g. one detector
+ * over much less than a day) M is nearly singular and only one pattern is resolvable: the
+ * statistic is then the maximum over the two amplitudes of the dominant pattern u (unit
+ * eigenvector of N with eigenvalue lam, found by the Jacobi rotation of N), i.e.
+ * 2F = ((u.x_cos)^2 + (u.x_sin)^2) / lam, and *degenerate is set. */
+static double orc_fstat(const double x[4], double A, double B, double C, int *degenerate)
+{
+  *degenerate = 0;
+  if (!(A > 0.0) && !(B > 0.0)) return 0.0;
+  double D = A * B - C * C;
+  if (D >= ORC_FSTAT_EPS * A * B && D > 0.0) {
+    double M[16] = {A, C, 0, 0,  C, B, 0, 0,  0, 0, A, C,  0, 0, C, B};
+    double c[4];
+    if (orc_solve(4, M, x, c) == 0) return x[0] * c[0] + x[1] * c[1] + x[2] * c[2] + x[3] * c[3];
+  }
+  *degenerate = 1;
+  double th = 0.5 * atan2(2.0 * C, A - B);
+  double u0 = cos(th), u1 = sin(th);
+  double lam = A * u0 * u0 + 2.0 * C * u0 * u1 + B * u1 * u1;
+  if (!(lam > 0.0)) return 0.0;
+  double pc = u0 * x[0] + u1 * x[1], ps = u0 * x[2] + u1 * x[3];
+  return (pc * pc + ps * ps) / lam;
+}
+
+/* Per-template result: out[0..8] = Re z+, Im z+, Re zx, Im zx, hh+, hhx, rho, hh+x, 2F
+ * (the last two 0 unless o->fstat). */
 static void orc_template_sum(const orc_data *D, const orc_opts *o,
                              const double *A, const double *phi, const double *f,
                              const double *fdot, const double *fddot, const unsigned char *use,
                              double *out, uint32_t *flags, double *tie)
 {
   orc_sum zpr = {0, 0, 0}, zpi = {0, 0, 0}, zxr = {0, 0, 0}, zxi = {0, 0, 0}, hp = {0, 0, 0}, hx = {0, 0, 0};
+  orc_sum hpx = {0, 0, 0};
   uint32_t fl = 0;
   double tie_min = 1.0;
   double T = D->T;
@@ -563,6 +634,7 @@ static void orc_template_sum(const orc_data *D, const orc_opts *o,
     double hterm = A[a] * A[a] * T / S;
     orc_sum_add(&hp, fpa * fpa * hterm);
     orc_sum_add(&hx, fxa * fxa * hterm);
+    orc_sum_add(&hpx, fpa * fxa * hterm);
   }
   int c = o->compensated;
   out[0] = orc_sum_get(&zpr, c);
@@ -582,7 +654,18 @@ static void orc_template_sum(const orc_data *D, const orc_opts *o,
   } else {
     out[6] = sqrt(re * re + im * im) / sqrt(hh);
   }
-  for (int i = 0; i < 7; i++)
+  out[7] = out[8] = 0.0;
+  if (o->fstat) {
+    /* F-statistic (Sec. II.B): x_nu = <x, h_nu> for h_nu = A (a cos, b cos, a sin, b sin)(phi),
+     * with a = F+, b = Fx: the cos parts are the real and the sin parts the imaginary parts
+     * of z_+ and z_x (the projector of Sec. II.A with A+ = 1 or Ax = 1). */
+    double x[4] = {out[0], out[2], out[1], out[3]};
+    int deg = 0;
+    out[7] = orc_sum_get(&hpx, c);
+    out[8] = orc_fstat(x, out[4], out[5], out[7], &deg);
+    if (deg) fl |= ORC_F_FSTAT_DEGENERATE;
+  }
+  for (int i = 0; i < 9; i++)
     if (!isfinite(out[i])) fl |= ORC_F_NONFINITE;
   *flags = fl;
   if (tie) *tie = tie_min;
@@ -596,10 +679,10 @@ int orc_ip_params(long n_sft, long n, double T, long k_lo, long n_bins,
                   const double *A, const double *phi, const double *f, const double *fdot,
                   const double *fddot, const unsigned char *use,
                   int K, int kernel, int t_ref, double beta_switch, double a_plus, double a_cross,
-                  double delta_max, int compensated, double *out, uint32_t *flags, double *tie)
+                  double delta_max, int compensated, int fstat, double *out, uint32_t *flags, double *tie)
 {
   orc_data D = {n_sft, n, T, k_lo, n_bins, xb, psd, fp, fx};
-  orc_opts o = {K, kernel, t_ref, beta_switch, a_plus, a_cross, delta_max, compensated};
+  orc_opts o = {K, kernel, t_ref, beta_switch, a_plus, a_cross, delta_max, compensated, fstat};
   orc_template_sum(&D, &o, A, phi, f, fdot, fddot, use, out, flags, tie);
   return 0;
 }
@@ -615,11 +698,11 @@ int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
              long n_tmpl, int wf, const double *mc, const double *q, const double *t_c,
              const double *phi_c, const int32_t *a_first, const int32_t *a_last,
              int K, int kernel, int t_ref, double beta_switch, double a_plus, double a_cross,
-             double tsun, double delta_max, int compensated,
+             double tsun, double delta_max, int compensated, int fstat,
              double *out, uint32_t *flags, double *tie, double *mismatch)
 {
   orc_data D = {n_sft, n, T, k_lo, n_bins, xb, psd, fp, fx};
-  orc_opts o = {K, kernel, t_ref, beta_switch, a_plus, a_cross, delta_max, compensated};
+  orc_opts o = {K, kernel, t_ref, beta_switch, a_plus, a_cross, delta_max, compensated, fstat};
   int err = 0;
 #pragma omp parallel
   {
@@ -675,7 +758,7 @@ int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
         A[a] = w[0]; ph[a] = w[1]; fr[a] = w[2]; fd[a] = w[3]; fdd[a] = w[4];
         use[a] = 1;
       }
-      orc_template_sum(&D, &o, A, ph, fr, fd, fdd, use, out + 7 * m, flags + m, tie ? tie + m : NULL);
+      orc_template_sum(&D, &o, A, ph, fr, fd, fdd, use, out + 9 * m, flags + m, tie ? tie + m : NULL);
       flags[m] |= extra;
     }
     free(buf);
