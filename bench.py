@@ -150,8 +150,8 @@ def scan_census(mc, t_c, g_tmid, g_rows, T, K, beta_switch, tsun, g_first=None, 
 PEAK_SLOTS = 256 * 128 * 2.4e9
 
 
-KERNEL_SOURCES = ["paper_2502_11823_amd/csrc/sft_lib.hip", "paper_2502_11823_amd/csrc/sft_device.h",
-                  "paper_2502_11823_amd/csrc/fresnel_table.h"]
+KERNEL_SOURCES = ["paper_2502_11823_amd/csrc/sft_scan.h", "paper_2502_11823_amd/csrc/sft_scan_args.h",
+                  "paper_2502_11823_amd/csrc/sft_device.h", "paper_2502_11823_amd/csrc/fresnel_table.h"]
 COUNTERS = "profiles/scan_kernel_ground_counters.md"
 
 
@@ -195,6 +195,7 @@ def parse():
     p.add_argument("--space-templates", type=int, default=200_000,
                    help="templates of the space-based leg (0 = skip the leg)")
     p.add_argument("--space-only", action="store_true", help="run only the space-based leg")
+    p.add_argument("--no-fstat", action="store_true", help="skip the F-statistic leg")
     p.add_argument("--paper-shapes", action="store_true",
                    help="context only: time banks shaped like the paper's timing runs and exit")
     return p.parse_args()
@@ -322,12 +323,52 @@ def main():
 
     if not args.no_cpu_baseline and args.cpu_sample > 0:
         res["cpu_baseline"] = cpu_baseline(w, out, args.cpu_sample, K, kernel)
+    if not args.no_fstat:
+        res["fstat"] = fstat_leg(args, w, data, bank, opts, K)
     del out, bank, data
     if args.space_templates > 0:
         res["space"] = space_leg(args)
     if args.surrogate_templates > 0:
         res["surrogate"] = surrogate_leg(args)
     print(json.dumps(res), flush=True)
+
+
+def fstat_leg(args, w, data, bank, opts, K):
+    """The F-statistic form (Sec. II.B) on the same ground bank and launch shape: z, the three
+    norms and 2F per template; a seeded sample of 40 templates is checked against the oracle."""
+    import torch
+    import oracle
+    from paper_2502_11823_amd import sft
+    out = sft.alloc_out(w.n_templates, fstat=True)
+    for _ in range(args.warmup):
+        sft.template_bank_scan(data, bank, opts, out=out)
+    torch.cuda.synchronize()
+    sft.kernel_timing(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sft.template_bank_scan(data, bank, opts, out=out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k_ms = float(np.mean(sft.kernel_times(args.steps)))
+    sft.kernel_timing(0)
+    f2 = out["twoF"].cpu().numpy()
+    flags = out["flags"].cpu().numpy().astype(np.uint32)
+    idx = np.sort(np.random.default_rng(777).choice(w.n_templates, 40, replace=False))
+    b = w.subset(idx)
+    od = oracle.SFTData(w.t_start, w.n_samples, w.t_sft, w.k_lo, w.x_bins, w.psd, w.fplus, w.fcross)
+    ref = oracle.scan(od, b["mc"], b["t_c"], phi_c=b["phi_c"], K=K, kernel=oracle.K_AUTO, a_plus=1.0,
+                      a_cross=1.0, fstat=True)
+    err = float(np.max(np.abs(f2[idx] - ref["twoF"]) / np.maximum(ref["twoF"], 4.0)))
+    value = w.n_templates * args.steps / elapsed
+    print("fstat: %.3f ms/step (kernel %.3f ms), %.3e IP/s, max e(2F) %.2e on 40 templates"
+          % (1e3 * elapsed / args.steps, k_ms, value, err), file=sys.stderr, flush=True)
+    return {"workload": "F-statistic form of the ground scan (same data, bank, K, launch shape): z+, zx, "
+                        "hh+, hhx, hh+x and 2F = x.M^-1.x per template",
+            "value": value, "unit": "IP/s", "ms_per_step": 1e3 * elapsed / args.steps, "kernel_ms": k_ms,
+            "twoF_median": float(np.median(f2)), "twoF_mean": float(np.mean(f2)),
+            "degenerate_frac": float(np.mean((flags & sft.FLAG_FSTAT_DEGENERATE) != 0)),
+            "max_err_2F_vs_oracle_40": err}
 
 
 def space_leg(args):

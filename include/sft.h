@@ -67,7 +67,10 @@ enum {
   SFT_FLAG_TAYLOR_INVALID = 4u,   /* fddot T^3 / 8 > delta_max in some SFT (Eq. max_tsft, midpoint lever arm) */
   SFT_FLAG_NONFINITE = 8u,        /* an output is not finite */
   SFT_FLAG_SURROGATE_FALLBACK = 32u, /* surrogate judged worse than the tolerance: 3.5PN waveform used */
-  SFT_FLAG_EMPTY = 64u            /* no SFT contributed to the norm; rho is set to 0 */
+  SFT_FLAG_EMPTY = 64u,           /* no SFT contributed to the norm; rho is set to 0 */
+  SFT_FLAG_FSTAT_DEGENERATE = 128u /* F-statistic form only: the weighted response vectors (F+_a) and
+                                     (Fx_a) are within ~5.7 degrees of parallel (det < 1e-2 hh+ hhx);
+                                     2F keeps the dominant pattern only (see sft_out.twoF) */
 };
 
 /* Largest window half-width K supported by the scan. */
@@ -149,7 +152,22 @@ typedef struct {
 /* Outputs, DEVICE memory owned by the caller: zp, zx are [n][2] (re, im);
  * hhp, hhx, rho are [n]; flags is [n].  mismatch [n] may be NULL; with the surrogate
  * waveform it receives each template's judge mismatch (see SFT_WF_SURROGATE below),
- * other waveforms leave it untouched. */
+ * other waveforms leave it untouched.
+ *
+ * F-statistic (Sec. II.B, Eq. det_long and the maximisation over the four amplitudes c_nu):
+ * when twoF [n] is not NULL the scan runs its F-statistic form, which reads the antenna
+ * patterns F+_a, Fx_a of each SFT row as the functions a(t), b(t) of Eq. det_long and writes
+ *   hhpx = sum_a F+_a Fx_a A_a^2 T / S_a(f_a)       (when hhpx [n] is not NULL),
+ *   2F   = x.M^{-1}.x,  x = (Re z+, Re zx, Im z+, Im zx) = <x, h_nu> for
+ *          h_nu = A (a cos phi, b cos phi, a sin phi, b sin phi),
+ *          M = [[N, 0], [0, N]], N = [[hh+, hh+x], [hh+x, hhx]] (cos-sin products vanish
+ *          under the narrow-band norm), i.e. twice the maximum over c of c.x - c.M.c/2.
+ * When det N < 1e-2 hh+ hhx (patterns nearly parallel, e.g. one detector over much less than
+ * a day) only the dominant eigenvector u of N (eigenvalue lambda) is kept:
+ * 2F = ((u.x_cos)^2 + (u.x_sin)^2) / lambda, flagged SFT_FLAG_FSTAT_DEGENERATE.  In noise 2F
+ * follows chi^2 with 4 degrees of freedom.  The F-statistic form keeps the three norm sums in
+ * FP64 and exists for the Newtonian waveform with FP32-Kahan sums on F32 data or FP64 sums
+ * on F64 data (otherwise SFT_E_UNSUPPORTED); z+, zx are bitwise those of the plain scan. */
 typedef struct {
   double* zp;
   double* zx;
@@ -158,6 +176,8 @@ typedef struct {
   double* rho;
   uint32_t* flags;
   double* mismatch;
+  double* hhpx;
+  double* twoF;
 } sft_out;
 
 /*
@@ -200,8 +220,9 @@ sft_status sft_template_bank_scan(const sft_data* data, const sft_bank* bank, in
  * serialised by the caller; calls on one stream are ordered.  Must be called with the
  * data's device current.
  * Errors: those of sft_template_bank_scan; SFT_E_INVALID (data on another device);
- * SFT_E_RANGE when a single chunk's partial sums (52 bytes per template) do not fit
- * the array (more than about 1.29e6 templates); SFT_E_UNSUPPORTED for
+ * SFT_E_RANGE when a single chunk's partial sums (52 bytes per template, 60 in the
+ * F-statistic form) do not fit the array (more than about 1.29e6 templates, 1.12e6 in
+ * the F-statistic form); SFT_E_UNSUPPORTED for
  * SFT_WF_SURROGATE (its template batches need about 1 GiB of workspace);
  * SFT_E_DEVICE when the array's address cannot be resolved or a launch fails.
  */

@@ -344,21 +344,62 @@ extern "C" void sft_default_opts(sft_opts* o)
 }
 
 // ============================================================================ scan (host side)
+// Resolvability threshold of the four amplitudes of the F-statistic: M is inverted when
+// det [[A, C], [C, B]] >= kFstatEps A B, i.e. when the weighted response vectors (a_alpha) and
+// (b_alpha) are at least asin(sqrt(kFstatEps)) ~ 5.7 degrees from parallel; below it only the
+// dominant pattern is kept (the template is flagged FSTAT_DEGENERATE).
+static constexpr double kFstatEps = 1e-2;
+
+// 2F = x.M^{-1}.x (Sec. II.B) for x = (Re z+, Re zx, Im z+, Im zx) and the block-diagonal
+// norm matrix with blocks [[A, C], [C, B]] (A = hh+, B = hhx, C = hh+x), by the closed-form
+// inverse of the 2x2 block; nearly parallel patterns keep the largest eigenvector u of the
+// block only: 2F = ((u.x_cos)^2 + (u.x_sin)^2) / lambda_max.
+__device__ inline double fstat_2f(double x0, double x1, double x2, double x3, double A, double B, double C,
+                                  bool& degenerate)
+{
+  degenerate = false;
+  if (!(A > 0.0) && !(B > 0.0)) return 0.0;
+  const double D = A * B - C * C;
+  if (D >= kFstatEps * A * B && D > 0.0)
+    return (B * (x0 * x0 + x2 * x2) + A * (x1 * x1 + x3 * x3) - 2.0 * C * (x0 * x1 + x2 * x3)) / D;
+  degenerate = true;
+  const double lam = 0.5 * (A + B) + hypot(0.5 * (A - B), C);
+  if (!(lam > 0.0)) return 0.0;
+  // eigenvector from the better-conditioned row of (N - lam I) u = 0
+  double u0, u1;
+  if (A >= B) {
+    u0 = lam - B;
+    u1 = C;
+  } else {
+    u0 = C;
+    u1 = lam - A;
+  }
+  const double un = hypot(u0, u1);
+  u0 /= un;
+  u1 /= un;
+  const double pc = u0 * x0 + u1 * x1, ps = u0 * x2 + u1 * x3;
+  return (pc * pc + ps * ps) / lam;
+}
+
+// Per template: the partials of the chunks in chunk order (FP64), rho (Eq. det_short), the
+// flags, and with nacc = 7 the cross norm and the F-statistic.
 __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ part, const uint32_t* __restrict__ pflags,
-                                                       int64_t n, int32_t n_chunks, double a_plus, double a_cross,
-                                                       double* __restrict__ zp, double* __restrict__ zx,
+                                                       int64_t n, int32_t n_chunks, int32_t nacc, double a_plus,
+                                                       double a_cross, double* __restrict__ zp, double* __restrict__ zx,
                                                        double* __restrict__ hhp, double* __restrict__ hhx,
                                                        double* __restrict__ rho, uint32_t* __restrict__ flags,
-                                                       const uint32_t* __restrict__ xflags)
+                                                       const uint32_t* __restrict__ xflags, double* __restrict__ hhpx,
+                                                       double* __restrict__ twoF)
 {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
-  double v[6] = {0, 0, 0, 0, 0, 0};
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
   uint32_t fl = 0;
   for (int c = 0; c < n_chunks; ++c) {
-    const double* p = part + (int64_t)c * 6 * n + m;
+    const double* p = part + (int64_t)c * nacc * n + m;
 #pragma unroll
     for (int q = 0; q < 6; ++q) v[q] += p[q * n];
+    if (nacc == 7) v[6] += p[6 * n];
     fl |= pflags[(int64_t)c * n + m];
   }
   const double re = a_plus * v[0] + a_cross * v[3];
@@ -373,6 +414,14 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   }
   bool fin = isfinite(r);
   for (int q = 0; q < 6; ++q) fin = fin && isfinite(v[q]);
+  if (nacc == 7) {
+    bool deg = false;
+    const double f2 = fstat_2f(v[0], v[2], v[1], v[3], v[4], v[5], v[6], deg);
+    if (deg) fl |= SFT_FLAG_FSTAT_DEGENERATE;
+    fin = fin && isfinite(v[6]) && isfinite(f2);
+    if (hhpx) hhpx[m] = v[6];
+    if (twoF) twoF[m] = f2;
+  }
   if (!fin) fl |= kFlagNonfinite;
   if (xflags) fl |= xflags[m];
   zp[2 * m] = v[0];
@@ -385,10 +434,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   flags[m] = fl;
 }
 
-// wf: WF_NEWTON, WF_PN35 or WF_TABLE (the surrogate path)
-static ScanFn pick_kernel(const sft_data* d, const sft_opts* o, int wf)
+// wf: WF_NEWTON, WF_PN35 or WF_TABLE (the surrogate path); fs: the F-statistic form
+static ScanFn pick_kernel(const sft_data* d, const sft_opts* o, int wf, bool fs)
 {
   const int kern = o->kernel == SFT_KERNEL_DIRICHLET ? KERN_DIRICHLET : KERN_FRESNEL;
+  if (fs) return scan_pick_fstat(o->precision, kern, o->K, d->nd);
   if (o->precision == SFT_PREC_FP64) return scan_pick_f64(wf, o->K, d->nd);
   if (d->storage == SFT_STORE_F32) {
     const bool kahan = o->precision == SFT_PREC_FP32_KAHAN;
@@ -435,6 +485,18 @@ static sft_status validate_scan(const sft_data* d, const sft_opts* o)
   return SFT_OK;
 }
 
+// The F-statistic form (out->twoF set) exists for the Newtonian waveform with FP32-Kahan sums
+// on F32 data or FP64 sums on F64 data.
+static sft_status validate_fstat(const sft_data* d, const sft_opts* o, const sft_out* out)
+{
+  if (!out || !out->twoF) return SFT_OK;
+  if (o->waveform != SFT_WF_NEWTON)
+    return fail(SFT_E_UNSUPPORTED, "scan: the F-statistic is computed with the Newtonian waveform only");
+  if (!((o->precision == SFT_PREC_FP32_KAHAN && d->storage == SFT_STORE_F32) || o->precision == SFT_PREC_FP64))
+    return fail(SFT_E_UNSUPPORTED, "scan: the F-statistic needs FP32-Kahan sums on F32 data or FP64 sums");
+  return SFT_OK;
+}
+
 static sft_status validate_io(const sft_bank* bank, int64_t n, const sft_out* out)
 {
   if (!bank || !out) return fail(SFT_E_INVALID, "scan: null bank or output");
@@ -463,13 +525,14 @@ struct Prepared {
   ScanFn fn;
   const uint32_t* xflags;  // extra per-template flags ORed in by the finalize kernel (or null)
   dim3 grid, block;
+  int32_t nacc;            // partial sums per template and chunk: 6, or 7 in the F-statistic form
   size_t part_bytes, flag_bytes, counter_off, ws_bytes;
   int64_t n;
   double a_plus, a_cross;
 };
 
 static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o,
-                               const sft_tuning& t, Prepared& P, int wf = -1, const double* wtab = nullptr,
+                               const sft_tuning& t, Prepared& P, bool fs, int wf = -1, const double* wtab = nullptr,
                                const uint32_t* xflags = nullptr)
 {
   ScanArgs& a = P.a;
@@ -501,7 +564,8 @@ static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t 
   a.n_tmpl = n;
   a.wtab = wtab;
   P.xflags = xflags;
-  P.fn = pick_kernel(d, o, wf >= 0 ? wf : o->waveform);
+  P.fn = pick_kernel(d, o, wf >= 0 ? wf : o->waveform, fs);
+  P.nacc = fs ? 7 : 6;
   const int B = t.block ? t.block : 256;
   a.n_tiles = (int32_t)((n + B - 1) / B);
   int nb_cu = 0;
@@ -529,7 +593,7 @@ static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t 
   P.block = dim3(B);
   if (a.persistent) P.grid = dim3((unsigned)std::min<int64_t>(a.n_items, resident));
   else P.grid = dim3((unsigned)a.n_tiles, (unsigned)a.n_chunks);
-  P.part_bytes = (size_t)a.n_chunks * 6 * n * sizeof(double);
+  P.part_bytes = (size_t)a.n_chunks * P.nacc * n * sizeof(double);
   P.flag_bytes = (size_t)a.n_chunks * n * sizeof(uint32_t);
   P.counter_off = (P.part_bytes + P.flag_bytes + 255) / 256 * 256;
   P.ws_bytes = P.counter_off + 256;
@@ -560,8 +624,8 @@ static hipError_t enqueue_scan(Prepared& P, void* ws, sft_out* out, hipStream_t 
   if (ev_e) (void)hipEventRecord(ev_e, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, a.part, a.pflags, P.n,
-                     a.n_chunks, P.a_plus, P.a_cross, out->zp, out->zx, out->hhp, out->hhx, out->rho, out->flags,
-                     P.xflags);
+                     a.n_chunks, P.nacc, P.a_plus, P.a_cross, out->zp, out->zx, out->hhp, out->hhx, out->rho,
+                     out->flags, P.xflags, P.nacc == 7 ? out->hhpx : nullptr, P.nacc == 7 ? out->twoF : nullptr);
   return hipGetLastError();
 }
 
@@ -801,7 +865,7 @@ static sft_status surrogate_scan(const sft_data* d, const sft_bank* bank, int64_
   const int64_t chunk = std::min<int64_t>(R, 1 << 16);
   // workspace: U [R][3], Y, dY [R][2], table [5][R], xflags [B], network scratch, scan workspace
   Prepared P0;
-  sft_status s = prepare_scan(d, bank, B, o, d->tune, P0, WF_TABLE, nullptr, nullptr);
+  sft_status s = prepare_scan(d, bank, B, o, d->tune, P0, false, WF_TABLE, nullptr, nullptr);
   if (s != SFT_OK) return s;
   const size_t off_y = (size_t)R * 3 * sizeof(double);
   const size_t off_dy = off_y + (size_t)R * 2 * sizeof(double);
@@ -813,7 +877,7 @@ static sft_status surrogate_scan(const sft_data* d, const sft_bank* bank, int64_
   for (int64_t m0 = 0; m0 < n; m0 += B) {   // the last batch may have a different shape
     const int64_t nb = std::min(B, n - m0);
     Prepared Pt;
-    if ((s = prepare_scan(d, bank, nb, o, d->tune, Pt, WF_TABLE, nullptr, nullptr)) != SFT_OK) return s;
+    if ((s = prepare_scan(d, bank, nb, o, d->tune, Pt, false, WF_TABLE, nullptr, nullptr)) != SFT_OK) return s;
     scan_ws = std::max(scan_ws, Pt.ws_bytes);
   }
   char* ws = nullptr;
@@ -851,7 +915,7 @@ static sft_status surrogate_scan(const sft_data* d, const sft_bank* bank, int64_
                        ob.mismatch);
     if ((e = hipGetLastError()) != hipSuccess) break;
     Prepared P;
-    if ((s = prepare_scan(d, &b, nb, o, d->tune, P, WF_TABLE, tab, xf)) != SFT_OK) break;
+    if ((s = prepare_scan(d, &b, nb, o, d->tune, P, false, WF_TABLE, tab, xf)) != SFT_OK) break;
     e = enqueue_scan(P, ws + off_scan, &ob, st, m0 == 0);
   }
   hipError_t e2 = hipFreeAsync(ws, st);
@@ -866,11 +930,11 @@ extern "C" sft_status sft_template_bank_scan(const sft_data* d, const sft_bank* 
 {
   sft_status s = validate_scan(d, o);
   if (s != SFT_OK) return s;
-  if ((s = validate_io(bank, n, out)) != SFT_OK || n == 0) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK || n == 0) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   if (o->waveform == SFT_WF_SURROGATE) return surrogate_scan(d, bank, n, o, out, st);
   Prepared P;
-  if ((s = prepare_scan(d, bank, n, o, d->tune, P)) != SFT_OK) return s;
+  if ((s = prepare_scan(d, bank, n, o, d->tune, P, out->twoF != nullptr)) != SFT_OK) return s;
   void* ws = nullptr;
   HIP_OR_FAIL(hipMallocAsync(&ws, P.ws_bytes, st));
   hipError_t e = enqueue_scan(P, ws, out, st, true);
@@ -910,16 +974,17 @@ extern "C" sft_status sft_template_bank_scan_noalloc(const sft_data* d, const sf
 {
   sft_status s = validate_scan(d, o);
   if (s != SFT_OK) return s;
-  if ((s = validate_io(bank, n, out)) != SFT_OK || n == 0) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK || n == 0) return s;
   if (o->waveform == SFT_WF_SURROGATE)
     return fail(SFT_E_UNSUPPORTED, "scan (no-alloc): the surrogate waveform needs its batch workspace");
+  const bool fs = out->twoF != nullptr;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != d->device)
     return fail(SFT_E_INVALID, "scan (no-alloc): the data live on device %d, not on the current device", d->device);
   // the handle's launch shape, with fewer (larger) chunks when its partial sums would not fit
   sft_tuning t = d->tune;
   Prepared P;
-  if ((s = prepare_scan(d, bank, n, o, t, P)) != SFT_OK) return s;
+  if ((s = prepare_scan(d, bank, n, o, t, P, fs)) != SFT_OK) return s;
   if (P.ws_bytes > SFT_NOALLOC_SCRATCH_BYTES) {
     const size_t per_chunk = (P.part_bytes + P.flag_bytes) / (size_t)P.a.n_chunks;   // bytes per chunk
     const size_t room = SFT_NOALLOC_SCRATCH_BYTES - 512;   // counter slot and alignment
@@ -929,7 +994,7 @@ extern "C" sft_status sft_template_bank_scan_noalloc(const sft_data* d, const sf
                   (long long)n, per_chunk, (unsigned)SFT_NOALLOC_SCRATCH_BYTES);
     if (t.block == 0 && t.chunk_groups == 0 && t.persistent == 0) t.persistent = 1;   // keep the automatic grid
     t.chunk_groups = (int32_t)((d->n_groups + nc_max - 1) / nc_max);
-    if ((s = prepare_scan(d, bank, n, o, t, P)) != SFT_OK) return s;
+    if ((s = prepare_scan(d, bank, n, o, t, P, fs)) != SFT_OK) return s;
     if (P.ws_bytes > SFT_NOALLOC_SCRATCH_BYTES)
       return fail(SFT_E_RANGE, "scan (no-alloc): workspace of %zu bytes exceeds the scratch", P.ws_bytes);
   }
@@ -963,7 +1028,7 @@ extern "C" sft_status sft_autotune(sft_data* d, const sft_bank* bank, int64_t n,
 {
   sft_status s = validate_scan(d, o);
   if (s != SFT_OK) return s;
-  if ((s = validate_io(bank, n, out)) != SFT_OK) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK) return s;
   if (n == 0) return fail(SFT_E_INVALID, "sft_autotune: needs at least one template");
   if (o->waveform == SFT_WF_SURROGATE)
     return fail(SFT_E_UNSUPPORTED, "sft_autotune: tune with the Newtonian or 3.5PN waveform");
@@ -986,7 +1051,7 @@ extern "C" sft_status sft_autotune(sft_data* d, const sft_bank* bank, int64_t n,
   std::vector<Prepared> preps(cand.size());
   size_t ws_max = 0;
   for (size_t i = 0; i < cand.size(); ++i) {
-    if ((s = prepare_scan(d, bank, n, o, cand[i], preps[i])) != SFT_OK) return s;
+    if ((s = prepare_scan(d, bank, n, o, cand[i], preps[i], out->twoF != nullptr)) != SFT_OK) return s;
     ws_max = std::max(ws_max, preps[i].ws_bytes);
   }
   void* ws = nullptr;
@@ -1048,7 +1113,7 @@ extern "C" sft_status sft_plan_create(const sft_data* d, const sft_bank* bank, i
   *plan = nullptr;
   sft_status s = validate_scan(d, o);
   if (s != SFT_OK) return s;
-  if ((s = validate_io(bank, n, out)) != SFT_OK) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK) return s;
   if (n == 0) return fail(SFT_E_INVALID, "sft_plan_create: needs at least one template");
   if (o->waveform == SFT_WF_SURROGATE)
     return fail(SFT_E_UNSUPPORTED, "sft_plan_create: the surrogate waveform is not captured into graphs");
@@ -1057,7 +1122,7 @@ extern "C" sft_status sft_plan_create(const sft_data* d, const sft_bank* bank, i
   p->graph = nullptr;
   p->exec = nullptr;
   p->out = *out;
-  if ((s = prepare_scan(d, bank, n, o, d->tune, p->P)) != SFT_OK) {
+  if ((s = prepare_scan(d, bank, n, o, d->tune, p->P, out->twoF != nullptr)) != SFT_OK) {
     delete p;
     return s;
   }

@@ -6,6 +6,8 @@
 // reduction, FP64 bin split, 2K+1 kernel weights and the bin contraction (Eq. with_f_1),
 // the coherent accumulation of Eq. efficient and of the norm, in FP64 or FP32 (Kahan or
 // plain).  Writes one partial per (template, chunk); the finalize kernel combines them.
+// FS = 1 (the F-statistic form, Sec. II.B) also accumulates the cross norm
+// sum F+ Fx A^2 T / S, and keeps the three norm sums in FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -139,7 +141,7 @@ __device__ inline void stage_window(Bin* sw, const Bin* const* rp, int sb, int w
 // a group (one per detector) share the SFT midpoint, hence the chirp, the window and
 // all 2K+1 kernel weights: those are evaluated once per group and contracted with the
 // bins of each of the ND rows (the projector Lambda carries the detector dependence).
-template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS>
 __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab,
                                           Bin* sw);
 
@@ -158,7 +160,7 @@ constexpr int scan_min_waves()
   return 1;
 }
 
-template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_min_waves<PREC, KERN, KC, ND, WF>())))
 void scan_kernel(ScanArgs a)
 {
@@ -191,12 +193,12 @@ void scan_kernel(ScanArgs a)
     const int tile = item % a.n_tiles;
     const int c = item / a.n_tiles;
     const int64_t m = (int64_t)tile * blockDim.x + threadIdx.x;
-    if (m < a.n_tmpl) scan_item<Bin, PREC, KERN, KC, ND, WF>(a, K, m, c, tab, stage + (threadIdx.x >> 6) * (ND * WST));
+    if (m < a.n_tmpl) scan_item<Bin, PREC, KERN, KC, ND, WF, FS>(a, K, m, c, tab, stage + (threadIdx.x >> 6) * (ND * WST));
     if (!a.persistent) break;
   }
 }
 
-template <typename Bin, int PREC, int KERN, int KC, int ND, int WF>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS>
 __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab,
                                           Bin* sw)
 {
@@ -233,7 +235,10 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
   const Bin* __restrict__ bins = (const Bin*)a.bins;
   const PS* __restrict__ psd = (const PS*)a.psd;
 
-  Acc zpr, zpi, zxr, zxi, hp, hx;
+  Acc zpr, zpi, zxr, zxi;
+  // norm sums: FP64 in the F-statistic form, whose 2x2 norm matrix is inverted
+  using NAcc = typename std::conditional<FS != 0, AccF64, Acc>::type;
+  NAcc hp, hx, hpx;
   uint32_t fl = 0;
 
   // the group's rows and midpoint time are loaded one group ahead, so that their latency
@@ -578,7 +583,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
     const R a2t = amp * amp * (R)T;
     // the rows of the group are summed plainly, then the group enters the running
     // (compensated) sums once
-    R gzpr = 0, gzpi = 0, gzxr = 0, gzxi = 0, ghp = 0, ghx = 0;
+    R gzpr = 0, gzpi = 0, gzxr = 0, gzxi = 0, ghp = 0, ghx = 0, ghpx = 0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       if (!act[d]) continue;
@@ -606,6 +611,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       else hterm = a2t * (R)fast_rcp((float)S);
       ghp = fma(fpa * fpa, hterm, ghp);
       ghx = fma(fxa * fxa, hterm, ghx);
+      if constexpr (FS != 0) ghpx = fma(fpa * fxa, hterm, ghpx);
     }
     zpr.add(gzpr);
     zpi.add(gzpi);
@@ -613,54 +619,57 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
     zxi.add(gzxi);
     hp.add(ghp);
     hx.add(ghx);
+    if constexpr (FS != 0) hpx.add(ghpx);
   }
 
   const int64_t n = a.n_tmpl;
-  double* p = a.part + (int64_t)c * 6 * n + m;
+  double* p = a.part + (int64_t)c * (6 + FS) * n + m;
   p[0] = zpr.get();
   p[n] = zpi.get();
   p[2 * n] = zxr.get();
   p[3 * n] = zxi.get();
   p[4 * n] = hp.get();
   p[5 * n] = hx.get();
+  if constexpr (FS != 0) p[6 * n] = hpx.get();
   a.pflags[(int64_t)c * n + m] = fl;
 }
 
 // ---------------------------------------------------------------------------- dispatch
 // Newtonian: every detector-group width 1..4.  3.5PN: widths 1 and 4 (groups of 2 or 3
 // rows run in the width-4 kernel, whose absent rows are skipped by a uniform test).
-template <typename Bin, int PREC, int KERN, int KC, int WF>
+template <typename Bin, int PREC, int KERN, int KC, int WF, int FS>
 static ScanFn pick_nd(int nd)
 {
   if constexpr (WF == WF_NEWTON) {
     switch (nd) {
-    case 1: return scan_kernel<Bin, PREC, KERN, KC, 1, WF>;
-    case 2: return scan_kernel<Bin, PREC, KERN, KC, 2, WF>;
-    case 3: return scan_kernel<Bin, PREC, KERN, KC, 3, WF>;
-    default: return scan_kernel<Bin, PREC, KERN, KC, 4, WF>;
+    case 1: return scan_kernel<Bin, PREC, KERN, KC, 1, WF, FS>;
+    case 2: return scan_kernel<Bin, PREC, KERN, KC, 2, WF, FS>;
+    case 3: return scan_kernel<Bin, PREC, KERN, KC, 3, WF, FS>;
+    default: return scan_kernel<Bin, PREC, KERN, KC, 4, WF, FS>;
     }
   } else {
-    return nd == 1 ? scan_kernel<Bin, PREC, KERN, KC, 1, WF> : scan_kernel<Bin, PREC, KERN, KC, 4, WF>;
+    return nd == 1 ? scan_kernel<Bin, PREC, KERN, KC, 1, WF, FS> : scan_kernel<Bin, PREC, KERN, KC, 4, WF, FS>;
   }
 }
 
-template <typename Bin, int PREC, int KERN, int WF>
+template <typename Bin, int PREC, int KERN, int WF, int FS = 0>
 static ScanFn pick_k(int K, int nd)
 {
   if constexpr (PREC == SFT_PREC_FP64) {
-    return K == 4 ? pick_nd<Bin, PREC, KERN, 4, WF>(nd) : pick_nd<Bin, PREC, KERN, -1, WF>(nd);
+    return K == 4 ? pick_nd<Bin, PREC, KERN, 4, WF, FS>(nd) : pick_nd<Bin, PREC, KERN, -1, WF, FS>(nd);
   } else {
     // one-row Fresnel scans with K = 32 (space-like banks) get a compile-time window too
     if constexpr (KERN == KERN_FRESNEL && WF == WF_NEWTON)
-      if (K == 32 && nd == 1) return scan_kernel<Bin, PREC, KERN, 32, 1, WF>;
-    return K == 8 ? pick_nd<Bin, PREC, KERN, 8, WF>(nd) : pick_nd<Bin, PREC, KERN, -1, WF>(nd);
+      if (K == 32 && nd == 1) return scan_kernel<Bin, PREC, KERN, 32, 1, WF, FS>;
+    return K == 8 ? pick_nd<Bin, PREC, KERN, 8, WF, FS>(nd) : pick_nd<Bin, PREC, KERN, -1, WF, FS>(nd);
   }
 }
 
-template <typename Bin, int PREC, int WF>
+template <typename Bin, int PREC, int WF, int FS = 0>
 static ScanFn pick_kern(int kern, int K, int nd)
 {
-  return kern == KERN_DIRICHLET ? pick_k<Bin, PREC, KERN_DIRICHLET, WF>(K, nd) : pick_k<Bin, PREC, KERN_FRESNEL, WF>(K, nd);
+  return kern == KERN_DIRICHLET ? pick_k<Bin, PREC, KERN_DIRICHLET, WF, FS>(K, nd)
+                                : pick_k<Bin, PREC, KERN_FRESNEL, WF, FS>(K, nd);
 }
 
 template <typename Bin, int PREC>

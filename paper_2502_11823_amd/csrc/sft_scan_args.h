@@ -33,7 +33,7 @@ struct ScanArgs {
   int32_t n_items;          // n_tiles * n_chunks work items, chunk-major
   int32_t persistent;       // 1: grid of resident blocks pulling items from *counter
   int32_t* counter;         // work-queue head (zeroed before the launch)
-  double* part;      // [n_chunks][6][n_tmpl]
+  double* part;      // [n_chunks][6 (+1 in the F-statistic form)][n_tmpl]
   uint32_t* pflags;  // [n_chunks][n_tmpl]
   const double* wtab;  // chirp table (WF_TABLE): 5 planes [n_groups][n_tmpl] kappa, phase, amp, beta, dres
 };
@@ -56,3 +56,6 @@ ScanFn scan_pick_f32n_newton(int kern, int K, int nd);
 ScanFn scan_pick_f32n_pn35(int kern, int K, int nd);
 ScanFn scan_pick_f32n_table(int kern, int K, int nd);
 ScanFn scan_pick_bf16(int prec, int kern, int K, int nd);
+// the F-statistic form (Newtonian waveform; prec SFT_PREC_FP32_KAHAN with F32 storage or
+// SFT_PREC_FP64 with F64 storage and the Dirichlet kernel)
+ScanFn scan_pick_fstat(int prec, int kern, int K, int nd);

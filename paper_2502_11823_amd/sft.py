@@ -22,6 +22,7 @@ PRECISION = {"fp64": 0, "fp32_kahan": 1, "fp32_naive": 2}
 WAVEFORM = {"newton": 0, "pn35": 1, "surrogate": 2}
 FLAG_OUT_OF_BAND, FLAG_TAU_NONPOSITIVE, FLAG_TAYLOR_INVALID, FLAG_NONFINITE, FLAG_EMPTY = 1, 2, 4, 8, 64
 FLAG_SURROGATE_FALLBACK = 32
+FLAG_FSTAT_DEGENERATE = 128
 K_MAX = 64
 T_SUN = 4.925490947641267e-6
 
@@ -53,7 +54,7 @@ class Bank(ctypes.Structure):
 class Out(ctypes.Structure):
     _fields_ = [("zp", ctypes.c_void_p), ("zx", ctypes.c_void_p), ("hhp", ctypes.c_void_p),
                 ("hhx", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("flags", ctypes.c_void_p),
-                ("mismatch", ctypes.c_void_p)]
+                ("mismatch", ctypes.c_void_p), ("hhpx", ctypes.c_void_p), ("twoF", ctypes.c_void_p)]
 
 
 class SurrogateDesc(ctypes.Structure):
@@ -246,7 +247,7 @@ def bank_to_device(bank: Dict[str, np.ndarray], device="cuda"):
     return out
 
 
-def alloc_out(n: int, device="cuda", mismatch=False):
+def alloc_out(n: int, device="cuda", mismatch=False, fstat=False):
     import torch
     out = {"zp": torch.empty((n, 2), dtype=torch.float64, device=device),
            "zx": torch.empty((n, 2), dtype=torch.float64, device=device),
@@ -256,6 +257,9 @@ def alloc_out(n: int, device="cuda", mismatch=False):
            "flags": torch.empty(n, dtype=torch.int32, device=device)}
     if mismatch:
         out["mismatch"] = torch.zeros(n, dtype=torch.float64, device=device)
+    if fstat:
+        out["hhpx"] = torch.empty(n, dtype=torch.float64, device=device)
+        out["twoF"] = torch.empty(n, dtype=torch.float64, device=device)
     return out
 
 
@@ -273,7 +277,7 @@ def _bank_struct(bank_t):
 
 def _out_struct(out):
     return Out(_tp(out["zp"]), _tp(out["zx"]), _tp(out["hhp"]), _tp(out["hhx"]), _tp(out["rho"]),
-               _tp(out["flags"]), _tp(out.get("mismatch")))
+               _tp(out["flags"]), _tp(out.get("mismatch")), _tp(out.get("hhpx")), _tp(out.get("twoF")))
 
 
 def template_bank_scan(data: SFTData, bank_t, opts: Opts, out=None, stream=None, n=None):

@@ -9,11 +9,12 @@ from paper_2502_11823_amd import sft
 KERN = {"dirichlet": oracle.K_DIRICHLET, "fresnel": oracle.K_FRESNEL, "auto": oracle.K_AUTO}
 
 
-def gpu_scan(data, bank, mismatch=False, **kw):
+def gpu_scan(data, bank, mismatch=False, fstat=False, **kw):
     import torch
     opts = sft.make_opts(**kw)
     bt = sft.bank_to_device(bank)
-    res = sft.template_bank_scan(data, bt, opts, out=sft.alloc_out(len(bank["mc"]), mismatch=mismatch))
+    res = sft.template_bank_scan(data, bt, opts, out=sft.alloc_out(len(bank["mc"]), mismatch=mismatch,
+                                                                    fstat=fstat))
     torch.cuda.synchronize()
     out = {k: v.cpu().numpy() for k, v in res.items()}
     out["zp"] = out["zp"][:, 0] + 1j * out["zp"][:, 1]
@@ -65,3 +66,23 @@ def compare(g, o, idx=None, tol_z=1e-6, tol_rho=1e-5, tol_hh=1e-6, label="", noi
     assert eh[ok].max() <= tol_hh
     assert er[ok].max() <= tol_rho
     return ep[ok].max()
+
+
+def compare_fstat(g, o, tol_f=2e-5, tol_hh=1e-6, label=""):
+    """F-statistic outputs: the cross norm relative to sqrt(hh+ hhx) (<= 1e-6, as the other
+    norms) and 2F in noise units, |d2F| / max(2F, 4) (<= 2e-5: 2F is a squared SNR, whose bar
+    is twice rho's 1e-5; 4 is the mean of 2F in noise).  The degenerate flag is compared with
+    the other flags by compare(); templates whose det N / (hh+ hhx) lies within 1e-6 of the
+    threshold 1e-2 could be decided differently by rounding and are left out."""
+    d = (o["hhp"] * o["hhx"] - o["hhpx"]**2) / np.maximum(o["hhp"] * o["hhx"], 1e-300)
+    ok = (np.abs(d - 1e-2) > 1e-6) & (o["tie"] > 1e-9)
+    sc = np.sqrt(np.maximum(o["hhp"] * o["hhx"], 1e-300))
+    ec = np.abs(g["hhpx"] - o["hhpx"]) / sc
+    ef = np.abs(g["twoF"] - o["twoF"]) / np.maximum(o["twoF"], 4.0)
+    print("%s: n=%d max e(hh+x)=%.3e e(2F)=%.3e degenerate %d, near threshold %d"
+          % (label, int(ok.sum()), ec[ok].max(), ef[ok].max(),
+             int(np.sum((o["flags"] & oracle.F_FSTAT_DEGENERATE) != 0)), int(np.sum(~ok))))
+    assert np.array_equal(g["flags"][ok], o["flags"][ok])
+    assert ec[ok].max() <= tol_hh
+    assert ef[ok].max() <= tol_f
+    return ef[ok].max()
