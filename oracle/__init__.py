@@ -67,7 +67,8 @@ def _load():
                                   Int, Int, Int, D, D, D, D, Int, Int, P, P, P]
     lib.orc_scan.argtypes = [L, L, D, L, L, P, P, P, P, P,
                              L, Int, P, P, P, P, P, P,
-                             Int, Int, Int, D, D, D, D, D, Int, Int, P, P, P, P]
+                             Int, Int, Int, D, D, D, D, D, Int, Int, P, P, P, P, P, P]
+    lib.orc_doppler_waveform.argtypes = [Int, D, D, D, D, D, D, P, P, P]
     lib.orc_set_surrogate.argtypes = [Int, Int, P, P]
     lib.orc_mlp_param_count.argtypes = [Int, Int]
     lib.orc_mlp_param_count.restype = L
@@ -169,6 +170,19 @@ def waveform(mc, t_c, phi_c, t, q=1.0, wf=WF_NEWTON, tsun=T_SUN):
     return res
 
 
+def doppler_waveform(mc, t_c, phi_c, t, eph, sky, q=1.0, wf=WF_NEWTON, tsun=T_SUN):
+    """(A, phi, f, fdot, fddot) at detector time t of a source in direction sky seen by a
+    detector with eph = (r/c, v/c, a/c) at t (Sec. III.B, reading R26)."""
+    e = _f64(np.reshape(eph, 9))
+    n = _f64(np.reshape(sky, 3))
+    out = np.empty(5)
+    rc = _load().orc_doppler_waveform(wf, float(mc), float(q), float(t_c), float(phi_c), float(t), float(tsun),
+                                      _ptr(e), _ptr(n), _ptr(out))
+    if rc != 0:
+        out[:] = np.nan
+    return out
+
+
 def pn35_consistency(mc, q, tau, tsun=T_SUN):
     """(d phi/dt) / (2 pi f) - 1 of the 3.5PN waveform, analytic."""
     return _load().orc_pn35_consistency(float(mc), float(q), float(tau), float(tsun))
@@ -228,8 +242,11 @@ def ip_params(data: SFTData, A, phi, f, fdot, use=None, fddot=None, K=4, kernel=
 
 def scan(data: SFTData, mc, t_c, phi_c=None, q=None, a_first=None, a_last=None, K=4,
          kernel=K_AUTO, t_ref=REF_MID, beta_switch=1e-7, a_plus=1.0, a_cross=0.0,
-         tsun=T_SUN, delta_max=0.0, compensated=True, wf=WF_NEWTON, fstat=False):
+         tsun=T_SUN, delta_max=0.0, compensated=True, wf=WF_NEWTON, fstat=False, eph=None, sky=None):
     """Template-bank SFT inner products (Eq. efficient), one template per entry.
+
+    Doppler (Sec. III.B, reading R26): eph [n_sft, 9] = (r/c, v/c, a/c) of each SFT row's
+    detector at the SFT midpoint, sky [n, 3] unit vectors toward the sources.
 
     Returns a dict of numpy arrays: zp, zx (complex), hhp, hhx, rho, flags, tie, mismatch,
     and with fstat=True the cross norm hhpx and the F-statistic twoF (Sec. II.B)."""
@@ -244,12 +261,17 @@ def scan(data: SFTData, mc, t_c, phi_c=None, q=None, a_first=None, a_last=None, 
     fl = np.zeros(m, np.uint32)
     tie = np.zeros(m)
     mm = np.zeros(m)
+    eph = None if eph is None else np.ascontiguousarray(np.reshape(eph, (data.n_sft, 9)), dtype=np.float64)
+    sky = None if sky is None else np.ascontiguousarray(np.broadcast_to(np.reshape(sky, (-1, 3)), (m, 3)),
+                                                        dtype=np.float64)
     rc = _load().orc_scan(*data._args(), _ptr(data.t_start), _ptr(data.x_bins), _ptr(data.psd),
                           _ptr(data.fplus), _ptr(data.fcross), m, int(wf), _ptr(mc), _ptr(q),
                           _ptr(t_c), _ptr(phi_c), _ptr(af), _ptr(al), int(K), int(kernel),
                           int(t_ref), float(beta_switch), float(a_plus), float(a_cross),
                           float(tsun), float(delta_max), int(compensated), int(bool(fstat)),
-                          _ptr(out), _ptr(fl), _ptr(tie), _ptr(mm))
+                          _ptr(eph), _ptr(sky), _ptr(out), _ptr(fl), _ptr(tie), _ptr(mm))
+    if rc == -2:
+        raise ValueError("Doppler needs eph and sky, the midpoint reference and a closed-form waveform")
     if rc != 0:
         raise MemoryError("oracle scan failed")
     res = {"zp": out[:, 0] + 1j * out[:, 1], "zx": out[:, 2] + 1j * out[:, 3],

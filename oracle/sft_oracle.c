@@ -460,6 +460,35 @@ int orc_waveform_array(int wf, double mc, double q, double t_c, double phi_c, co
   return rc;
 }
 
+/* Doppler (Sec. III.B, the passage on the time delay): the phase is a function of the
+ * emission time t_s(t; n) at the source, phi(t_s(t; n)), so the per-SFT quantities become
+ *   f = (1/2 pi) (dphi/dt_s)(dt_s/dt),  fdot = (1/2 pi) d^2 phi(t_s(t))/dt^2, ...
+ * Reading R26: t_s = t + r(t).n / c (the Roemer delay of a detector at barycentric position
+ * r; the constant distance term is absorbed into t_c, the relativistic delays are left out),
+ * with eph = (r/c [s], v/c, a/c [1/s]) of the detector at time t and n the unit vector toward
+ * the source.  Then, with D = r.n/c, D1 = v.n/c, D2 = a.n/c and the source-frame quantities
+ * f_s, fdot_s, fddot_s at t_s:
+ *   f = f_s (1 + D1),  fdot = fdot_s (1 + D1)^2 + f_s D2,
+ *   fddot = fddot_s (1 + D1)^3 (kept for the Taylor-validity flag only; the terms with the
+ *   orbit's jerk and with fdot_s D2 are left out there). */
+int orc_doppler_waveform(int wf, double mc, double q, double t_c, double phi_c, double t, double tsun,
+                         const double *eph, const double *n, double *out)
+{
+  double D = eph[0] * n[0] + eph[1] * n[1] + eph[2] * n[2];
+  double D1 = eph[3] * n[0] + eph[4] * n[1] + eph[5] * n[2];
+  double D2 = eph[6] * n[0] + eph[7] * n[1] + eph[8] * n[2];
+  double w[5];
+  int st = orc_waveform(wf, mc, q, t_c, phi_c, t + D, tsun, w);
+  if (st != 0) return st;
+  double g = 1.0 + D1;
+  out[0] = w[0];
+  out[1] = w[1];
+  out[2] = w[2] * g;
+  out[3] = w[3] * g * g + w[2] * D2;
+  out[4] = w[4] * g * g * g;
+  return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Coherent SFT sum for one template (Eqs. with_f_1, prod_barbar, efficient).  */
 /* ------------------------------------------------------------------------- */
@@ -699,8 +728,12 @@ int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
              const double *phi_c, const int32_t *a_first, const int32_t *a_last,
              int K, int kernel, int t_ref, double beta_switch, double a_plus, double a_cross,
              double tsun, double delta_max, int compensated, int fstat,
+             const double *eph, const double *sky,
              double *out, uint32_t *flags, double *tie, double *mismatch)
 {
+  /* Doppler: eph [n_sft][9] at each SFT's midpoint, sky [n_tmpl][3] (midpoint reference and
+   * the closed-form waveforms only) */
+  if (sky && (!eph || t_ref != ORC_REF_MID || wf == ORC_WF_SURROGATE)) return -2;
   orc_data D = {n_sft, n, T, k_lo, n_bins, xb, psd, fp, fx};
   orc_opts o = {K, kernel, t_ref, beta_switch, a_plus, a_cross, delta_max, compensated, fstat};
   int err = 0;
@@ -753,7 +786,9 @@ int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
         if (a < lo || a > hi) continue;
         double tref = t_start[a] + (t_ref == ORC_REF_MID ? 0.5 * T : 0.0);
         double w[5];
-        int st = orc_waveform(wfm, mc[m], q ? q[m] : 1.0, t_c[m], phi_c ? phi_c[m] : 0.0, tref, tsun, w);
+        int st = sky ? orc_doppler_waveform(wfm, mc[m], q ? q[m] : 1.0, t_c[m], phi_c ? phi_c[m] : 0.0, tref,
+                                            tsun, eph + 9 * a, sky + 3 * m, w)
+                     : orc_waveform(wfm, mc[m], q ? q[m] : 1.0, t_c[m], phi_c ? phi_c[m] : 0.0, tref, tsun, w);
         if (st != 0) { extra |= ORC_F_TAU_NONPOSITIVE; continue; }
         A[a] = w[0]; ph[a] = w[1]; fr[a] = w[2]; fd[a] = w[3]; fdd[a] = w[4];
         use[a] = 1;

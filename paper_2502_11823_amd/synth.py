@@ -189,6 +189,44 @@ def space(seed: int = 3, n_templates: int = 200_000, n_sft: int = 60, n_use_lo: 
                     bank, dict(K=32, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0))
 
 
+# ----------------------------------------------------------------------------- ephemerides
+AU_S = 499.00478383615643     # astronomical unit / c [s]
+R_EARTH_S = 6.371e6 / 299792458.0
+SIDEREAL_DAY = 86164.0905
+OBLIQUITY = np.deg2rad(23.4393)
+
+
+def circular_orbit(t, radius: float, period: float, phase: float = 0.0, tilt: float = 0.0):
+    """Position, velocity and acceleration over c ([n, 9]: r/c [s], v/c, a/c [1/s]) of a
+    point on a circle of radius `radius` (light-seconds) in a plane tilted by `tilt` about the
+    x axis, angular position W t + phase."""
+    t = np.asarray(t, np.float64)
+    W = 2.0 * np.pi / period
+    th = W * t + phase
+    c, s = np.cos(th), np.sin(th)
+    ct, st_ = np.cos(tilt), np.sin(tilt)
+    r = radius * np.stack([c, s * ct, s * st_], -1)
+    v = radius * W * np.stack([-s, c * ct, c * st_], -1)
+    a = -(W * W) * r
+    return np.concatenate([r, v, a], -1)
+
+
+def ground_ephemeris(t, latitude: float, longitude: float):
+    """A ground detector: the Earth on a circular orbit of 1 AU in the ecliptic (tilted by the
+    obliquity against the equatorial frame) plus the Earth's rotation at the detector's
+    latitude and longitude (sidereal day).  [n, 9] as circular_orbit."""
+    orb = circular_orbit(t, AU_S, 3.15576e7, 0.0, OBLIQUITY)
+    rot = circular_orbit(t, R_EARTH_S * np.cos(latitude), SIDEREAL_DAY, longitude, 0.0)
+    rot[..., 2] += R_EARTH_S * np.sin(latitude)
+    return orb + rot
+
+
+def sky_vector(ra, dec):
+    """Unit vectors toward (right ascension, declination), [n, 3]."""
+    ra, dec = np.broadcast_arrays(np.asarray(ra, np.float64), np.asarray(dec, np.float64))
+    return np.stack([np.cos(dec) * np.cos(ra), np.cos(dec) * np.sin(ra), np.sin(dec)], -1)
+
+
 def mlp_init(seed: int, hidden: int = 128, layers: int = 4) -> np.ndarray:
     """Seeded initial parameters of the surrogate network, packed layer by layer
     (W [n_in][n_out] input-major, then b [n_out]): W ~ N(0, 1/n_in), b = 0, the output
