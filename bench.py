@@ -196,6 +196,7 @@ def parse():
                    help="templates of the space-based leg (0 = skip the leg)")
     p.add_argument("--space-only", action="store_true", help="run only the space-based leg")
     p.add_argument("--no-fstat", action="store_true", help="skip the F-statistic leg")
+    p.add_argument("--no-doppler", action="store_true", help="skip the Doppler leg")
     p.add_argument("--paper-shapes", action="store_true",
                    help="context only: time banks shaped like the paper's timing runs and exit")
     return p.parse_args()
@@ -326,6 +327,8 @@ def main():
     if not args.no_fstat:
         res["fstat"] = fstat_leg(args, w, data, bank, opts, K)
     del out, bank, data
+    if not args.no_doppler:
+        res["doppler"] = doppler_leg(args, w, opts, K)
     if args.space_templates > 0:
         res["space"] = space_leg(args)
     if args.surrogate_templates > 0:
@@ -369,6 +372,51 @@ def fstat_leg(args, w, data, bank, opts, K):
             "twoF_median": float(np.median(f2)), "twoF_mean": float(np.mean(f2)),
             "degenerate_frac": float(np.mean((flags & sft.FLAG_FSTAT_DEGENERATE) != 0)),
             "max_err_2F_vs_oracle_40": err}
+
+
+# detector sites of the Doppler leg (latitude, longitude) [rad]
+SITES = [(0.81, -1.58), (0.53, -2.08), (0.76, 0.18)]
+
+
+def doppler_leg(args, w, opts, K):
+    """The Doppler form (Sec. III.B) on the ground bank: every template with its own sky
+    position, each detector at its own site on the rotating, orbiting Earth (every SFT row then
+    has its own waveform: one row per timestamp group), autotuned launch shape."""
+    import torch
+    from paper_2502_11823_amd import sft, synth
+    tm = w.t_start + 0.5 * w.t_sft
+    eph = np.empty((w.n_sft, 9))
+    for d, (lat, lon) in enumerate(SITES):
+        m = w.det == d
+        eph[m] = synth.ground_ephemeris(tm[m], lat, lon)
+    g = np.random.default_rng(99)
+    bank_h = dict(w.bank)
+    bank_h["sky"] = synth.sky_vector(g.uniform(0, 2 * np.pi, w.n_templates),
+                                     np.arcsin(g.uniform(-1, 1, w.n_templates)))
+    data = sft.SFTData.from_workload(w, storage="f32")
+    data.set_ephemeris(eph)
+    bank = sft.bank_to_device(bank_h)
+    out = sft.alloc_out(w.n_templates)
+    best, _ = sft.autotune(data, bank, opts, out=out, reps=2)
+    for _ in range(args.warmup):
+        sft.template_bank_scan(data, bank, opts, out=out)
+    torch.cuda.synchronize()
+    sft.kernel_timing(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sft.template_bank_scan(data, bank, opts, out=out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k_ms = float(np.mean(sft.kernel_times(args.steps)))
+    sft.kernel_timing(0)
+    value = w.n_templates * args.steps / elapsed
+    print("doppler: %.3f ms/step (kernel %.3f ms), %.3e IP/s" % (1e3 * elapsed / args.steps, k_ms, value),
+          file=sys.stderr, flush=True)
+    return {"workload": "Doppler form of the ground scan: 3 detector sites (Earth orbit + rotation), "
+                        "random sky position per template, one SFT row per timestamp group",
+            "value": value, "unit": "IP/s", "ms_per_step": 1e3 * elapsed / args.steps, "kernel_ms": k_ms,
+            "tuning": best.as_dict()}
 
 
 def space_leg(args):

@@ -112,6 +112,21 @@ sft_status sft_load_data(const sft_data_desc* desc, const double* t_start, const
 /* Release a handle and its device memory (NULL is a no-op). */
 void sft_free_data(sft_data* data);
 
+/*
+ * sft_set_ephemeris -- detector motion for the Doppler form of the scan (Sec. III.B: the
+ * phase as a function of the emission time t_s(t; n), the frequency
+ * (1/2 pi)(dphi/dt_s)(dt_s/dt)).
+ *   eph : host [n_sft][9], for each SFT row at its midpoint: the detector's position r/c [s],
+ *         velocity v/c and acceleration a/c [1/s] relative to the solar-system barycentre,
+ *         in any fixed frame (the bank's sky vectors use the same frame).  Only the Roemer
+ *         delay r.n/c is modelled (the relativistic delays are left out).
+ * Rows that share a start time no longer share a waveform: afterwards every row is its own
+ * timestamp group (time order kept), for every scan of the handle.  The call returns after
+ * the upload on hip_stream.  Errors: SFT_E_INVALID (null, non-finite entry), SFT_E_NOMEM,
+ * SFT_E_DEVICE.
+ */
+sft_status sft_set_ephemeris(sft_data* data, const double* eph, void* hip_stream);
+
 typedef struct {
   int32_t K;            /* window half-width: bins k0-K .. k0+K, 0 <= K <= SFT_K_MAX (Sec. III.C truncation) */
   int32_t kernel;       /* SFT_KERNEL_* */
@@ -139,7 +154,15 @@ void sft_default_opts(sft_opts* opts);
  * dominant-mode amplitude through 2PN.  Template m uses SFT rows a_first[m]..a_last[m]
  * (inclusive, clamped to the data).  q (mass ratio) is read only by waveforms that
  * depend on it and may be NULL otherwise; phi_c, a_first, a_last may be NULL
- * (0, 0, n_sft - 1). */
+ * (0, 0, n_sft - 1).
+ * sky [n][3] (may be NULL): unit vectors toward the sources, in the frame of the data's
+ * ephemeris (sft_set_ephemeris).  Given, the scan runs its Doppler form (Sec. III.B): the
+ * phase is taken at the emission time t_s = t + r(t).n / c of each SFT row's detector, and
+ * f = f_s (1 + v.n/c), fdot = fdot_s (1 + v.n/c)^2 + f_s a.n/c at the SFT midpoint, with
+ * f_s, fdot_s the source-frame chirp at t_s (t_c is then the coalescence time at the source,
+ * up to the constant light travel time); fddot for the validity flag is fddot_s (1 + v.n/c)^3.
+ * The Doppler form exists for the Newtonian waveform with FP32-Kahan sums on F32 data or
+ * FP64 sums on F64 data (SFT_E_UNSUPPORTED otherwise). */
 typedef struct {
   const double* mc;
   const double* q;
@@ -147,6 +170,7 @@ typedef struct {
   const double* phi_c;
   const int32_t* a_first;
   const int32_t* a_last;
+  const double* sky;
 } sft_bank;
 
 /* Outputs, DEVICE memory owned by the caller: zp, zx are [n][2] (re, im);

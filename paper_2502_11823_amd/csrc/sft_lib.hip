@@ -136,6 +136,8 @@ struct sft_data {
   int32_t* g_rows;        // [n_groups][SFT_GROUP_MAX] rows, -1 = absent
   int32_t cu_count;       // compute units of the device
   sft_tuning tune;        // launch shape of the scans on this handle (0 fields = automatic)
+  double* g_eph;          // [n_groups][9] detector r/c, v/c, a/c at the group's midpoint (Doppler), or null;
+                          // set, every group holds one row
 };
 
 template <typename Bin> __device__ inline void store_bin(Bin* p, double re, double im);
@@ -325,7 +327,61 @@ extern "C" void sft_free_data(sft_data* h)
   if (h->g_rows) (void)hipFree(h->g_rows);
   if (h->fp) (void)hipFree(h->fp);
   if (h->fx) (void)hipFree(h->fx);
+  if (h->g_eph) (void)hipFree(h->g_eph);
   delete h;
+}
+
+// Doppler (Sec. III.B): detector positions per SFT row.  Rows of one start time (detectors at
+// different places) no longer share the waveform, so every row becomes its own timestamp group,
+// in the same time order.
+extern "C" sft_status sft_set_ephemeris(sft_data* h, const double* eph, void* hip_stream)
+{
+  if (!h || !eph) return fail(SFT_E_INVALID, "sft_set_ephemeris: null argument");
+  for (int64_t i = 0; i < (int64_t)h->n_sft * 9; ++i)
+    if (!std::isfinite(eph[i])) return fail(SFT_E_INVALID, "sft_set_ephemeris: non-finite entry %lld", (long long)i);
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<double> tmid(h->n_groups);
+  std::vector<int32_t> grows((size_t)h->n_groups * SFT_GROUP_MAX);
+  hipError_t e = hipMemcpyAsync(tmid.data(), h->g_tmid, tmid.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(grows.data(), h->g_rows, grows.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(SFT_E_DEVICE, "sft_set_ephemeris: %s", hipGetErrorString(e));
+  std::vector<double> nt, ne;
+  std::vector<int32_t> nr;
+  for (int32_t g = 0; g < h->n_groups; ++g)
+    for (int d = 0; d < SFT_GROUP_MAX; ++d) {
+      const int32_t r = grows[(size_t)g * SFT_GROUP_MAX + d];
+      if (r < 0) continue;
+      nt.push_back(tmid[g]);
+      nr.push_back(r);
+      for (int q = 1; q < SFT_GROUP_MAX; ++q) nr.push_back(-1);
+      for (int q = 0; q < 9; ++q) ne.push_back(eph[(size_t)r * 9 + q]);
+    }
+  double *d_t = nullptr, *d_e = nullptr;
+  int32_t* d_r = nullptr;
+  if ((e = hipMalloc(&d_t, nt.size() * sizeof(double))) == hipSuccess &&
+      (e = hipMalloc(&d_e, ne.size() * sizeof(double))) == hipSuccess &&
+      (e = hipMalloc(&d_r, nr.size() * sizeof(int32_t))) == hipSuccess &&
+      (e = hipMemcpyAsync(d_t, nt.data(), nt.size() * sizeof(double), hipMemcpyHostToDevice, st)) == hipSuccess &&
+      (e = hipMemcpyAsync(d_e, ne.data(), ne.size() * sizeof(double), hipMemcpyHostToDevice, st)) == hipSuccess &&
+      (e = hipMemcpyAsync(d_r, nr.data(), nr.size() * sizeof(int32_t), hipMemcpyHostToDevice, st)) == hipSuccess)
+    e = hipStreamSynchronize(st);   // the host vectors go out of scope here
+  if (e != hipSuccess) {
+    if (d_t) (void)hipFree(d_t);
+    if (d_e) (void)hipFree(d_e);
+    if (d_r) (void)hipFree(d_r);
+    return fail(e == hipErrorOutOfMemory ? SFT_E_NOMEM : SFT_E_DEVICE, "sft_set_ephemeris: %s", hipGetErrorString(e));
+  }
+  (void)hipFree(h->g_tmid);
+  (void)hipFree(h->g_rows);
+  if (h->g_eph) (void)hipFree(h->g_eph);
+  h->g_tmid = d_t;
+  h->g_rows = d_r;
+  h->g_eph = d_e;
+  h->n_groups = (int32_t)nt.size();
+  h->nd = 1;
+  return SFT_OK;
 }
 
 extern "C" void sft_default_opts(sft_opts* o)
@@ -435,9 +491,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
 }
 
 // wf: WF_NEWTON, WF_PN35 or WF_TABLE (the surrogate path); fs: the F-statistic form
-static ScanFn pick_kernel(const sft_data* d, const sft_opts* o, int wf, bool fs)
+static ScanFn pick_kernel(const sft_data* d, const sft_opts* o, int wf, bool fs, bool dop)
 {
   const int kern = o->kernel == SFT_KERNEL_DIRICHLET ? KERN_DIRICHLET : KERN_FRESNEL;
+  if (dop) return scan_pick_doppler(o->precision, fs ? 1 : 0, kern, o->K);
   if (fs) return scan_pick_fstat(o->precision, kern, o->K, d->nd);
   if (o->precision == SFT_PREC_FP64) return scan_pick_f64(wf, o->K, d->nd);
   if (d->storage == SFT_STORE_F32) {
@@ -494,6 +551,19 @@ static sft_status validate_fstat(const sft_data* d, const sft_opts* o, const sft
     return fail(SFT_E_UNSUPPORTED, "scan: the F-statistic is computed with the Newtonian waveform only");
   if (!((o->precision == SFT_PREC_FP32_KAHAN && d->storage == SFT_STORE_F32) || o->precision == SFT_PREC_FP64))
     return fail(SFT_E_UNSUPPORTED, "scan: the F-statistic needs FP32-Kahan sums on F32 data or FP64 sums");
+  return SFT_OK;
+}
+
+// The Doppler form (bank->sky set) needs the data's ephemeris, the Newtonian waveform and
+// FP32-Kahan sums on F32 data or FP64 sums on F64 data.
+static sft_status validate_doppler(const sft_data* d, const sft_opts* o, const sft_bank* bank)
+{
+  if (!bank || !bank->sky) return SFT_OK;
+  if (!d->g_eph) return fail(SFT_E_INVALID, "scan: bank.sky given but the data have no ephemeris (sft_set_ephemeris)");
+  if (o->waveform != SFT_WF_NEWTON)
+    return fail(SFT_E_UNSUPPORTED, "scan: the Doppler form is computed with the Newtonian waveform only");
+  if (!((o->precision == SFT_PREC_FP32_KAHAN && d->storage == SFT_STORE_F32) || o->precision == SFT_PREC_FP64))
+    return fail(SFT_E_UNSUPPORTED, "scan: the Doppler form needs FP32-Kahan sums on F32 data or FP64 sums");
   return SFT_OK;
 }
 
@@ -561,10 +631,12 @@ static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t 
   a.phi_c = bank->phi_c;
   a.a_first = bank->a_first;
   a.a_last = bank->a_last;
+  a.sky = bank->sky;
+  a.g_eph = d->g_eph;
   a.n_tmpl = n;
   a.wtab = wtab;
   P.xflags = xflags;
-  P.fn = pick_kernel(d, o, wf >= 0 ? wf : o->waveform, fs);
+  P.fn = pick_kernel(d, o, wf >= 0 ? wf : o->waveform, fs, bank->sky != nullptr);
   P.nacc = fs ? 7 : 6;
   const int B = t.block ? t.block : 256;
   a.n_tiles = (int32_t)((n + B - 1) / B);
@@ -930,7 +1002,8 @@ extern "C" sft_status sft_template_bank_scan(const sft_data* d, const sft_bank* 
 {
   sft_status s = validate_scan(d, o);
   if (s != SFT_OK) return s;
-  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK || n == 0) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK ||
+      (s = validate_doppler(d, o, bank)) != SFT_OK || n == 0) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   if (o->waveform == SFT_WF_SURROGATE) return surrogate_scan(d, bank, n, o, out, st);
   Prepared P;
@@ -974,7 +1047,8 @@ extern "C" sft_status sft_template_bank_scan_noalloc(const sft_data* d, const sf
 {
   sft_status s = validate_scan(d, o);
   if (s != SFT_OK) return s;
-  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK || n == 0) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK ||
+      (s = validate_doppler(d, o, bank)) != SFT_OK || n == 0) return s;
   if (o->waveform == SFT_WF_SURROGATE)
     return fail(SFT_E_UNSUPPORTED, "scan (no-alloc): the surrogate waveform needs its batch workspace");
   const bool fs = out->twoF != nullptr;
@@ -1028,7 +1102,8 @@ extern "C" sft_status sft_autotune(sft_data* d, const sft_bank* bank, int64_t n,
 {
   sft_status s = validate_scan(d, o);
   if (s != SFT_OK) return s;
-  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK ||
+      (s = validate_doppler(d, o, bank)) != SFT_OK) return s;
   if (n == 0) return fail(SFT_E_INVALID, "sft_autotune: needs at least one template");
   if (o->waveform == SFT_WF_SURROGATE)
     return fail(SFT_E_UNSUPPORTED, "sft_autotune: tune with the Newtonian or 3.5PN waveform");
@@ -1113,7 +1188,8 @@ extern "C" sft_status sft_plan_create(const sft_data* d, const sft_bank* bank, i
   *plan = nullptr;
   sft_status s = validate_scan(d, o);
   if (s != SFT_OK) return s;
-  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK) return s;
+  if ((s = validate_io(bank, n, out)) != SFT_OK || (s = validate_fstat(d, o, out)) != SFT_OK ||
+      (s = validate_doppler(d, o, bank)) != SFT_OK) return s;
   if (n == 0) return fail(SFT_E_INVALID, "sft_plan_create: needs at least one template");
   if (o->waveform == SFT_WF_SURROGATE)
     return fail(SFT_E_UNSUPPORTED, "sft_plan_create: the surrogate waveform is not captured into graphs");

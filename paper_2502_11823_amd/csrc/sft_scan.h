@@ -7,7 +7,9 @@
 // the coherent accumulation of Eq. efficient and of the norm, in FP64 or FP32 (Kahan or
 // plain).  Writes one partial per (template, chunk); the finalize kernel combines them.
 // FS = 1 (the F-statistic form, Sec. II.B) also accumulates the cross norm
-// sum F+ Fx A^2 T / S, and keeps the three norm sums in FP64.
+// sum F+ Fx A^2 T / S, and keeps the three norm sums in FP64.  DP = 1 (the Doppler form,
+// Sec. III.B) evaluates the chirp at the emission time t + r.n/c of each SFT row's detector
+// and carries the factor dt_s/dt into f and fdot (one row per timestamp group).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -141,7 +143,7 @@ __device__ inline void stage_window(Bin* sw, const Bin* const* rp, int sb, int w
 // a group (one per detector) share the SFT midpoint, hence the chirp, the window and
 // all 2K+1 kernel weights: those are evaluated once per group and contracted with the
 // bins of each of the ND rows (the projector Lambda carries the detector dependence).
-template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS, int DP>
 __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab,
                                           Bin* sw);
 
@@ -160,7 +162,7 @@ constexpr int scan_min_waves()
   return 1;
 }
 
-template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS = 0>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS = 0, int DP = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_min_waves<PREC, KERN, KC, ND, WF>())))
 void scan_kernel(ScanArgs a)
 {
@@ -193,12 +195,13 @@ void scan_kernel(ScanArgs a)
     const int tile = item % a.n_tiles;
     const int c = item / a.n_tiles;
     const int64_t m = (int64_t)tile * blockDim.x + threadIdx.x;
-    if (m < a.n_tmpl) scan_item<Bin, PREC, KERN, KC, ND, WF, FS>(a, K, m, c, tab, stage + (threadIdx.x >> 6) * (ND * WST));
+    if (m < a.n_tmpl)
+      scan_item<Bin, PREC, KERN, KC, ND, WF, FS, DP>(a, K, m, c, tab, stage + (threadIdx.x >> 6) * (ND * WST));
     if (!a.persistent) break;
   }
 }
 
-template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS, int DP>
 __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab,
                                           Bin* sw)
 {
@@ -220,6 +223,13 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
   }
   const double tc = a.t_c[m];
   const double phic = a.phi_c ? a.phi_c[m] : 0.0;
+  // Doppler form: unit vector toward the source
+  double nx = 0.0, ny = 0.0, nz = 0.0;
+  if constexpr (DP != 0) {
+    nx = a.sky[3 * m];
+    ny = a.sky[3 * m + 1];
+    nz = a.sky[3 * m + 2];
+  }
   // 3.5PN: symmetric mass ratio, total mass, nu/(5M), nu^(2/5) and the series coefficients
   double nu = 0.25, Mt = 0.0, inv5Mnu = 0.0, nu25 = 0.0;
   PNCoef pcf{};
@@ -268,7 +278,15 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       any = any || act[d];
     }
     if (!any) continue;
-    const double tau = tc - tmid;
+    // Doppler form: Roemer delay r.n/c and its rates v.n/c, a.n/c of the row's detector
+    double dl = 0.0, dl1 = 0.0, dl2 = 0.0;
+    if constexpr (DP != 0) {
+      const double* e = a.g_eph + 9 * (int64_t)g;
+      dl = fma(e[0], nx, fma(e[1], ny, e[2] * nz));
+      dl1 = fma(e[3], nx, fma(e[4], ny, e[5] * nz));
+      dl2 = fma(e[6], nx, fma(e[7], ny, e[8] * nz));
+    }
+    const double tau = DP != 0 ? tc - (tmid + dl) : tc - tmid;
     if (!(tau > 0.0)) {
       fl |= kFlagTau;
       continue;
@@ -286,6 +304,15 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       ch.dres = w[4 * ps];
     } else {
       ch = newton_chirp(tau, inv5M, cf, phic, T);
+    }
+    if constexpr (DP != 0) {
+      // f = f_s (1 + D'), fdot = fdot_s (1 + D')^2 + f_s D'' (in bins: times T and T^2),
+      // fddot scaled by (1 + D')^3 for the validity flag
+      const double g1 = 1.0 + dl1;
+      const double ks = ch.kappa;
+      ch.kappa = ks * g1;
+      ch.beta = fma(ch.beta, g1 * g1, ks * dl2 * T);
+      ch.dres *= g1 * g1 * g1;
     }
     if (a.delta_max > 0.0 && ch.dres > a.delta_max) fl |= kFlagTaylor;
     if (!(ch.kappa < 1.0e9)) {
@@ -670,6 +697,19 @@ static ScanFn pick_kern(int kern, int K, int nd)
 {
   return kern == KERN_DIRICHLET ? pick_k<Bin, PREC, KERN_DIRICHLET, WF, FS>(K, nd)
                                 : pick_k<Bin, PREC, KERN_FRESNEL, WF, FS>(K, nd);
+}
+
+// Doppler form: one row per timestamp group
+template <typename Bin, int PREC, int KERN, int FS>
+static ScanFn pick_doppler_k(int K)
+{
+  if constexpr (PREC == SFT_PREC_FP64) {
+    return K == 4 ? scan_kernel<Bin, PREC, KERN, 4, 1, WF_NEWTON, FS, 1> : scan_kernel<Bin, PREC, KERN, -1, 1, WF_NEWTON, FS, 1>;
+  } else {
+    if constexpr (KERN == KERN_FRESNEL)
+      if (K == 32) return scan_kernel<Bin, PREC, KERN, 32, 1, WF_NEWTON, FS, 1>;
+    return K == 8 ? scan_kernel<Bin, PREC, KERN, 8, 1, WF_NEWTON, FS, 1> : scan_kernel<Bin, PREC, KERN, -1, 1, WF_NEWTON, FS, 1>;
+  }
 }
 
 template <typename Bin, int PREC>

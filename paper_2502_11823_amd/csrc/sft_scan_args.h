@@ -36,6 +36,8 @@ struct ScanArgs {
   double* part;      // [n_chunks][6 (+1 in the F-statistic form)][n_tmpl]
   uint32_t* pflags;  // [n_chunks][n_tmpl]
   const double* wtab;  // chirp table (WF_TABLE): 5 planes [n_groups][n_tmpl] kappa, phase, amp, beta, dres
+  const double* sky;   // Doppler form: [n_tmpl][3] unit vectors toward the sources
+  const double* g_eph; // Doppler form: [n_groups][9] detector r/c, v/c, a/c (one row per group)
 };
 
 enum { KERN_DIRICHLET = 0, KERN_FRESNEL = 1 };
@@ -59,3 +61,6 @@ ScanFn scan_pick_bf16(int prec, int kern, int K, int nd);
 // the F-statistic form (Newtonian waveform; prec SFT_PREC_FP32_KAHAN with F32 storage or
 // SFT_PREC_FP64 with F64 storage and the Dirichlet kernel)
 ScanFn scan_pick_fstat(int prec, int kern, int K, int nd);
+// the Doppler form (one row per timestamp group; Newtonian waveform; fs selects the
+// F-statistic form as well)
+ScanFn scan_pick_doppler(int prec, int fs, int kern, int K);

@@ -48,7 +48,8 @@ class Opts(ctypes.Structure):
 
 class Bank(ctypes.Structure):
     _fields_ = [("mc", ctypes.c_void_p), ("q", ctypes.c_void_p), ("t_c", ctypes.c_void_p),
-                ("phi_c", ctypes.c_void_p), ("a_first", ctypes.c_void_p), ("a_last", ctypes.c_void_p)]
+                ("phi_c", ctypes.c_void_p), ("a_first", ctypes.c_void_p), ("a_last", ctypes.c_void_p),
+                ("sky", ctypes.c_void_p)]
 
 
 class Out(ctypes.Structure):
@@ -78,7 +79,8 @@ EXPORTS = ["sft_load_data", "sft_free_data", "sft_default_opts", "sft_template_b
            "sft_get_tuning", "sft_set_tuning", "sft_autotune", "sft_plan_create", "sft_plan_launch",
            "sft_plan_destroy", "sft_surrogate_param_count", "sft_surrogate_create", "sft_surrogate_free",
            "sft_surrogate_get_params", "sft_surrogate_targets", "sft_surrogate_loss_grad", "sft_surrogate_adam",
-           "sft_surrogate_train", "sft_surrogate_infer", "sft_template_bank_scan_noalloc"]
+           "sft_surrogate_train", "sft_surrogate_infer", "sft_template_bank_scan_noalloc",
+           "sft_set_ephemeris"]
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 _lib = None
@@ -102,6 +104,8 @@ def lib():
     L.sft_template_bank_scan.argtypes = [P, ctypes.POINTER(Bank), ctypes.c_int64, ctypes.POINTER(Opts),
                                          ctypes.POINTER(Out), P]
     L.sft_template_bank_scan.restype = ctypes.c_int32
+    L.sft_set_ephemeris.argtypes = [P, P, P]
+    L.sft_set_ephemeris.restype = ctypes.c_int32
     L.sft_template_bank_scan_noalloc.argtypes = L.sft_template_bank_scan.argtypes
     L.sft_template_bank_scan_noalloc.restype = ctypes.c_int32
     D = ctypes.c_double
@@ -223,6 +227,11 @@ class SFTData:
         return cls(w.t_start, w.n_samples, w.t_sft, w.k_lo, w.x_bins, w.psd, w.fplus, w.fcross,
                    storage=storage, stream=stream)
 
+    def set_ephemeris(self, eph, stream=None):
+        """Detector r/c, v/c, a/c per SFT row at its midpoint, [n_sft, 9] (Doppler form)."""
+        e = np.ascontiguousarray(np.reshape(eph, (self.n_sft, 9)), dtype=np.float64)
+        _check(lib().sft_set_ephemeris(self.handle, e.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().sft_free_data(self.handle)
@@ -238,7 +247,7 @@ class SFTData:
 def bank_to_device(bank: Dict[str, np.ndarray], device="cuda"):
     import torch
     out = {}
-    for k in ("mc", "q", "t_c", "phi_c"):
+    for k in ("mc", "q", "t_c", "phi_c", "sky"):
         if k in bank and bank[k] is not None:
             out[k] = torch.as_tensor(np.ascontiguousarray(bank[k], dtype=np.float64), device=device)
     for k in ("a_first", "a_last"):
@@ -271,8 +280,11 @@ def _bank_struct(bank_t):
     for k, t in bank_t.items():
         if not t.is_cuda or not t.is_contiguous():
             raise ValueError("bank array %s must be a contiguous device tensor" % k)
+    sky = bank_t.get("sky")
+    if sky is not None and tuple(sky.shape) != (int(bank_t["mc"].numel()), 3):
+        raise ValueError("bank sky must be [n, 3]")
     return Bank(_tp(bank_t.get("mc")), _tp(bank_t.get("q")), _tp(bank_t.get("t_c")),
-                _tp(bank_t.get("phi_c")), _tp(bank_t.get("a_first")), _tp(bank_t.get("a_last")))
+                _tp(bank_t.get("phi_c")), _tp(bank_t.get("a_first")), _tp(bank_t.get("a_last")), _tp(sky))
 
 
 def _out_struct(out):
