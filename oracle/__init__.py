@@ -61,6 +61,10 @@ def _load():
     lib.orc_faddeeva_eval.argtypes = [L, P, P]
     lib.orc_rdft.argtypes = [P, L, P]
     lib.orc_make_sfts.argtypes = [P, L, L, L, D, P]
+    lib.orc_median_bias.argtypes = [Int]
+    lib.orc_median_bias.restype = D
+    lib.orc_psd_running_median.argtypes = [P, L, D, Int, L, L, P]
+    lib.orc_strain_sfts.argtypes = [P, L, L, D, Int, L, L, P, P, P]
     lib.orc_waveform.argtypes = [Int, D, D, D, D, D, D, P]
     lib.orc_waveform_array.argtypes = [Int, D, D, D, D, P, L, D, P]
     lib.orc_ip_params.argtypes = [L, L, D, L, L, P, P, P, P, P, P, P, P, P, P,
@@ -156,6 +160,34 @@ def make_sfts(x, n, n_sft, dt):
     if rc != 0:
         raise ValueError("series shorter than n_sft * n")
     return _cplx(out).reshape(n_sft, nb)
+
+
+def median_bias(w):
+    """Expected median of 2w+1 exponential variables of unit mean (reading R27)."""
+    return _load().orc_median_bias(int(w))
+
+
+def psd_running_median(power, n, T, w, k_lo, n_bins):
+    """Per-SFT PSD from the periodogram power[0..n/2] by the bias-corrected running median."""
+    p = _f64(power)
+    out = np.empty(int(n_bins))
+    if _load().orc_psd_running_median(_ptr(p), int(n), float(T), int(w), int(k_lo), int(n_bins), _ptr(out)) != 0:
+        raise ValueError("band or block outside [0, n/2]")
+    return out
+
+
+def strain_sfts(x, n, dt, w, k_lo, n_bins):
+    """SFTs (band bins, complex [n_seg, n_bins]), PSDs [n_seg, n_bins] and the keep flags of the
+    consecutive segments of a strain series (Eq. d_SFT; reading R27)."""
+    x = _f64(x)
+    n_seg = x.size // int(n)
+    bins = np.empty(2 * n_seg * int(n_bins))
+    psd = np.empty(n_seg * int(n_bins))
+    keep = np.empty(n_seg, np.int32)
+    if _load().orc_strain_sfts(_ptr(x), x.size, int(n), float(dt), int(w), int(k_lo), int(n_bins), _ptr(bins),
+                               _ptr(psd), _ptr(keep)) != 0:
+        raise ValueError("band or block outside [0, n/2]")
+    return _cplx(bins).reshape(n_seg, int(n_bins)), psd.reshape(n_seg, int(n_bins)), keep
 
 
 # --------------------------------------------------------------------------- waveform

@@ -161,6 +161,88 @@ int orc_make_sfts(const double *x, long n_total, long n, long n_sft, double dt, 
   return 0;
 }
 
+/* Per-SFT noise PSD (reading R27; the paper leaves the estimator to the whitening literature
+ * it cites in Sec. III.B): the running median of the SFT's own periodogram
+ * P[k] = |x~[k]|^2 over a block of N = 2w+1 bins centred on k (shifted, not clipped, at the
+ * ends of [0, n/2], so that every block holds N bins), divided by the expected median of N
+ * independent exponential variables of unit mean, B(N) = sum_{i=0}^{w} 1/(N - i) (the mean of
+ * the (w+1)-th order statistic), and scaled by 2/T, since E|x~|^2 = T S / 2 for the one-sided
+ * PSD S of stationary Gaussian noise under a rectangular window.
+ * pw: [n/2 + 1] periodogram; out[i] = S at bin k_lo + i, i < n_bins.  Returns -1 when
+ * n/2 + 1 < N or the band leaves [0, n/2]. */
+static int orc_cmp_double(const void *a, const void *b)
+{
+  double x = *(const double *)a, y = *(const double *)b;
+  return (x > y) - (x < y);
+}
+
+double orc_median_bias(int w)
+{
+  long N = 2L * w + 1;
+  double B = 0.0;
+  for (long i = 0; i <= w; i++) B += 1.0 / (double)(N - i);
+  return B;
+}
+
+int orc_psd_running_median(const double *pw, long n, double T, int w, long k_lo, long n_bins, double *out)
+{
+  long nh = n / 2, N = 2L * w + 1;
+  if (w < 0 || nh + 1 < N || k_lo < 0 || k_lo + n_bins - 1 > nh) return -1;
+  double *blk = (double *)malloc(sizeof(double) * (size_t)N);
+  if (!blk) return -1;
+  double B = orc_median_bias(w);
+  for (long i = 0; i < n_bins; i++) {
+    long k = k_lo + i;
+    long s = k - w;
+    if (s < 0) s = 0;
+    if (s + N - 1 > nh) s = nh - (N - 1);
+    memcpy(blk, pw + s, sizeof(double) * (size_t)N);
+    qsort(blk, (size_t)N, sizeof(double), orc_cmp_double);
+    out[i] = 2.0 * blk[w] / (T * B);
+  }
+  free(blk);
+  return 0;
+}
+
+/* SFTs and PSDs of a raw strain series (Sec. III.B, Eq. d_SFT; reading R27): segment a covers
+ * samples [a n, (a+1) n).  A segment holding a non-finite sample is a data gap: keep[a] = 0
+ * and its outputs are zero.  bins: [n_seg][n_bins][2] x~ of the band, psd: [n_seg][n_bins]. */
+int orc_strain_sfts(const double *x, long n_total, long n, double dt, int w, long k_lo, long n_bins,
+                    double *bins, double *psd, int32_t *keep)
+{
+  long n_seg = n_total / n, nh = n / 2;
+  double *sp = (double *)malloc(sizeof(double) * (size_t)(2 * (nh + 1)));
+  double *pw = (double *)malloc(sizeof(double) * (size_t)(nh + 1));
+  if (!sp || !pw) { free(sp); free(pw); return -1; }
+  int rc = 0;
+  for (long a = 0; a < n_seg && rc == 0; a++) {
+    const double *seg = x + a * n;
+    int ok = 1;
+    for (long j = 0; j < n; j++)
+      if (!isfinite(seg[j])) { ok = 0; break; }
+    keep[a] = ok;
+    double *bo = bins + a * 2 * n_bins, *po = psd + a * n_bins;
+    if (!ok) {
+      memset(bo, 0, sizeof(double) * (size_t)(2 * n_bins));
+      memset(po, 0, sizeof(double) * (size_t)n_bins);
+      continue;
+    }
+    orc_rdft(seg, n, sp);
+    for (long k = 0; k <= nh; k++) {
+      double re = dt * sp[2 * k], im = dt * sp[2 * k + 1];
+      pw[k] = re * re + im * im;
+    }
+    for (long i = 0; i < n_bins; i++) {
+      bo[2 * i] = dt * sp[2 * (k_lo + i)];
+      bo[2 * i + 1] = dt * sp[2 * (k_lo + i) + 1];
+    }
+    rc = orc_psd_running_median(pw, n, dt * (double)n, w, k_lo, n_bins, po);
+  }
+  free(sp);
+  free(pw);
+  return rc;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Fresnel integrals and the auxiliary function G.                           */
 /* ------------------------------------------------------------------------- */
