@@ -113,6 +113,55 @@ sft_status sft_load_data(const sft_data_desc* desc, const double* t_start, const
 void sft_free_data(sft_data* data);
 
 /*
+ * SFTs from raw strain on the device (Sec. III.B segmentation, Eq. d_SFT), with the per-SFT
+ * noise PSD estimated from the SFT itself: the running median of the periodogram
+ * P[k] = |x~[k]|^2 over blocks of 2w+1 bins centred on k (shifted at the ends of [0, n/2]),
+ * divided by B = sum_{i=0}^{w} 1/(2w+1-i) (the mean of the middle order statistic of 2w+1
+ * unit exponentials) and scaled by 2/T (E|x~|^2 = T S / 2 for stationary Gaussian noise).
+ * Each detector's series is cut into consecutive segments of n samples, segment a covering
+ * samples [a n, (a+1) n) and starting at t0 + a n dt; a segment holding a non-finite sample is
+ * a data gap (missing SFT).
+ */
+typedef struct {
+  int32_t n_det;        /* detector series */
+  int32_t n_samples;    /* samples per SFT, n: a power of two in [16, 16384] */
+  int64_t n_total;      /* samples per series; n_seg = n_total / n segments (a remainder is unused) */
+  double dt;            /* sampling interval [s]; T = n dt */
+  double t0;            /* time of sample 0 of every series [s] */
+  int32_t k_lo;         /* first stored bin */
+  int32_t n_bins;       /* stored bins k_lo .. k_lo + n_bins - 1, all <= n/2 */
+  int32_t psd_w;        /* running-median half width w; 2w + 1 <= n/2 + 1 */
+  int32_t storage;      /* SFT_STORE_* of the handle made by sft_load_strain */
+  int32_t reserved;     /* must be 0 */
+  int32_t reserved2;    /* must be 0 */
+} sft_strain_desc;
+
+/*
+ * sft_make_sfts -- the SFTs and PSDs of every segment, asynchronously on hip_stream (returns
+ * after the launch has been enqueued and its small host uploads are done).
+ *   x    : DEVICE [n_det][n_total] strain series (FP64), read only.
+ *   bins : DEVICE out [n_det][n_seg][n_bins][2] x~ = dt sum_j x_j e^{-2 pi i j k / n} of the band.
+ *   psd  : DEVICE out [n_det][n_seg][n_bins] the estimated one-sided PSD.
+ *   keep : DEVICE out [n_det][n_seg] 1, or 0 for a gap (whose bins and PSD are written as 0).
+ * Errors: SFT_E_INVALID (null, bad descriptor, band or block outside [0, n/2]),
+ * SFT_E_UNSUPPORTED (n not a power of two in [16, 16384]), SFT_E_RANGE, SFT_E_DEVICE.
+ */
+sft_status sft_make_sfts(const sft_strain_desc* desc, const double* x, double* bins, double* psd, int32_t* keep,
+                         void* hip_stream);
+
+/*
+ * sft_load_strain -- sft_make_sfts followed by sft_load_data on the device: the segments that
+ * are not gaps become the handle's SFT rows (detector by detector, in time order), whitened by
+ * their own PSD estimates.
+ *   fplus, fcross : host [n_det][n_seg] antenna patterns per segment, or NULL (F+ = 1, Fx = 0).
+ *   n_rows        : host out (may be NULL), the number of SFT rows kept.
+ * Synchronous on hip_stream.  Errors: those of sft_make_sfts and sft_load_data; SFT_E_INVALID
+ * when every segment is a gap.
+ */
+sft_status sft_load_strain(const sft_strain_desc* desc, const double* x, const double* fplus, const double* fcross,
+                           void* hip_stream, sft_data** out, int32_t* n_rows);
+
+/*
  * sft_set_ephemeris -- detector motion for the Doppler form of the scan (Sec. III.B: the
  * phase as a function of the emission time t_s(t; n), the frequency
  * (1/2 pi)(dphi/dt_s)(dt_s/dt)).

@@ -208,19 +208,12 @@ static void build_groups(const double* t_start, int32_t n_sft, double T, std::ve
   }
 }
 
-extern "C" sft_status sft_load_data(const sft_data_desc* d, const double* t_start, const double* x_bins,
-                                    const double* psd, const double* fplus, const double* fcross,
-                                    void* hip_stream, sft_data** out)
+// The device part of loading: raw bins dx [n_sft][n_bins][2] and PSD dp [n_sft][n_bins] (FP64,
+// device) are whitened, converted and packed by load_kernel; the timestamp groups are built
+// from the host start times.  dx and dp stay owned by the caller.
+static sft_status load_device(const sft_data_desc* d, const double* t_start, const double* dx, const double* dp,
+                              const double* fplus, const double* fcross, hipStream_t st, sft_data** out)
 {
-  if (!d || !t_start || !x_bins || !psd || !out) return fail(SFT_E_INVALID, "sft_load_data: null argument");
-  *out = nullptr;
-  if (d->n_sft < 1 || d->n_samples < 2 || (d->n_samples & 1) || !(d->t_sft > 0.0) || d->reserved != 0)
-    return fail(SFT_E_INVALID, "sft_load_data: bad descriptor (n_sft=%d n=%d T=%g)", d->n_sft, d->n_samples, d->t_sft);
-  if (d->k_lo < 0 || d->n_bins < 1 || d->k_lo + d->n_bins - 1 > d->n_samples / 2)
-    return fail(SFT_E_INVALID, "sft_load_data: band [%d, %d) outside [0, n/2]", d->k_lo, d->k_lo + d->n_bins);
-  if (d->storage != SFT_STORE_F64 && d->storage != SFT_STORE_F32 && d->storage != SFT_STORE_BF16)
-    return fail(SFT_E_INVALID, "sft_load_data: unknown storage %d", d->storage);
-  hipStream_t st = (hipStream_t)hip_stream;
   sft_data* h = new sft_data();
   std::memset(h, 0, sizeof(*h));
   HIP_OR_FAIL(hipGetDevice(&h->device));
@@ -241,44 +234,29 @@ extern "C" sft_status sft_load_data(const sft_data_desc* d, const double* t_star
   size_t ne = (size_t)d->n_sft * h->n_ext;
   size_t bin_sz = d->storage == SFT_STORE_F64 ? sizeof(double2) : d->storage == SFT_STORE_F32 ? sizeof(float2) : sizeof(bf16x2);
   size_t ps_sz = d->storage == SFT_STORE_F64 ? sizeof(double) : sizeof(float);
-  double *dx = nullptr, *dp = nullptr, *dts = nullptr;
-  auto cleanup = [&]() {
-    if (dx) (void)hipFree(dx);
-    if (dp) (void)hipFree(dp);
-    if (dts) (void)hipFree(dts);
-  };
   hipError_t e = hipSuccess;
   if ((e = hipMalloc(&h->bins, ne * bin_sz)) != hipSuccess || (e = hipMalloc(&h->psd, nb * ps_sz)) != hipSuccess ||
       (e = hipMalloc(&h->fp, d->n_sft * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&h->fx, d->n_sft * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&dx, nb * 2 * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&dp, nb * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&dts, d->n_sft * sizeof(double))) != hipSuccess) {
-    cleanup();
+      (e = hipMalloc(&h->fx, d->n_sft * sizeof(double))) != hipSuccess) {
     sft_free_data(h);
     return fail(e == hipErrorOutOfMemory ? SFT_E_NOMEM : SFT_E_DEVICE, "sft_load_data: hipMalloc: %s", hipGetErrorString(e));
   }
-  std::string err;
   do {
-    if ((e = hipMemcpyAsync(dx, x_bins, nb * 2 * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess) break;
-    if ((e = hipMemcpyAsync(dp, psd, nb * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess) break;
-    if ((e = hipMemcpyAsync(dts, t_start, d->n_sft * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess) break;
     if (fplus) e = hipMemcpyAsync(h->fp, fplus, d->n_sft * sizeof(double), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) break;
     if (fcross) e = hipMemcpyAsync(h->fx, fcross, d->n_sft * sizeof(double), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) break;
     if (!fplus || !fcross) {
       // defaults F+ = 1, Fx = 0 staged from the host
-      double* tmp = new double[d->n_sft];
+      std::vector<double> tmp(d->n_sft);
       if (!fplus) {
         for (int i = 0; i < d->n_sft; i++) tmp[i] = 1.0;
-        e = hipMemcpy(h->fp, tmp, d->n_sft * sizeof(double), hipMemcpyHostToDevice);
+        e = hipMemcpy(h->fp, tmp.data(), d->n_sft * sizeof(double), hipMemcpyHostToDevice);
       }
       if (e == hipSuccess && !fcross) {
         for (int i = 0; i < d->n_sft; i++) tmp[i] = 0.0;
-        e = hipMemcpy(h->fx, tmp, d->n_sft * sizeof(double), hipMemcpyHostToDevice);
+        e = hipMemcpy(h->fx, tmp.data(), d->n_sft * sizeof(double), hipMemcpyHostToDevice);
       }
-      delete[] tmp;
       if (e != hipSuccess) break;
     }
     unsigned blocks = (unsigned)((ne + 255) / 256);
@@ -309,13 +287,133 @@ extern "C" sft_status sft_load_data(const sft_data_desc* d, const double* t_star
       e = hipStreamSynchronize(st);   // the host vectors go out of scope here
     }
   } while (0);
-  cleanup();
   if (e != hipSuccess) {
     sft_free_data(h);
     return fail(SFT_E_DEVICE, "sft_load_data: %s", hipGetErrorString(e));
   }
   *out = h;
   return SFT_OK;
+}
+
+static sft_status validate_desc(const sft_data_desc* d)
+{
+  if (d->n_sft < 1 || d->n_samples < 2 || (d->n_samples & 1) || !(d->t_sft > 0.0) || d->reserved != 0)
+    return fail(SFT_E_INVALID, "sft_load_data: bad descriptor (n_sft=%d n=%d T=%g)", d->n_sft, d->n_samples, d->t_sft);
+  if (d->k_lo < 0 || d->n_bins < 1 || d->k_lo + d->n_bins - 1 > d->n_samples / 2)
+    return fail(SFT_E_INVALID, "sft_load_data: band [%d, %d) outside [0, n/2]", d->k_lo, d->k_lo + d->n_bins);
+  if (d->storage != SFT_STORE_F64 && d->storage != SFT_STORE_F32 && d->storage != SFT_STORE_BF16)
+    return fail(SFT_E_INVALID, "sft_load_data: unknown storage %d", d->storage);
+  return SFT_OK;
+}
+
+extern "C" sft_status sft_load_data(const sft_data_desc* d, const double* t_start, const double* x_bins,
+                                    const double* psd, const double* fplus, const double* fcross,
+                                    void* hip_stream, sft_data** out)
+{
+  if (!d || !t_start || !x_bins || !psd || !out) return fail(SFT_E_INVALID, "sft_load_data: null argument");
+  *out = nullptr;
+  sft_status s = validate_desc(d);
+  if (s != SFT_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  size_t nb = (size_t)d->n_sft * d->n_bins;
+  double *dx = nullptr, *dp = nullptr;
+  hipError_t e = hipMalloc(&dx, nb * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&dp, nb * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpyAsync(dx, x_bins, nb * 2 * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dp, psd, nb * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) s = load_device(d, t_start, dx, dp, fplus, fcross, st, out);   // synchronises st
+  if (dx) (void)hipFree(dx);
+  if (dp) (void)hipFree(dp);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? SFT_E_NOMEM : SFT_E_DEVICE, "sft_load_data: %s", hipGetErrorString(e));
+  return s;
+}
+
+// rows of the kept segments: dx[r] = bins[src[r]], dp[r] = psd[src[r]]
+__global__ void gather_rows_kernel(const double* __restrict__ bins, const double* __restrict__ psd,
+                                   const int32_t* __restrict__ src, int32_t n_rows, int32_t n_bins,
+                                   double* __restrict__ dx, double* __restrict__ dp)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_rows * n_bins) return;
+  const int64_t r = i / n_bins, k = i - r * n_bins;
+  const int64_t s = (int64_t)src[r] * n_bins + k;
+  dx[2 * i] = bins[2 * s];
+  dx[2 * i + 1] = bins[2 * s + 1];
+  dp[i] = psd[s];
+}
+
+extern "C" sft_status sft_load_strain(const sft_strain_desc* sd, const double* x, const double* fplus,
+                                      const double* fcross, void* hip_stream, sft_data** out, int32_t* n_rows)
+{
+  if (!sd || !x || !out) return fail(SFT_E_INVALID, "sft_load_strain: null argument");
+  *out = nullptr;
+  if (sd->n_samples < 16 || sd->n_total < sd->n_samples || sd->n_det < 1)
+    return fail(SFT_E_INVALID, "sft_load_strain: bad descriptor");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t n_seg = sd->n_total / sd->n_samples;
+  const int64_t n_all = n_seg * sd->n_det;
+  const size_t nb = (size_t)n_all * sd->n_bins;
+  double *bins = nullptr, *psd = nullptr, *dx = nullptr, *dp = nullptr;
+  int32_t *keep = nullptr, *src = nullptr;
+  sft_status s = SFT_OK;
+  hipError_t e = hipMalloc(&bins, nb * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&psd, nb * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&keep, (size_t)n_all * sizeof(int32_t));
+  std::vector<int32_t> hk(n_all);
+  if (e == hipSuccess) s = sft_make_sfts(sd, x, bins, psd, keep, hip_stream);
+  if (e == hipSuccess && s == SFT_OK) {
+    e = hipMemcpyAsync(hk.data(), keep, hk.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  std::vector<int32_t> rows;
+  std::vector<double> t_start, fp, fx;
+  if (e == hipSuccess && s == SFT_OK) {
+    const double T = sd->dt * sd->n_samples;
+    for (int64_t a = 0; a < n_all; ++a) {
+      if (!hk[a]) continue;
+      rows.push_back((int32_t)a);
+      t_start.push_back(sd->t0 + (double)(a % n_seg) * T);
+      fp.push_back(fplus ? fplus[a] : 1.0);
+      fx.push_back(fcross ? fcross[a] : 0.0);
+    }
+    if (rows.empty()) s = fail(SFT_E_INVALID, "sft_load_strain: every segment is a gap");
+  }
+  if (e == hipSuccess && s == SFT_OK) {
+    const size_t nr = rows.size() * (size_t)sd->n_bins;
+    e = hipMalloc(&dx, nr * 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&dp, nr * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&src, rows.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpyAsync(src, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, bins, psd, src,
+                         (int32_t)rows.size(), sd->n_bins, dx, dp);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      sft_data_desc dd{};
+      dd.n_sft = (int32_t)rows.size();
+      dd.n_samples = sd->n_samples;
+      dd.t_sft = sd->dt * sd->n_samples;
+      dd.k_lo = sd->k_lo;
+      dd.n_bins = sd->n_bins;
+      dd.storage = sd->storage;
+      s = validate_desc(&dd);
+      if (s == SFT_OK) s = load_device(&dd, t_start.data(), dx, dp, fp.data(), fx.data(), st, out);   // synchronises st
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  for (void* p : {(void*)bins, (void*)psd, (void*)keep, (void*)dx, (void*)dp, (void*)src})
+    if (p) (void)hipFree(p);
+  if (e != hipSuccess) {
+    if (*out) {
+      sft_free_data(*out);
+      *out = nullptr;
+    }
+    return fail(e == hipErrorOutOfMemory ? SFT_E_NOMEM : SFT_E_DEVICE, "sft_load_strain: %s", hipGetErrorString(e));
+  }
+  if (s == SFT_OK && n_rows) *n_rows = (int32_t)rows.size();
+  return s;
 }
 
 extern "C" void sft_free_data(sft_data* h)

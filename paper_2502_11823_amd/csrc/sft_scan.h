@@ -422,10 +422,27 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       ib = ib * fma(-bpos, ib, 2.0);
       ib = ib * fma(-bpos, ib, 2.0);
       const double dm64 = ds64 - 0.5 * bpos;
+      // Run-time K kernels (windows up to 129 bins, drifts beyond a hundred bins): p-+ of bin jj
+      // as an exact integer plus an FP32 fraction split from the FP64 values, each rounded once
+      // (to ulp(|p|) / 2); dm - jj in FP32 carries the rounding of beta / 2 (~ulp(beta)) into
+      // every bin.  The compile-time windows (drift up to a few tens of bins) keep dm - jj: the
+      // split costs them registers (a larger spill, ~5% of the ground scan).
+      constexpr bool PSPLIT = KC < 0;
+      const double dp64 = ds64 + 0.5 * bpos;
+      const double nmr = PSPLIT ? rint(dm64) : 0.0, npr = PSPLIT ? rint(dp64) : 0.0;
+      const int nmi = (int)nmr, npi = (int)npr;
+      const float fm = (float)(dm64 - nmr), fpf = (float)(dp64 - npr);
       // central bin from its direct series (small drift and small delta)
       const bool cser = bp <= SFT_SERIES_BETA && fabsf(ds) <= SFT_SERIES_DELTA;
       // one row: sums of b e(p-) and b e(p+) (unused with several rows)
-      float smr = 0.f, smi = 0.f, spr = 0.f, spi = 0.f;
+      // Bin sums: FP32 for the compile-time windows (17 or 65 bins); FP64 for the run-time K
+      // kernels (windows up to 129 bins, where a plain FP32 running sum loses ~eps sqrt(N/2)
+      // ~ 5e-7 of the SFT's term), with the products still formed in FP32.
+      using BS = typename std::conditional<(KC < 0 && PREC != SFT_PREC_FP64), double, float>::type;
+      BS smr = 0, smi = 0, spr = 0, spi = 0;
+      BS wre[ND], wim[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) wre[d] = wim[d] = (BS)0;
       // Outer bins: jj >= jup or jj <= jdn puts both endpoints of a lane at least one bin
       // beyond the asymptotic threshold |p| = SFT_G_VASYM sqrt(beta / 2), with no stationary
       // point inside the SFT (p- and p+ of one sign).  With the bounds taken over the active
@@ -480,7 +497,14 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
           if constexpr (STG) BinIO<Bin>::load(sw + d * WST + (idx - sb), bre[d], bim[d]);
           else BinIO<Bin>::load(rp[d] + idx, bre[d], bim[d]);
         }
-        const float pm = dm - (float)jj, pp = dp - (float)jj;
+        float pm, pp;
+        if constexpr (PSPLIT) {
+          pm = (float)(nmi - jj) + fm;
+          pp = (float)(npi - jj) + fpf;
+        } else {
+          pm = dm - (float)jj;
+          pp = dp - (float)jj;
+        }
         float2 em, ep;
         if constexpr (TR < 4) {
           em = fres_endpoint_asym<TR>(pm, bq);
@@ -522,15 +546,27 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
           const float hi = fmaf(-rhr, ep.y, fmaf(-rhi, ep.x, em.y));
 #pragma unroll
           for (int d = 0; d < ND; ++d) {
-            cre[d] = fmaf(bre[d], hr, fmaf(-bim[d], hi, cre[d]));
-            cim[d] = fmaf(bre[d], hi, fmaf(bim[d], hr, cim[d]));
+            if constexpr (std::is_same<BS, float>::value) {
+              wre[d] = fmaf(bre[d], hr, fmaf(-bim[d], hi, wre[d]));
+              wim[d] = fmaf(bre[d], hi, fmaf(bim[d], hr, wim[d]));
+            } else {
+              wre[d] += (BS)fmaf(bre[d], hr, -bim[d] * hi);
+              wim[d] += (BS)fmaf(bre[d], hi, bim[d] * hr);
+            }
           }
         } else {
           // one row: the bins accumulate b e(p-) and b e(p+)
-          smr = fmaf(bre[0], em.x, fmaf(-bim[0], em.y, smr));
-          smi = fmaf(bre[0], em.y, fmaf(bim[0], em.x, smi));
-          spr = fmaf(bre[0], ep.x, fmaf(-bim[0], ep.y, spr));
-          spi = fmaf(bre[0], ep.y, fmaf(bim[0], ep.x, spi));
+          if constexpr (std::is_same<BS, float>::value) {
+            smr = fmaf(bre[0], em.x, fmaf(-bim[0], em.y, smr));
+            smi = fmaf(bre[0], em.y, fmaf(bim[0], em.x, smi));
+            spr = fmaf(bre[0], ep.x, fmaf(-bim[0], ep.y, spr));
+            spi = fmaf(bre[0], ep.y, fmaf(bim[0], ep.x, spi));
+          } else {
+            smr += (BS)fmaf(bre[0], em.x, -bim[0] * em.y);
+            smi += (BS)fmaf(bre[0], em.y, bim[0] * em.x);
+            spr += (BS)fmaf(bre[0], ep.x, -bim[0] * ep.y);
+            spi += (BS)fmaf(bre[0], ep.y, bim[0] * ep.x);
+          }
         }
       };
       // The bins as segments of one series tier each (bounds wave-uniform, so no per-bin
@@ -558,14 +594,15 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       }
       if constexpr (ND == 1) {
         // one row: the bins accumulated b e(p-) and b e(p+); apply the phasors once
-        cre[0] = (eqr * smr - eqy * smi) - (fqr * spr - fqy * spi);
-        cim[0] = (eqr * smi + eqy * smr) - (fqr * spi + fqy * spr);
+        const float sr = (float)smr, si = (float)smi, qr = (float)spr, qi = (float)spi;
+        cre[0] = (eqr * sr - eqy * si) - (fqr * qr - fqy * qi);
+        cim[0] = (eqr * si + eqy * sr) - (fqr * qi + fqy * qr);
       } else {
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-          const R cr = cre[d];
-          cre[d] = eqr * cr - eqy * cim[d];
-          cim[d] = eqr * cim[d] + eqy * cr;
+          const float cr = (float)wre[d], ci = (float)wim[d];
+          cre[d] = eqr * cr - eqy * ci;
+          cim[d] = eqr * ci + eqy * cr;
         }
       }
       // Central bin of a lane with small drift and small delta: its weight F(delta, beta) from

@@ -80,7 +80,7 @@ EXPORTS = ["sft_load_data", "sft_free_data", "sft_default_opts", "sft_template_b
            "sft_plan_destroy", "sft_surrogate_param_count", "sft_surrogate_create", "sft_surrogate_free",
            "sft_surrogate_get_params", "sft_surrogate_targets", "sft_surrogate_loss_grad", "sft_surrogate_adam",
            "sft_surrogate_train", "sft_surrogate_infer", "sft_template_bank_scan_noalloc",
-           "sft_set_ephemeris"]
+           "sft_set_ephemeris", "sft_make_sfts", "sft_load_strain"]
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 _lib = None
@@ -105,6 +105,10 @@ def lib():
                                          ctypes.POINTER(Out), P]
     L.sft_template_bank_scan.restype = ctypes.c_int32
     L.sft_set_ephemeris.argtypes = [P, P, P]
+    L.sft_make_sfts.argtypes = [P, P, P, P, P, P]
+    L.sft_make_sfts.restype = ctypes.c_int32
+    L.sft_load_strain.argtypes = [P, P, P, P, P, P, P]
+    L.sft_load_strain.restype = ctypes.c_int32
     L.sft_set_ephemeris.restype = ctypes.c_int32
     L.sft_template_bank_scan_noalloc.argtypes = L.sft_template_bank_scan.argtypes
     L.sft_template_bank_scan_noalloc.restype = ctypes.c_int32
@@ -200,6 +204,33 @@ def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+class StrainDesc(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int32), ("n_samples", ctypes.c_int32), ("n_total", ctypes.c_int64),
+                ("dt", ctypes.c_double), ("t0", ctypes.c_double), ("k_lo", ctypes.c_int32),
+                ("n_bins", ctypes.c_int32), ("psd_w", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+
+
+def _strain_desc(x_t, n, dt, t0, k_lo, n_bins, psd_w, storage="f32"):
+    if not x_t.is_cuda or not x_t.is_contiguous() or x_t.dim() != 2 or str(x_t.dtype) != "torch.float64":
+        raise ValueError("strain must be a contiguous [n_det, n_total] float64 device tensor")
+    return StrainDesc(int(x_t.shape[0]), int(n), int(x_t.shape[1]), float(dt), float(t0), int(k_lo), int(n_bins),
+                      int(psd_w), STORAGE[storage], 0, 0)
+
+
+def make_sfts(x_t, n, dt, k_lo, n_bins, psd_w, t0=0.0, stream=None):
+    """SFT band bins, PSD estimates and keep flags of every segment of the strain series x_t
+    [n_det, n_total] (device FP64): tensors [n_det, n_seg, n_bins] complex128, float64, int32."""
+    import torch
+    d = _strain_desc(x_t, n, dt, t0, k_lo, n_bins, psd_w)
+    n_seg = d.n_total // int(n)
+    bins = torch.empty((d.n_det, n_seg, int(n_bins), 2), dtype=torch.float64, device=x_t.device)
+    psd = torch.empty((d.n_det, n_seg, int(n_bins)), dtype=torch.float64, device=x_t.device)
+    keep = torch.empty((d.n_det, n_seg), dtype=torch.int32, device=x_t.device)
+    _check(lib().sft_make_sfts(ctypes.byref(d), _tp(x_t), _tp(bins), _tp(psd), _tp(keep), _stream_ptr(stream)))
+    return torch.view_as_complex(bins), psd, keep
+
+
 class SFTData:
     """Device-resident whitened SFTs (owns an sft_data handle)."""
 
@@ -221,6 +252,26 @@ class SFTData:
         self.n_sft, self.n_bins, self.storage = n_sft, n_bins, storage
         self.t_sft, self.n_samples, self.k_lo = float(t_sft), int(n_samples), int(k_lo)
         self._keep = None
+
+    @classmethod
+    def from_strain(cls, x_t, n, dt, k_lo, n_bins, psd_w, t0=0.0, fplus=None, fcross=None, storage="f32",
+                    stream=None):
+        """SFTs made on the device from the strain series x_t [n_det, n_total] (device FP64),
+        whitened by their own PSD estimates; gaps (segments with a non-finite sample) dropped.
+        fplus, fcross: [n_det, n_seg] per segment, or None."""
+        d = _strain_desc(x_t, n, dt, t0, k_lo, n_bins, psd_w, storage)
+        fp = None if fplus is None else np.ascontiguousarray(fplus, dtype=np.float64).ravel()
+        fx = None if fcross is None else np.ascontiguousarray(fcross, dtype=np.float64).ravel()
+        h = ctypes.c_void_p()
+        nr = ctypes.c_int32()
+        _check(lib().sft_load_strain(ctypes.byref(d), _tp(x_t), _p(fp), _p(fx), _stream_ptr(stream),
+                                     ctypes.byref(h), ctypes.byref(nr)))
+        self = cls.__new__(cls)
+        self.handle = h
+        self.n_sft, self.n_bins, self.storage = int(nr.value), int(n_bins), storage
+        self.t_sft, self.n_samples, self.k_lo = float(dt) * int(n), int(n), int(k_lo)
+        self._keep = None
+        return self
 
     @classmethod
     def from_workload(cls, w, storage="f32", stream=None):

@@ -108,13 +108,15 @@ def test_shuffled_bank_mixes_staged_and_gathered_windows(ground_small, K, kernel
     assert e.max() < 1e-6
 
 
-@pytest.mark.parametrize("n_det,pad", [(3, 1.5e5), (1, 1.5e5), (3, 100.0), (1, 100.0)])
+@pytest.mark.parametrize("n_det,pad", [(3, 1.5e5), (1, 1.5e5), (3, 100.0), (1, 100.0), (3, 60.0), (1, 60.0)])
 def test_largest_window_full_band(n_det, pad):
     """K = 64 (the largest window), band from DC to Nyquist.  Far from merger (pad 1.5e5 s,
     k0 ~ 43-49, drift ~0.004 bins) the windows reach below DC and take the mirrored bins, and
     the central bin takes the small-drift series; near merger (pad 100 s, k0 ~ 250-725, drifts
     up to 75 bins, inside beta/2 + 8 <= K) the lanes of a wavefront spread by tens of bins, so
-    some groups fit the LDS stage and others fall back to gathers."""
+    some groups fit the LDS stage and others fall back to gathers.  Pad 60 s: the last SFTs
+    drift by up to ~134 bins, past beta/2 + 8 <= K, where the window no longer holds the track
+    (the result is still the same truncated sum on both sides, with its flags)."""
     with np.errstate(divide="ignore"):   # the coloured PSD is infinite at DC: that bin is masked
         w = synth.ground(seed=12, n_templates=300, n_slots=40, n_det=n_det, k_lo=0, k_hi=2049,
                          t_end_pad=pad, mc_lo=1.2, mc_hi=1.5)
