@@ -198,6 +198,7 @@ def parse():
     p.add_argument("--no-fstat", action="store_true", help="skip the F-statistic leg")
     p.add_argument("--no-doppler", action="store_true", help="skip the Doppler leg")
     p.add_argument("--no-strain", action="store_true", help="skip the SFT-creation leg")
+    p.add_argument("--no-r-study", action="store_true", help="skip the accuracy-study leg")
     p.add_argument("--strain-only", action="store_true", help="run only the SFT-creation leg")
     p.add_argument("--paper-shapes", action="store_true",
                    help="context only: time banks shaped like the paper's timing runs and exit")
@@ -336,6 +337,8 @@ def main():
         res["doppler"] = doppler_leg(args, w, opts, K)
     if not args.no_strain:
         res["strain"] = strain_leg(args)
+    if not args.no_r_study:
+        res["r_study"] = r_study_leg()
     if args.space_templates > 0:
         res["space"] = space_leg(args)
     if args.surrogate_templates > 0:
@@ -379,6 +382,22 @@ def fstat_leg(args, w, data, bank, opts, K):
             "twoF_median": float(np.median(f2)), "twoF_mean": float(np.mean(f2)),
             "degenerate_frac": float(np.mean((flags & sft.FLAG_FSTAT_DEGENERATE) != 0)),
             "max_err_2F_vs_oracle_40": err}
+
+
+def r_study_leg():
+    """The accuracy study of Sec. IV: r(delta, Delta k) for the BNS (3.5PN) and massive-BBH
+    (leading-order chirp) pilot sources, every step on the device (signal series, direct
+    integral, SFTs, SFT inner product)."""
+    from paper_2502_11823_amd import study
+    res = {}
+    for case in ("bns", "mbbh"):
+        r = study.r_study(case, dks=(4, 8, 12, 16, 20, 24, 32, 40, 48, 64),
+                          log=lambda m: print(m, file=sys.stderr, flush=True))
+        res[case] = {"waveform": r["waveform"], "duration_h": r["duration_h"], "n0": r["n0"],
+                     "fddot_max": r["fddot_max"], "config": {str(k): v for k, v in r["config"].items()},
+                     "r": {str(k): {str(dk): v for dk, v in row.items()} for k, row in r["r"].items()},
+                     "seconds": r["seconds"]}
+    return res
 
 
 def strain_leg(args):

@@ -120,7 +120,9 @@ void sft_free_data(sft_data* data);
  * unit exponentials) and scaled by 2/T (E|x~|^2 = T S / 2 for stationary Gaussian noise).
  * Each detector's series is cut into consecutive segments of n samples, segment a covering
  * samples [a n, (a+1) n) and starting at t0 + a n dt; a segment holding a non-finite sample is
- * a data gap (missing SFT).
+ * a data gap (missing SFT).  n a power of two: an FFT per segment; other even n (the SFT
+ * lengths of Sec. IV, e.g. 106 s at 40 Hz) with a known white PSD: the band bins by their
+ * defining sum.
  */
 typedef struct {
   int32_t n_det;        /* detector series */
@@ -132,8 +134,8 @@ typedef struct {
   int32_t n_bins;       /* stored bins k_lo .. k_lo + n_bins - 1, all <= n/2 */
   int32_t psd_w;        /* running-median half width w; 2w + 1 <= n/2 + 1 */
   int32_t storage;      /* SFT_STORE_* of the handle made by sft_load_strain */
-  int32_t reserved;     /* must be 0 */
-  int32_t reserved2;    /* must be 0 */
+  double s_white;       /* > 0: a known white one-sided PSD, used for every bin (no estimate, psd_w
+                           ignored); 0: the running-median estimate (needs n a power of two) */
 } sft_strain_desc;
 
 /*
@@ -144,7 +146,8 @@ typedef struct {
  *   psd  : DEVICE out [n_det][n_seg][n_bins] the estimated one-sided PSD.
  *   keep : DEVICE out [n_det][n_seg] 1, or 0 for a gap (whose bins and PSD are written as 0).
  * Errors: SFT_E_INVALID (null, bad descriptor, band or block outside [0, n/2]),
- * SFT_E_UNSUPPORTED (n not a power of two in [16, 16384]), SFT_E_RANGE, SFT_E_DEVICE.
+ * SFT_E_UNSUPPORTED (n odd or outside [16, 16384], or not a power of two without s_white),
+ * SFT_E_RANGE, SFT_E_DEVICE.
  */
 sft_status sft_make_sfts(const sft_strain_desc* desc, const double* x, double* bins, double* psd, int32_t* keep,
                          void* hip_stream);
@@ -160,6 +163,31 @@ sft_status sft_make_sfts(const sft_strain_desc* desc, const double* x, double* b
  */
 sft_status sft_load_strain(const sft_strain_desc* desc, const double* x, const double* fplus, const double* fcross,
                            void* hip_stream, sft_data** out, int32_t* n_rows);
+
+/*
+ * Time-domain companions, for accuracy studies of the SFT inner product (Sec. IV.A: the
+ * relative error r = 1 - sqrt(([d,h]) / <d,h>) against the direct integral).
+ *
+ * sft_waveform_series -- the strain of one template at the samples t_j = t0 + j dt, j < n:
+ *   h_j = A(t_j) [F+_j A+ cos phi(t_j) + Fx_j Ax sin phi(t_j)]   (the projector of Sec. II.A),
+ * with the waveform of the scans (SFT_WF_NEWTON or SFT_WF_PN35, mass ratio q for the latter),
+ * zero where tau = t_c - t_j <= 0.  fplus, fcross: DEVICE [n] per-sample antenna patterns, or
+ * NULL (1 and 0).  h: DEVICE out [n].  quantities: DEVICE out [n][5] (A, phi, f, fdot, fddot at
+ * each sample) or NULL.  Asynchronous on hip_stream.  Errors: SFT_E_INVALID, SFT_E_UNSUPPORTED
+ * (other waveforms), SFT_E_RANGE, SFT_E_DEVICE.
+ */
+sft_status sft_waveform_series(int32_t waveform, double mc, double q, double t_c, double phi_c, double tsun,
+                               double t0, double dt, int64_t n, const double* fplus, const double* fcross,
+                               double a_plus, double a_cross, double* h, double* quantities, void* hip_stream);
+
+/*
+ * sft_td_product -- <x, y> = 4 Re int x~* y~ / S df = (2 / S) dt sum_j x_j y_j for a white
+ * one-sided PSD S (Eqs. fd_product, td_product, whitened_data), x, y DEVICE [n].  FP64,
+ * compensated, in a fixed order (bitwise reproducible).  Synchronous on hip_stream; the result
+ * goes to the host *out.  Errors: SFT_E_INVALID, SFT_E_DEVICE.
+ */
+sft_status sft_td_product(const double* x, const double* y, int64_t n, double dt, double psd, void* hip_stream,
+                          double* out);
 
 /*
  * sft_set_ephemeris -- detector motion for the Doppler form of the scan (Sec. III.B: the

@@ -60,8 +60,8 @@ __device__ inline bool pair_less(double va, int ia, double vb, int ib)
 
 __global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
     const double* __restrict__ x, int64_t n_total, int32_t n_seg, int32_t logM, double dt, int32_t w, double psd_scale,
-    int32_t k_lo, int32_t n_bins, int32_t staged, const double2* __restrict__ tw, const double2* __restrict__ rtw,
-    double* __restrict__ bins, double* __restrict__ psd, int32_t* __restrict__ keep)
+    int32_t k_lo, int32_t n_bins, int32_t staged, double s_white, const double2* __restrict__ tw,
+    const double2* __restrict__ rtw, double* __restrict__ bins, double* __restrict__ psd, int32_t* __restrict__ keep)
 {
   // LDS: buf[M + 1] complex; with staged = 1 a region of M + 1 doubles after it, holding the
   // twiddles during the transform and the periodogram afterwards
@@ -153,7 +153,10 @@ __global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
   }
   auto P = [&](int j) { return staged ? U[j] : pw(buf, j); };
   const int N = 2 * w + 1;
-  if (w <= kMaxSortW) {
+  if (s_white > 0.0) {
+    // a known white PSD: no estimate
+    for (int i = tid; i < n_bins; i += blockDim.x) po[i] = s_white;
+  } else if (w <= kMaxSortW) {
     const int lane = tid & 63, wv = tid >> 6;
     double* sv = s_val[wv];
     int* si = s_idx[wv];
@@ -239,6 +242,70 @@ __global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
   if (tid == 0) keep[row] = 1;
 }
 
+// Segments whose length n is not a power of two: the band bins by their defining sum
+// X[k] = sum_j x_j e^{-2 pi i j k / n} (Eq. d_SFT), one bin per thread, the segment in LDS (read
+// as a broadcast), the twiddle advanced by the rotation e^{-2 pi i k / n} and re-anchored from
+// the exact table W[m] = e^{-2 pi i m / n} every kAnchor samples (rounding drift <= kAnchor eps).
+// The PSD is the given white level (no estimate).
+constexpr int kAnchor = 256;
+
+__global__ __launch_bounds__(kStrainBlock) void strain_dft_kernel(
+    const double* __restrict__ x, int64_t n_total, int32_t n_seg, int32_t n, double dt, double s_white,
+    int32_t k_lo, int32_t n_bins, const double2* __restrict__ W, double* __restrict__ bins, double* __restrict__ psd,
+    int32_t* __restrict__ keep)
+{
+  extern __shared__ double xl[];   // the segment, n values
+  __shared__ int s_bad;
+  const int row = blockIdx.x;
+  const int det = row / n_seg, seg = row - det * n_seg;
+  const double* xs = x + (int64_t)det * n_total + (int64_t)seg * n;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  bool bad = false;
+  for (int j = tid; j < n; j += blockDim.x) {
+    const double v = xs[j];
+    bad = bad || !isfinite(v);
+    xl[j] = v;
+  }
+  if (bad) s_bad = 1;
+  __syncthreads();
+  double* bo = bins + (int64_t)row * 2 * n_bins;
+  double* po = psd + (int64_t)row * n_bins;
+  if (s_bad) {
+    for (int i = tid; i < n_bins; i += blockDim.x) {
+      bo[2 * i] = 0.0;
+      bo[2 * i + 1] = 0.0;
+      po[i] = 0.0;
+    }
+    if (tid == 0) keep[row] = 0;
+    return;
+  }
+  for (int i = tid; i < n_bins; i += blockDim.x) {
+    const int k = k_lo + i;
+    const double2 r = W[k % n];
+    const int step = (int)(((int64_t)kAnchor * k) % n);
+    double re = 0.0, im = 0.0;
+    int idx = 0;   // (j0 k) mod n
+    for (int j0 = 0; j0 < n; j0 += kAnchor) {
+      double2 wv = W[idx];
+      const int j1 = j0 + kAnchor < n ? j0 + kAnchor : n;
+      for (int j = j0; j < j1; ++j) {
+        const double xj = xl[j];
+        re = fma(xj, wv.x, re);
+        im = fma(xj, wv.y, im);
+        wv = cmul(wv, r);
+      }
+      idx += step;
+      idx = idx >= n ? idx - n : idx;
+    }
+    bo[2 * i] = dt * re;
+    bo[2 * i + 1] = dt * im;
+    po[i] = s_white;
+  }
+  if (tid == 0) keep[row] = 1;
+}
+
 }  // namespace
 
 static sft_status strain_fail(sft_status st, const char* msg) { return sft_set_error(st, msg); }
@@ -248,22 +315,49 @@ extern "C" sft_status sft_make_sfts(const sft_strain_desc* d, const double* x, d
 {
   if (!d || !x || !bins || !psd || !keep) return strain_fail(SFT_E_INVALID, "sft_make_sfts: null argument");
   const int n = d->n_samples;
-  if (n < 16 || n > 16384 || (n & (n - 1)))
-    return strain_fail(SFT_E_UNSUPPORTED, "sft_make_sfts: n_samples must be a power of two in [16, 16384]");
-  if (d->n_det < 1 || d->n_total < n || !(d->dt > 0.0) || d->reserved != 0 || d->reserved2 != 0)
+  const bool pow2 = (n & (n - 1)) == 0;
+  if (n < 16 || n > 16384 || (n & 1))
+    return strain_fail(SFT_E_UNSUPPORTED, "sft_make_sfts: n_samples must be even and in [16, 16384]");
+  if (!pow2 && !(d->s_white > 0.0))
+    return strain_fail(SFT_E_UNSUPPORTED, "sft_make_sfts: the PSD estimate needs n a power of two (else give s_white)");
+  if (d->n_det < 1 || d->n_total < n || !(d->dt > 0.0) || !(d->s_white >= 0.0))
     return strain_fail(SFT_E_INVALID, "sft_make_sfts: bad descriptor");
   const int M = n / 2;
   if (d->k_lo < 0 || d->n_bins < 1 || d->k_lo + d->n_bins - 1 > M)
     return strain_fail(SFT_E_INVALID, "sft_make_sfts: band outside [0, n/2]");
-  if (d->psd_w < 0 || 2 * d->psd_w + 1 > M + 1)
+  if (!(d->s_white > 0.0) && (d->psd_w < 0 || 2 * d->psd_w + 1 > M + 1))
     return strain_fail(SFT_E_INVALID, "sft_make_sfts: running-median block wider than the spectrum");
   const int64_t n_seg = d->n_total / n;
   if (n_seg * d->n_det > INT32_MAX) return strain_fail(SFT_E_RANGE, "sft_make_sfts: too many segments");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  if (!pow2) {
+    std::vector<double2> W(n);
+    for (int m = 0; m < n; ++m) {
+      const long double a = -2.0L * pi * (long double)m / (long double)n;
+      W[m] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    double2* d_W = nullptr;
+    hipError_t e = hipMallocAsync((void**)&d_W, n * sizeof(double2), st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_W, W.data(), n * sizeof(double2), hipMemcpyHostToDevice, st);
+    const size_t lds = (size_t)n * sizeof(double);
+    if (e == hipSuccess && lds > 65536)
+      e = hipFuncSetAttribute((const void*)strain_dft_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess && n_seg > 0) {
+      hipLaunchKernelGGL(strain_dft_kernel, dim3((unsigned)(n_seg * d->n_det)), dim3(kStrainBlock), lds, st, x,
+                         d->n_total, (int32_t)n_seg, n, d->dt, d->s_white, d->k_lo, d->n_bins, d_W, bins, psd, keep);
+      e = hipGetLastError();
+    }
+    hipError_t e2 = hipStreamSynchronize(st);   // W is read by the upload
+    if (d_W) (void)hipFreeAsync(d_W, st);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return strain_fail(SFT_E_DEVICE, hipGetErrorString(e));
+    return SFT_OK;
+  }
   int logM = 0;
   while ((1 << logM) < M) ++logM;
   // twiddles in long double, rounded once
   std::vector<double2> tw(M / 2 > 0 ? M / 2 : 1), rtw(M / 2 + 1);
-  const long double pi = 3.141592653589793238462643383279502884L;
   for (int j = 0; j < M / 2; ++j) {
     const long double a = -2.0L * pi * (long double)j / (long double)M;
     tw[j] = make_double2((double)cosl(a), (double)sinl(a));
@@ -276,7 +370,6 @@ extern "C" sft_status sft_make_sfts(const sft_strain_desc* d, const double* x, d
   for (int i = 0; i <= d->psd_w; ++i) B += 1.0 / (double)(2 * d->psd_w + 1 - i);
   const double T = d->dt * n;
   const double psd_scale = 2.0 / (T * B);
-  hipStream_t st = (hipStream_t)hip_stream;
   double2 *d_tw = nullptr, *d_rtw = nullptr;
   hipError_t e = hipMallocAsync((void**)&d_tw, tw.size() * sizeof(double2), st);
   if (e == hipSuccess) e = hipMallocAsync((void**)&d_rtw, rtw.size() * sizeof(double2), st);
@@ -289,8 +382,8 @@ extern "C" sft_status sft_make_sfts(const sft_strain_desc* d, const double* x, d
     e = hipFuncSetAttribute((const void*)strain_sft_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e == hipSuccess && n_seg > 0) {
     hipLaunchKernelGGL(strain_sft_kernel, dim3((unsigned)(n_seg * d->n_det)), dim3(kStrainBlock), lds, st, x,
-                       d->n_total, (int32_t)n_seg, logM, d->dt, d->psd_w, psd_scale, d->k_lo, d->n_bins, staged, d_tw,
-                       d_rtw, bins, psd, keep);
+                       d->n_total, (int32_t)n_seg, logM, d->dt, d->psd_w, psd_scale, d->k_lo, d->n_bins, staged,
+                       d->s_white, d_tw, d_rtw, bins, psd, keep);
     e = hipGetLastError();
   }
   // the twiddle uploads read host vectors: finish before they go out of scope

@@ -80,7 +80,7 @@ EXPORTS = ["sft_load_data", "sft_free_data", "sft_default_opts", "sft_template_b
            "sft_plan_destroy", "sft_surrogate_param_count", "sft_surrogate_create", "sft_surrogate_free",
            "sft_surrogate_get_params", "sft_surrogate_targets", "sft_surrogate_loss_grad", "sft_surrogate_adam",
            "sft_surrogate_train", "sft_surrogate_infer", "sft_template_bank_scan_noalloc",
-           "sft_set_ephemeris", "sft_make_sfts", "sft_load_strain"]
+           "sft_set_ephemeris", "sft_make_sfts", "sft_load_strain", "sft_waveform_series", "sft_td_product"]
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 _lib = None
@@ -109,6 +109,11 @@ def lib():
     L.sft_make_sfts.restype = ctypes.c_int32
     L.sft_load_strain.argtypes = [P, P, P, P, P, P, P]
     L.sft_load_strain.restype = ctypes.c_int32
+    Dd = ctypes.c_double
+    L.sft_waveform_series.argtypes = [ctypes.c_int32, Dd, Dd, Dd, Dd, Dd, Dd, Dd, ctypes.c_int64, P, P, Dd, Dd, P, P, P]
+    L.sft_waveform_series.restype = ctypes.c_int32
+    L.sft_td_product.argtypes = [P, P, ctypes.c_int64, Dd, Dd, P, P]
+    L.sft_td_product.restype = ctypes.c_int32
     L.sft_set_ephemeris.restype = ctypes.c_int32
     L.sft_template_bank_scan_noalloc.argtypes = L.sft_template_bank_scan.argtypes
     L.sft_template_bank_scan_noalloc.restype = ctypes.c_int32
@@ -208,27 +213,53 @@ class StrainDesc(ctypes.Structure):
     _fields_ = [("n_det", ctypes.c_int32), ("n_samples", ctypes.c_int32), ("n_total", ctypes.c_int64),
                 ("dt", ctypes.c_double), ("t0", ctypes.c_double), ("k_lo", ctypes.c_int32),
                 ("n_bins", ctypes.c_int32), ("psd_w", ctypes.c_int32), ("storage", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("s_white", ctypes.c_double)]
 
 
-def _strain_desc(x_t, n, dt, t0, k_lo, n_bins, psd_w, storage="f32"):
+def _strain_desc(x_t, n, dt, t0, k_lo, n_bins, psd_w, storage="f32", s_white=0.0):
     if not x_t.is_cuda or not x_t.is_contiguous() or x_t.dim() != 2 or str(x_t.dtype) != "torch.float64":
         raise ValueError("strain must be a contiguous [n_det, n_total] float64 device tensor")
     return StrainDesc(int(x_t.shape[0]), int(n), int(x_t.shape[1]), float(dt), float(t0), int(k_lo), int(n_bins),
-                      int(psd_w), STORAGE[storage], 0, 0)
+                      int(psd_w), STORAGE[storage], float(s_white))
 
 
-def make_sfts(x_t, n, dt, k_lo, n_bins, psd_w, t0=0.0, stream=None):
+def make_sfts(x_t, n, dt, k_lo, n_bins, psd_w, t0=0.0, stream=None, s_white=0.0):
     """SFT band bins, PSD estimates and keep flags of every segment of the strain series x_t
     [n_det, n_total] (device FP64): tensors [n_det, n_seg, n_bins] complex128, float64, int32."""
     import torch
-    d = _strain_desc(x_t, n, dt, t0, k_lo, n_bins, psd_w)
+    d = _strain_desc(x_t, n, dt, t0, k_lo, n_bins, psd_w, s_white=s_white)
     n_seg = d.n_total // int(n)
     bins = torch.empty((d.n_det, n_seg, int(n_bins), 2), dtype=torch.float64, device=x_t.device)
     psd = torch.empty((d.n_det, n_seg, int(n_bins)), dtype=torch.float64, device=x_t.device)
     keep = torch.empty((d.n_det, n_seg), dtype=torch.int32, device=x_t.device)
     _check(lib().sft_make_sfts(ctypes.byref(d), _tp(x_t), _tp(bins), _tp(psd), _tp(keep), _stream_ptr(stream)))
     return torch.view_as_complex(bins), psd, keep
+
+
+def waveform_series(mc, t_c, t0, dt, n, waveform="newton", q=1.0, phi_c=0.0, fplus=None, fcross=None,
+                    a_plus=1.0, a_cross=0.0, quantities=False, tsun=T_SUN, device="cuda", stream=None):
+    """Strain h [n] of one template at t_j = t0 + j dt on the device (and the waveform
+    quantities [n, 5] A, phi, f, fdot, fddot when asked)."""
+    import torch
+    h = torch.empty(int(n), dtype=torch.float64, device=device)
+    qv = torch.empty((int(n), 5), dtype=torch.float64, device=device) if quantities else None
+    for a in (fplus, fcross):
+        if a is not None and (not a.is_cuda or not a.is_contiguous() or a.numel() != int(n)):
+            raise ValueError("antenna patterns must be contiguous device tensors of n samples")
+    _check(lib().sft_waveform_series(WAVEFORM[waveform], float(mc), float(q), float(t_c), float(phi_c), float(tsun),
+                                     float(t0), float(dt), int(n), _tp(fplus), _tp(fcross), float(a_plus),
+                                     float(a_cross), _tp(h), _tp(qv), _stream_ptr(stream)))
+    return (h, qv) if quantities else h
+
+
+def td_product(x_t, y_t, dt, psd, stream=None):
+    """(2 / S) dt sum_j x_j y_j on the device (white one-sided PSD S)."""
+    if x_t.numel() != y_t.numel() or not x_t.is_contiguous() or not y_t.is_contiguous():
+        raise ValueError("x and y must be contiguous and of one length")
+    out = ctypes.c_double()
+    _check(lib().sft_td_product(_tp(x_t), _tp(y_t), int(x_t.numel()), float(dt), float(psd), _stream_ptr(stream),
+                                ctypes.byref(out)))
+    return out.value
 
 
 class SFTData:
@@ -255,11 +286,11 @@ class SFTData:
 
     @classmethod
     def from_strain(cls, x_t, n, dt, k_lo, n_bins, psd_w, t0=0.0, fplus=None, fcross=None, storage="f32",
-                    stream=None):
+                    stream=None, s_white=0.0):
         """SFTs made on the device from the strain series x_t [n_det, n_total] (device FP64),
         whitened by their own PSD estimates; gaps (segments with a non-finite sample) dropped.
         fplus, fcross: [n_det, n_seg] per segment, or None."""
-        d = _strain_desc(x_t, n, dt, t0, k_lo, n_bins, psd_w, storage)
+        d = _strain_desc(x_t, n, dt, t0, k_lo, n_bins, psd_w, storage, s_white)
         fp = None if fplus is None else np.ascontiguousarray(fplus, dtype=np.float64).ravel()
         fx = None if fcross is None else np.ascontiguousarray(fcross, dtype=np.float64).ravel()
         h = ctypes.c_void_p()

@@ -71,3 +71,12 @@ def test_psd_estimate_is_unbiased_on_white_noise(orc):
     assert abs(est.mean() - 1.0) < 4 * err
     wrong = est * orc.median_bias(w) / math.log(2)
     assert abs(wrong.mean() - 1.0) > 4 * err
+
+
+def test_study_tsft_is_eq_max_tsft(orc):
+    """The study's T_SFT (Eq. max_tsft, floored to whole seconds) is the oracle's, and reproduces
+    Table 1 for max fddot = 5e-6 Hz/s^2 (pinned against the paper by P9)."""
+    from paper_2502_11823_amd import study
+    for delta, want in ((3.0, 106), (2.0, 92), (1.0, 73)):
+        assert study.tsft(delta, 5e-6) == want == math.floor(orc.tsft_max(delta, 5e-6))
+        assert abs(study.tsft(delta, 5e-6, floor_seconds=False) - orc.tsft_max(delta, 5e-6)) < 1e-12
