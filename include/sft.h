@@ -204,11 +204,20 @@ sft_status sft_td_product(const double* x, const double* y, int64_t n, double dt
  */
 sft_status sft_set_ephemeris(sft_data* data, const double* eph, void* hip_stream);
 
+/* Reference time of each SFT's Taylor expansion (Sec. III.B): the midpoint (default) or the
+ * start, as the paper writes it.  With SFT_REF_START the waveform is evaluated at t_a, the
+ * window is centred on the start frequency, k0 = floor(f_a T + 1/2), the kernel is
+ * int_0^1 exp(i (2 pi x s + pi beta s^2)) ds on the data without the (-1)^k of the midpoint
+ * form, the norm uses A_a and S_a(f_a) at the start, and the validity flag f_ddot T^3 / 2. */
+enum { SFT_REF_MID = 0, SFT_REF_START = 1 };
+
 typedef struct {
   int32_t K;            /* window half-width: bins k0-K .. k0+K, 0 <= K <= SFT_K_MAX (Sec. III.C truncation) */
   int32_t kernel;       /* SFT_KERNEL_* */
   int32_t precision;    /* SFT_PREC_*: FP64 needs SFT_STORE_F64 data, the FP32 modes need F32 or BF16 data */
   int32_t waveform;     /* SFT_WF_* */
+  int32_t t_ref;        /* SFT_REF_MID or SFT_REF_START (the start needs the Newtonian or 3.5PN waveform
+                           and no ephemeris) */
   double beta_switch;   /* AUTO kernel: Dirichlet when |fdot T^2| <= beta_switch (bins) */
   double a_plus;        /* A+ of the projector, used for rho */
   double a_cross;       /* Ax of the projector, used for rho */
@@ -217,7 +226,7 @@ typedef struct {
   const struct sft_surrogate* surrogate;  /* network of SFT_WF_SURROGATE; NULL otherwise */
 } sft_opts;
 
-/* Fill *opts with K = 8, AUTO kernel, FP32_KAHAN, Newtonian waveform,
+/* Fill *opts with K = 8, AUTO kernel, FP32_KAHAN, Newtonian waveform, midpoint reference,
  * beta_switch = 1e-7, A+ = 1, Ax = 0, tsun = 4.925490947641267e-6 s, delta_max = 0,
  * surrogate = NULL. */
 void sft_default_opts(sft_opts* opts);

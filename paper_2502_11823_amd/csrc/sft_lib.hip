@@ -489,6 +489,7 @@ extern "C" void sft_default_opts(sft_opts* o)
   o->kernel = SFT_KERNEL_AUTO;
   o->precision = SFT_PREC_FP32_KAHAN;
   o->waveform = SFT_WF_NEWTON;
+  o->t_ref = SFT_REF_MID;
   o->beta_switch = 1e-7;
   o->a_plus = 1.0;
   o->a_cross = 0.0;
@@ -629,6 +630,10 @@ static sft_status validate_scan(const sft_data* d, const sft_opts* o)
       return fail(SFT_E_INVALID, "scan: the surrogate lives on device %d, not on the current device", o->surrogate->device);
   }
   if (!(o->tsun > 0.0)) return fail(SFT_E_INVALID, "scan: tsun must be positive");
+  if (o->t_ref != SFT_REF_MID && o->t_ref != SFT_REF_START)
+    return fail(SFT_E_INVALID, "scan: unknown reference time %d", o->t_ref);
+  if (o->t_ref == SFT_REF_START && o->waveform == SFT_WF_SURROGATE)
+    return fail(SFT_E_UNSUPPORTED, "scan: the surrogate waveform is evaluated at the SFT midpoints only");
   if (o->precision == SFT_PREC_FP64) {
     if (d->storage != SFT_STORE_F64) return fail(SFT_E_UNSUPPORTED, "scan: FP64 precision needs F64 storage");
     if (o->kernel != SFT_KERNEL_DIRICHLET) return fail(SFT_E_UNSUPPORTED, "scan: FP64 precision supports the Dirichlet kernel only");
@@ -658,6 +663,8 @@ static sft_status validate_doppler(const sft_data* d, const sft_opts* o, const s
 {
   if (!bank || !bank->sky) return SFT_OK;
   if (!d->g_eph) return fail(SFT_E_INVALID, "scan: bank.sky given but the data have no ephemeris (sft_set_ephemeris)");
+  if (o->t_ref != SFT_REF_MID)
+    return fail(SFT_E_UNSUPPORTED, "scan: the Doppler form uses the midpoint reference (its ephemeris is at the midpoints)");
   if (o->waveform != SFT_WF_NEWTON)
     return fail(SFT_E_UNSUPPORTED, "scan: the Doppler form is computed with the Newtonian waveform only");
   if (!((o->precision == SFT_PREC_FP32_KAHAN && d->storage == SFT_STORE_F32) || o->precision == SFT_PREC_FP64))
@@ -723,6 +730,7 @@ static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t 
   a.beta_switch = o->kernel == SFT_KERNEL_AUTO ? o->beta_switch : 0.0;
   a.tsun = o->tsun;
   a.delta_max = o->delta_max;
+  a.t_ref_start = o->t_ref == SFT_REF_START ? 1 : 0;
   a.mc = bank->mc;
   a.q = bank->q;
   a.t_c = bank->t_c;

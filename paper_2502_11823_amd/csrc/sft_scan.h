@@ -286,7 +286,9 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       dl1 = fma(e[3], nx, fma(e[4], ny, e[5] * nz));
       dl2 = fma(e[6], nx, fma(e[7], ny, e[8] * nz));
     }
-    const double tau = DP != 0 ? tc - (tmid + dl) : tc - tmid;
+    // the reference time of the Taylor expansion: the SFT midpoint, or its start
+    const double tref = a.t_ref_start ? tmid - 0.5 * T : tmid;
+    const double tau = DP != 0 ? tc - (tref + dl) : tc - tref;
     if (!(tau > 0.0)) {
       fl |= kFlagTau;
       continue;
@@ -314,6 +316,19 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       ch.beta = fma(ch.beta, g1 * g1, ks * dl2 * T);
       ch.dres *= g1 * g1 * g1;
     }
+    // Start reference: the kernel over [0, 1] is the midpoint kernel at x + beta/2 times
+    // exp(i (pi x + pi beta / 4)), with x = kappa - k; the (-1)^k of the midpoint form absorbs
+    // exp(i pi (kappa - k)) up to exp(i pi kappa).  So the start form is the midpoint form with
+    // the kernel argument kappa + beta/2 and the phase phi + pi kappa + pi beta / 4, the window
+    // still centred on the start frequency; the validity lever is T instead of T / 2.
+    // The drift in the shift is the kernel's: 0 where the Dirichlet limit is used.
+    double kwin = ch.kappa;
+    if (a.t_ref_start) {
+      const double bk = (KERN == KERN_FRESNEL && !(fabs(ch.beta) <= a.beta_switch)) ? ch.beta : 0.0;
+      kwin = fma(0.5, bk, ch.kappa);
+      ch.phase += kPi * fma(0.25, bk, ch.kappa);
+      ch.dres *= 4.0;
+    }
     if (a.delta_max > 0.0 && ch.dres > a.delta_max) fl |= kFlagTaylor;
     if (!(ch.kappa < 1.0e9)) {
       // frequency far above any stored band: no window bin and no norm bin exists
@@ -321,7 +336,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       continue;
     }
     const double kr = floor(ch.kappa + 0.5);
-    const double delta = ch.kappa - kr;
+    const double delta = kwin - kr;
     const int k0 = (int)kr;
     if (k0 < 0 || k0 > a.k_nyq) {
       // frequency below DC or above Nyquist: no representation in the data (its norm bins

@@ -20,6 +20,7 @@ struct ScanArgs {
   const double* fx;
   int32_t n_groups, n_ext, k_ext_lo, n_bins, k_lo, K;
   int32_t k_nyq;            // n / 2: window centres outside [0, k_nyq] have no data
+  int32_t t_ref_start;      // 1: Taylor expansion at the SFT start (SFT_REF_START), 0: midpoint
   double T, beta_switch, tsun, delta_max;
   const double* mc;
   const double* q;

@@ -41,7 +41,8 @@ class DataDesc(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("waveform", ctypes.c_int32), ("beta_switch", ctypes.c_double), ("a_plus", ctypes.c_double),
+                ("waveform", ctypes.c_int32), ("t_ref", ctypes.c_int32), ("beta_switch", ctypes.c_double),
+                ("a_plus", ctypes.c_double),
                 ("a_cross", ctypes.c_double), ("tsun", ctypes.c_double), ("delta_max", ctypes.c_double),
                 ("surrogate", ctypes.c_void_p)]
 
@@ -182,14 +183,18 @@ def _stream_ptr(stream) -> Optional[int]:
     return getattr(stream, "cuda_stream", stream)
 
 
+T_REF = {"mid": 0, "start": 1}
+
+
 def make_opts(K=8, kernel="auto", precision="fp32_kahan", waveform="newton", beta_switch=1e-7,
-              a_plus=1.0, a_cross=0.0, tsun=T_SUN, delta_max=0.0, surrogate=None) -> Opts:
+              a_plus=1.0, a_cross=0.0, tsun=T_SUN, delta_max=0.0, surrogate=None, t_ref="mid") -> Opts:
     o = Opts()
     lib().sft_default_opts(ctypes.byref(o))
     o.K = int(K)
     o.kernel = KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.waveform = WAVEFORM[waveform] if isinstance(waveform, str) else int(waveform)
+    o.t_ref = T_REF[t_ref] if isinstance(t_ref, str) else int(t_ref)
     o.beta_switch = float(beta_switch)
     o.a_plus = float(a_plus)
     o.a_cross = float(a_cross)

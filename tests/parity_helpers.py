@@ -32,6 +32,7 @@ def orc_scan(w, bank, x_bins=None, psd=None, **kw):
     kw.pop("surrogate", None)
     kw["wf"] = {"newton": oracle.WF_NEWTON, "pn35": oracle.WF_PN35,
                 "surrogate": oracle.WF_SURROGATE}[kw.pop("waveform", "newton")]
+    kw["t_ref"] = {"mid": oracle.REF_MID, "start": oracle.REF_START}[kw.pop("t_ref", "mid")]
     return oracle.scan(od, bank["mc"], bank["t_c"], phi_c=bank["phi_c"], q=bank.get("q"),
                        a_first=bank["a_first"], a_last=bank["a_last"], **kw)
 

@@ -30,11 +30,11 @@ def test_version_and_defaults():
     assert b"gfx950" in sft.lib().sft_version()
     o = sft.Opts()
     sft.lib().sft_default_opts(ctypes.byref(o))
-    assert (o.K, o.kernel, o.precision, o.waveform) == (8, 2, 1, 0)
+    assert (o.K, o.kernel, o.precision, o.waveform, o.t_ref) == (8, 2, 1, 0, 0)
     assert o.beta_switch == 1e-7 and o.a_plus == 1.0 and o.a_cross == 0.0
     assert abs(o.tsun - 4.925490947641267e-6) < 1e-20
     assert o.surrogate is None
-    assert ctypes.sizeof(sft.DataDesc) == 32 and ctypes.sizeof(sft.Opts) == 64
+    assert ctypes.sizeof(sft.DataDesc) == 32 and ctypes.sizeof(sft.Opts) == 72
     assert ctypes.sizeof(sft.Out) == 72 and ctypes.sizeof(sft.SurrogateDesc) == 88
 
 

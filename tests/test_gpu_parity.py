@@ -408,3 +408,74 @@ def test_paper_shaped_banks_sampled(name):
     idx = np.sort(synth.rng(21).choice(w.n_templates, 24, replace=False))
     o = orc_scan(w, w.subset(idx), **kw)
     compare(g, o, idx=idx, label="paper-shaped " + name)
+
+
+# ----------------------------------------------------------------------------- remaining instantiations
+def test_fp32_naive_fresnel_ground(ground_small):
+    """Plain FP32 sums with the Fresnel kernels (groups of three rows, K = 8 compile-time window)."""
+    data = sft.SFTData.from_workload(ground_small, storage="f32")
+    kw = dict(K=8, kernel="auto", precision="fp32_naive", a_plus=1.0, a_cross=1.0)
+    compare(gpu_scan(data, ground_small.bank, **kw), orc_scan(ground_small, ground_small.bank, **kw),
+            label="ground-small fp32 naive")
+
+
+def test_bf16_fresnel_multirow_is_reported_not_exact(ground_small):
+    """BF16 data bins with the Fresnel kernels and three rows per group: the 8-bit mantissa of
+    the data (relative 4e-3) bounds the error, which is measured and reported; flags are exact."""
+    data = sft.SFTData.from_workload(ground_small, storage="bf16")
+    kw = dict(K=8, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0)
+    g = gpu_scan(data, ground_small.bank, **kw)
+    o = orc_scan(ground_small, ground_small.bank, **kw)
+    e = np.abs(g["zp"] - o["zp"]) / np.maximum(np.abs(o["zp"]), np.sqrt(o["hhp"]))
+    print("ground-small bf16 fresnel: max e = %.3e, median %.3e" % (e.max(), np.median(e)))
+    assert 1e-5 < e.max() < 3e-2
+    assert np.array_equal(g["flags"], o["flags"])
+    # the norm does not read the data bins: FP32 accuracy
+    assert np.max(np.abs(g["hhp"] - o["hhp"]) / o["hhp"]) < 1e-6
+
+
+def test_newton_four_detectors_per_group():
+    """Four detectors sharing every start time: the width-4 group kernel (weights shared by four
+    rows) with gaps, K = 8 and a run-time window."""
+    w = synth.ground(seed=21, n_templates=400, n_slots=64, n_det=4, k_lo=40, k_hi=470, t_end_pad=300.0)
+    data = sft.SFTData.from_workload(w, storage="f32")
+    for K in (8, 6):
+        kw = dict(K=K, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0)
+        compare(gpu_scan(data, w.bank, **kw), orc_scan(w, w.bank, **kw), label="4 detectors K=%d" % K)
+
+
+@pytest.mark.parametrize("K", [8, 32])
+def test_pn35_fp32_one_row_fresnel(K):
+    """The 3.5PN waveform in FP32 sums on one detector (one row per group), Fresnel kernels."""
+    w = synth.ground(seed=22, n_templates=300, n_slots=96, n_det=1, k_lo=20, k_hi=700, t_end_pad=200.0)
+    bank = _with_q(w.bank, 9)
+    data = sft.SFTData.from_workload(w, storage="f32")
+    kw = dict(K=K, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0, waveform="pn35")
+    compare(gpu_scan(data, bank, **kw), orc_scan(w, bank, **kw), label="pn35 one row K=%d" % K)
+
+
+# ----------------------------------------------------------------------------- start reference
+def test_start_reference_fp64_tiny(tiny):
+    """The paper's own expansion point (Sec. III.B: Taylor expansion at the SFT start, Fig. 1):
+    FP64 Dirichlet on the tiny data against the oracle's start form."""
+    data = sft.SFTData.from_workload(tiny, storage="f64")
+    kw = dict(K=4, kernel="dirichlet", precision="fp64", t_ref="start", delta_max=1.0)
+    e = compare(gpu_scan(data, tiny.bank, **kw), orc_scan(tiny, tiny.bank, **kw), label="tiny fp64 start")
+    assert e < 1e-9
+
+
+@pytest.mark.parametrize("waveform,K", [("newton", 8), ("pn35", 8), ("newton", 24)])
+def test_start_reference_fresnel_ground(ground_small, waveform, K):
+    """Start reference with the Fresnel kernels, three rows per group, both closed-form
+    waveforms, compile-time and run-time windows; the validity flag uses the lever T."""
+    bank = _with_q(ground_small.bank, 11)
+    data = sft.SFTData.from_workload(ground_small, storage="f32")
+    kw = dict(K=K, kernel="auto", precision="fp32_kahan", a_plus=1.0, a_cross=1.0, waveform=waveform,
+              t_ref="start", delta_max=0.05)
+    g = gpu_scan(data, bank, **kw)
+    o = orc_scan(ground_small, bank, **kw)
+    compare(g, o, label="ground-small start %s K=%d" % (waveform, K))
+    assert np.any(o["flags"] & sft.FLAG_TAYLOR_INVALID)
+    # the two references differ (second order of the Taylor model), by far more than the bar
+    m = gpu_scan(data, bank, **dict(kw, t_ref="mid"))
+    assert np.max(np.abs(m["zp"] - g["zp"]) / np.sqrt(g["hhp"])) > 1e-3
