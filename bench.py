@@ -659,13 +659,26 @@ def surrogate_leg(args):
     return res
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, out, n_sample, K, kernel):
-    """The FP64 oracle on a seeded template sample of the same workload, host cores."""
+    """The FP64 oracle on a seeded template sample of the same workload, host cores; the same
+    oracle on one thread; the brute-force time-domain product of the tiny workload (the paper's
+    non-optimised comparator, Sec. V.C); the oracle on a sample of the space-based bank."""
     import oracle
+    from paper_2502_11823_amd import synth
     idx = np.sort(np.random.default_rng(12345).choice(w.n_templates, n_sample, replace=False))
     b = w.subset(idx)
     od = oracle.SFTData(w.t_start, w.n_samples, w.t_sft, w.k_lo, w.x_bins, w.psd, w.fplus, w.fcross)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.get_threads()
     t0 = time.perf_counter()
     ref = oracle.scan(od, b["mc"], b["t_c"], phi_c=b["phi_c"], K=K, kernel=oracle.K_AUTO,
                       a_plus=1.0, a_cross=1.0)
@@ -676,10 +689,44 @@ def cpu_baseline(w, out, n_sample, K, kernel):
     zx = zx[:, 0] + 1j * zx[:, 1]
     sc = np.maximum(np.abs(ref["zp"]), np.sqrt(ref["hhp"]))
     err = float(max(np.max(np.abs(zp - ref["zp"]) / sc), np.max(np.abs(zx - ref["zx"]) / sc)))
+    # one thread, 12 templates
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.scan(od, b["mc"][:12], b["t_c"][:12], phi_c=b["phi_c"][:12], K=K, kernel=oracle.K_AUTO,
+                a_plus=1.0, a_cross=1.0)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    # brute force on the tiny workload: the template at all 524,288 samples and sum x h / sigma^2
+    n_bf = 32
+    t = synth.tiny(seed=1, n_templates=n_bf)
+    tt = np.arange(t.n_sft * t.n_samples) * (t.t_sft / t.n_samples)
+    t0 = time.perf_counter()
+    for m in range(n_bf):
+        wv = oracle.waveform(t.bank["mc"][m], t.bank["t_c"][m], 0.0, tt)
+        h = wv[:, 0] * np.cos(wv[:, 1])
+        oracle.td_product(t.series, h, 1.0)
+    dtb = time.perf_counter() - t0
+    # the oracle on the space-based bank (60 SFTs of 2 days, K = 32, ragged ranges)
+    ws = synth.space(seed=3, n_templates=200_000)
+    n_sp = 4000
+    si = np.sort(np.random.default_rng(54321).choice(ws.n_templates, n_sp, replace=False))
+    bs = ws.subset(si)
+    ods = oracle.SFTData(ws.t_start, ws.n_samples, ws.t_sft, ws.k_lo, ws.x_bins, ws.psd, ws.fplus, ws.fcross)
+    t0 = time.perf_counter()
+    oracle.scan(ods, bs["mc"], bs["t_c"], phi_c=bs["phi_c"], a_first=bs["a_first"], a_last=bs["a_last"], K=32,
+                kernel=oracle.K_AUTO, a_plus=1.0, a_cross=1.0)
+    dts = time.perf_counter() - t0
     return {"value": n_sample / dt, "unit": "IP/s", "cores": threads, "kind": "oracle",
             "sample": "%d seeded templates of the same bank, all %d SFTs, FP64 oracle (C, OpenMP), %.1f s"
                       % (n_sample, w.n_sft, dt),
-            "max_rel_err_vs_gpu": err}
+            "max_rel_err_vs_gpu": err, "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+            "single_thread": {"value": 12 / dt1, "unit": "IP/s", "sample": "12 templates, %.1f s" % dt1},
+            "brute_force_tiny": {"value": n_bf / dtb, "unit": "IP/s",
+                                 "sample": "%d templates of the tiny workload, each the waveform at all %d samples "
+                                           "and sum x h / sigma^2 (numpy + oracle), %.1f s" % (n_bf, tt.size, dtb)},
+            "space_bank": {"value": n_sp / dts, "unit": "IP/s",
+                           "sample": "%d seeded templates of the space-based bank (8-60 SFTs, K = 32), %.1f s"
+                                     % (n_sp, dts)}}
 
 
 if __name__ == "__main__":

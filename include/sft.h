@@ -490,9 +490,13 @@ sft_status sft_surrogate_infer(const sft_surrogate* s, const double* u, int64_t 
                                void* hip_stream);
 
 /*
- * sft_inner_product -- one template, host arguments and host results; runs the
- * bank scan with n = 1 and waits for it.  zp and zx receive (re, im).  Any of the
- * output pointers may be NULL.  Same errors as sft_template_bank_scan.
+ * sft_inner_product -- the SFT inner product of one template (Sec. III.E, Eq. efficient:
+ * ([d,h]) = A+ Re z+ + Ax Im zx with z+, zx, the norms and rho as for the bank scan), host
+ * arguments and host results: mc, q, t_c, phi_c as one entry of sft_bank, SFT rows
+ * a_first..a_last.  Runs the bank scan with n = 1 on the default stream and waits for it;
+ * allocates and frees a small device block per call (a convenience for single evaluations,
+ * not for throughput).  zp and zx receive (re, im).  Any of the output pointers may be NULL.
+ * Same errors as sft_template_bank_scan.
  */
 sft_status sft_inner_product(const sft_data* data, double mc, double q, double t_c, double phi_c,
                              int32_t a_first, int32_t a_last, const sft_opts* opts,

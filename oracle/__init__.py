@@ -87,6 +87,10 @@ def _load():
     lib.orc_pn35_consistency.restype = D
     lib.orc_set_pn_order.argtypes = [Int]
     lib.orc_set_pn_order.restype = None
+    lib.orc_set_threads.argtypes = [Int]
+    lib.orc_set_threads.restype = None
+    lib.orc_get_threads.argtypes = []
+    lib.orc_get_threads.restype = Int
     lib.orc_tsft_max.argtypes = [D, D]
     lib.orc_tsft_max.restype = D
     _lib = lib
@@ -363,6 +367,15 @@ def fd_product(x, h, dt, S):
     x, h = _f64(x), _f64(h)
     S = _f64(np.broadcast_to(S, (x.size // 2 + 1,)))
     return _load().orc_fd_product(_ptr(x), _ptr(h), x.size, float(dt), _ptr(S))
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops."""
+    _load().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(_load().orc_get_threads())
 
 
 def tsft_max(delta, fddot_max):

@@ -41,6 +41,7 @@
  *   M_nu,mu = <h_nu, h_mu>, 2F = max_c 2 (c.x - c.M.c / 2) = x.M^{-1}.x (reading R25).
  */
 #define _GNU_SOURCE
+#include <omp.h>
 #include <complex.h>
 #include <math.h>
 #include <stdint.h>
@@ -887,6 +888,10 @@ int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
 /* ------------------------------------------------------------------------- */
 /* Brute-force inner products (Eqs. fd_product, td_product, whitened_data).   */
 /* ------------------------------------------------------------------------- */
+
+/* Thread count of the OpenMP loops (for timing the oracle on fewer cores). */
+void orc_set_threads(int n) { omp_set_num_threads(n < 1 ? 1 : n); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* <d,h> = dt * sum_j d_j h_j (discrete Eq. td_product), Neumaier-summed. */
 double orc_td_product(const double *d, const double *h, long N, double dt)
