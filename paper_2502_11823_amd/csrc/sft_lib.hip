@@ -594,6 +594,7 @@ static ScanFn pick_kernel(const sft_data* d, const sft_opts* o, int wf, bool fs,
 {
   const int kern = o->kernel == SFT_KERNEL_DIRICHLET ? KERN_DIRICHLET : KERN_FRESNEL;
   if (dop) return scan_pick_doppler(o->precision, fs ? 1 : 0, kern, o->K);
+  if (o->t_ref == SFT_REF_START) return scan_pick_start(d->storage, o->precision, wf, kern, d->nd, fs ? 1 : 0);
   if (fs) return scan_pick_fstat(o->precision, kern, o->K, d->nd);
   if (o->precision == SFT_PREC_FP64) return scan_pick_f64(wf, o->K, d->nd);
   if (d->storage == SFT_STORE_F32) {
@@ -730,7 +731,6 @@ static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t 
   a.beta_switch = o->kernel == SFT_KERNEL_AUTO ? o->beta_switch : 0.0;
   a.tsun = o->tsun;
   a.delta_max = o->delta_max;
-  a.t_ref_start = o->t_ref == SFT_REF_START ? 1 : 0;
   a.mc = bank->mc;
   a.q = bank->q;
   a.t_c = bank->t_c;

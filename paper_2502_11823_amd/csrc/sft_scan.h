@@ -6,6 +6,7 @@
 // reduction, FP64 bin split, 2K+1 kernel weights and the bin contraction (Eq. with_f_1),
 // the coherent accumulation of Eq. efficient and of the norm, in FP64 or FP32 (Kahan or
 // plain).  Writes one partial per (template, chunk); the finalize kernel combines them.
+// REF = 1: the Taylor expansion at the SFT start (the paper's form) instead of the midpoint.
 // FS = 1 (the F-statistic form, Sec. II.B) also accumulates the cross norm
 // sum F+ Fx A^2 T / S, and keeps the three norm sums in FP64.  DP = 1 (the Doppler form,
 // Sec. III.B) evaluates the chirp at the emission time t + r.n/c of each SFT row's detector
@@ -143,7 +144,7 @@ __device__ inline void stage_window(Bin* sw, const Bin* const* rp, int sb, int w
 // a group (one per detector) share the SFT midpoint, hence the chirp, the window and
 // all 2K+1 kernel weights: those are evaluated once per group and contracted with the
 // bins of each of the ND rows (the projector Lambda carries the detector dependence).
-template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS, int DP>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS, int DP, int REF>
 __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab,
                                           Bin* sw);
 
@@ -162,7 +163,7 @@ constexpr int scan_min_waves()
   return 1;
 }
 
-template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS = 0, int DP = 0>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS = 0, int DP = 0, int REF = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scan_min_waves<PREC, KERN, KC, ND, WF>())))
 void scan_kernel(ScanArgs a)
 {
@@ -196,12 +197,12 @@ void scan_kernel(ScanArgs a)
     const int c = item / a.n_tiles;
     const int64_t m = (int64_t)tile * blockDim.x + threadIdx.x;
     if (m < a.n_tmpl)
-      scan_item<Bin, PREC, KERN, KC, ND, WF, FS, DP>(a, K, m, c, tab, stage + (threadIdx.x >> 6) * (ND * WST));
+      scan_item<Bin, PREC, KERN, KC, ND, WF, FS, DP, REF>(a, K, m, c, tab, stage + (threadIdx.x >> 6) * (ND * WST));
     if (!a.persistent) break;
   }
 }
 
-template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS, int DP>
+template <typename Bin, int PREC, int KERN, int KC, int ND, int WF, int FS, int DP, int REF>
 __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const int64_t m, const int c, const float2* tab,
                                           Bin* sw)
 {
@@ -287,7 +288,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       dl2 = fma(e[6], nx, fma(e[7], ny, e[8] * nz));
     }
     // the reference time of the Taylor expansion: the SFT midpoint, or its start
-    const double tref = a.t_ref_start ? tmid - 0.5 * T : tmid;
+    const double tref = REF != 0 ? tmid - 0.5 * T : tmid;
     const double tau = DP != 0 ? tc - (tref + dl) : tc - tref;
     if (!(tau > 0.0)) {
       fl |= kFlagTau;
@@ -323,7 +324,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
     // still centred on the start frequency; the validity lever is T instead of T / 2.
     // The drift in the shift is the kernel's: 0 where the Dirichlet limit is used.
     double kwin = ch.kappa;
-    if (a.t_ref_start) {
+    if constexpr (REF != 0) {
       const double bk = (KERN == KERN_FRESNEL && !(fabs(ch.beta) <= a.beta_switch)) ? ch.beta : 0.0;
       kwin = fma(0.5, bk, ch.kappa);
       ch.phase += kPi * fma(0.25, bk, ch.kappa);
@@ -716,18 +717,31 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
 // ---------------------------------------------------------------------------- dispatch
 // Newtonian: every detector-group width 1..4.  3.5PN: widths 1 and 4 (groups of 2 or 3
 // rows run in the width-4 kernel, whose absent rows are skipped by a uniform test).
-template <typename Bin, int PREC, int KERN, int KC, int WF, int FS>
+template <typename Bin, int PREC, int KERN, int KC, int WF, int FS, int REF = 0>
 static ScanFn pick_nd(int nd)
 {
   if constexpr (WF == WF_NEWTON) {
     switch (nd) {
-    case 1: return scan_kernel<Bin, PREC, KERN, KC, 1, WF, FS>;
-    case 2: return scan_kernel<Bin, PREC, KERN, KC, 2, WF, FS>;
-    case 3: return scan_kernel<Bin, PREC, KERN, KC, 3, WF, FS>;
-    default: return scan_kernel<Bin, PREC, KERN, KC, 4, WF, FS>;
+    case 1: return scan_kernel<Bin, PREC, KERN, KC, 1, WF, FS, 0, REF>;
+    case 2: return scan_kernel<Bin, PREC, KERN, KC, 2, WF, FS, 0, REF>;
+    case 3: return scan_kernel<Bin, PREC, KERN, KC, 3, WF, FS, 0, REF>;
+    default: return scan_kernel<Bin, PREC, KERN, KC, 4, WF, FS, 0, REF>;
     }
   } else {
-    return nd == 1 ? scan_kernel<Bin, PREC, KERN, KC, 1, WF, FS> : scan_kernel<Bin, PREC, KERN, KC, 4, WF, FS>;
+    return nd == 1 ? scan_kernel<Bin, PREC, KERN, KC, 1, WF, FS, 0, REF> : scan_kernel<Bin, PREC, KERN, KC, 4, WF, FS, 0, REF>;
+  }
+}
+
+// Start reference: the run-time-K kernels only (any K), so that the compile-time windows of the
+// benchmark shapes carry no code for it.
+template <typename Bin, int PREC, int WF, int FS = 0>
+static ScanFn pick_start(int kern, int nd)
+{
+  if constexpr (PREC == SFT_PREC_FP64) {
+    return pick_nd<Bin, PREC, KERN_DIRICHLET, -1, WF, FS, 1>(nd);
+  } else {
+    return kern == KERN_DIRICHLET ? pick_nd<Bin, PREC, KERN_DIRICHLET, -1, WF, FS, 1>(nd)
+                                  : pick_nd<Bin, PREC, KERN_FRESNEL, -1, WF, FS, 1>(nd);
   }
 }
 

@@ -20,7 +20,6 @@ struct ScanArgs {
   const double* fx;
   int32_t n_groups, n_ext, k_ext_lo, n_bins, k_lo, K;
   int32_t k_nyq;            // n / 2: window centres outside [0, k_nyq] have no data
-  int32_t t_ref_start;      // 1: Taylor expansion at the SFT start (SFT_REF_START), 0: midpoint
   double T, beta_switch, tsun, delta_max;
   const double* mc;
   const double* q;
@@ -65,3 +64,5 @@ ScanFn scan_pick_fstat(int prec, int kern, int K, int nd);
 // the Doppler form (one row per timestamp group; Newtonian waveform; fs selects the
 // F-statistic form as well)
 ScanFn scan_pick_doppler(int prec, int fs, int kern, int K);
+// the Taylor expansion at the SFT start (run-time window)
+ScanFn scan_pick_start(int storage, int prec, int wf, int kern, int nd, int fs);
