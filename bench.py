@@ -196,6 +196,7 @@ def parse():
                    help="templates of the space-based leg (0 = skip the leg)")
     p.add_argument("--space-only", action="store_true", help="run only the space-based leg")
     p.add_argument("--no-fstat", action="store_true", help="skip the F-statistic leg")
+    p.add_argument("--no-order", action="store_true", help="skip the bank-order leg")
     p.add_argument("--no-doppler", action="store_true", help="skip the Doppler leg")
     p.add_argument("--no-strain", action="store_true", help="skip the SFT-creation leg")
     p.add_argument("--no-r-study", action="store_true", help="skip the accuracy-study leg")
@@ -332,6 +333,8 @@ def main():
         res["cpu_baseline"] = cpu_baseline(w, out, args.cpu_sample, K, kernel)
     if not args.no_fstat:
         res["fstat"] = fstat_leg(args, w, data, bank, opts, K)
+    if not args.no_order:
+        res["order"] = order_leg(args, w, data, bank, opts, out)
     del out, bank, data
     if not args.no_doppler:
         res["doppler"] = doppler_leg(args, w, opts, K)
@@ -344,6 +347,44 @@ def main():
     if args.surrogate_templates > 0:
         res["surrogate"] = surrogate_leg(args)
     print(json.dumps(res), flush=True)
+
+
+def order_leg(args, w, data, bank, opts, out):
+    """The same ground bank shuffled: scanned in its given order, and sorted by track on the
+    device (sort and gathers included in the time), against the sorted bank in its given order;
+    whole scans per step timed with events on the stream."""
+    import torch
+
+    from paper_2502_11823_amd import sft
+    t0 = time.time()
+    perm = np.random.default_rng(4242).permutation(w.n_templates)
+    shuf = sft.bank_to_device({k: np.ascontiguousarray(v[perm]) for k, v in w.bank.items()})
+    keep = sft.get_tuning(data)
+    tune = keep.as_dict()
+
+    def timed(b, order):
+        sft.set_tuning(data, block=tune["block"], chunk_groups=tune["chunk_groups"],
+                       persistent=tune["persistent"], order=order)
+        sft.template_bank_scan(data, b, opts, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            sft.template_bank_scan(data, b, opts, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    sorted_ms = timed(bank, "given")
+    shuf_given_ms = timed(shuf, "given")
+    shuf_track_ms = timed(shuf, "track")
+    sft.set_tuning(data, block=keep.block, chunk_groups=keep.chunk_groups, persistent=keep.persistent,
+                   order=keep.order)
+    del shuf
+    print("order leg %.1f s: sorted %.3f ms, shuffled %.3f ms, shuffled+track sort %.3f ms"
+          % (time.time() - t0, sorted_ms, shuf_given_ms, shuf_track_ms), file=sys.stderr, flush=True)
+    return {"workload": "the ground bank shuffled (seed 4242), same data, K and launch shape",
+            "sorted_given_ms": sorted_ms, "shuffled_given_ms": shuf_given_ms,
+            "shuffled_track_ms": shuf_track_ms, "track_over_sorted": shuf_track_ms / sorted_ms}
 
 
 def fstat_leg(args, w, data, bank, opts, K):

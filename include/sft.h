@@ -339,6 +339,9 @@ sft_status sft_template_bank_scan(const sft_data* data, const sft_bank* bank, in
 sft_status sft_template_bank_scan_noalloc(const sft_data* data, const sft_bank* bank, int64_t n_templates,
                                           const sft_opts* opts, sft_out* out, void* hip_stream);
 
+/* Order in which a scan visits the bank (sft_tuning.order). */
+enum { SFT_ORDER_GIVEN = 0, SFT_ORDER_TRACK = 1 };
+
 /*
  * Launch shape of the bank scan, kept per data handle (fields equal to 0 select the
  * automatic choice).  block: templates per workgroup, 64, 128 or 256 (default 256).
@@ -349,14 +352,25 @@ sft_status sft_template_bank_scan_noalloc(const sft_data* data, const sft_bank* 
  * pulling work items from a device counter until the queue is empty; 0 launches one
  * workgroup per item.  An all-zero tuning selects the automatic chunks with the
  * persistent grid.
- * Results are bitwise identical for a given tuning; different tunings change only the
- * order of the FP64 combination of partial sums.
+ * order: SFT_ORDER_GIVEN scans the bank in the caller's order, which is fast when
+ * neighbouring templates have nearly equal frequency tracks (a bank sorted by chirp mass at
+ * one coalescence time, say).  SFT_ORDER_TRACK first sorts the bank on the device by (first
+ * SFT row, leading-order frequency at the middle of the template's SFT range), scans it in
+ * that order and writes every result back to its template's given position: a bank in any
+ * order then runs at the speed of a sorted one.  The sort takes about 60 bytes per template
+ * of extra stream-ordered workspace.  A graph plan computes the order once, when it is
+ * created, and gathers the bank into it at every launch (contents changed later still give
+ * correct results); the allocation-free scan and the surrogate waveform always use the
+ * given order.
+ * Results are bitwise identical for a given tuning and bank order; different tunings change
+ * the order of the FP64 combination of partial sums, and a different bank order can change
+ * which series of the kernel a template's wavefront evaluates (rounding-level differences).
  */
 typedef struct {
   int32_t block;
   int32_t chunk_groups;
   int32_t persistent;
-  int32_t reserved;  /* must be 0 */
+  int32_t order;       /* SFT_ORDER_GIVEN (default) or SFT_ORDER_TRACK */
 } sft_tuning;
 
 /* Read or replace the tuning of a handle.  Errors: SFT_E_INVALID, SFT_E_RANGE. */
@@ -365,9 +379,11 @@ sft_status sft_set_tuning(sft_data* data, const sft_tuning* tuning);
 
 /*
  * sft_autotune -- time candidate tunings (block 64/128/256, 1..64 chunks, plain and
- * persistent grids) on the given bank with HIP events on hip_stream, reps timed runs
- * each after one warm-up, store the fastest in the handle and return it (best, best_ms
- * may be NULL).  Writes the outputs like a scan.  Synchronises hip_stream.
+ * persistent grids) on the given bank in its given order with HIP events on hip_stream,
+ * reps timed runs each after one warm-up; then time the fastest with SFT_ORDER_TRACK (sort
+ * included) and keep that order when it is faster.  Store the result in the handle and
+ * return it (best, best_ms may be NULL).  Writes the outputs like a scan.  Synchronises
+ * hip_stream.
  * Errors: those of sft_template_bank_scan, SFT_E_RANGE (reps outside [1, 100]).
  */
 sft_status sft_autotune(sft_data* data, const sft_bank* bank, int64_t n_templates, const sft_opts* opts,

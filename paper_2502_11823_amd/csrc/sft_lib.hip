@@ -27,6 +27,7 @@
 #include "sft_device.h"
 #include "sft_mlp.h"
 #include "sft_scan_args.h"
+#include "sft_sort.h"
 
 using namespace sftk;
 
@@ -138,6 +139,7 @@ struct sft_data {
   sft_tuning tune;        // launch shape of the scans on this handle (0 fields = automatic)
   double* g_eph;          // [n_groups][9] detector r/c, v/c, a/c at the group's midpoint (Doppler), or null;
                           // set, every group holds one row
+  double* row_tmid;       // [n_sft] midpoint t_start + T/2 of each row (bank ordering)
 };
 
 template <typename Bin> __device__ inline void store_bin(Bin* p, double re, double im);
@@ -280,6 +282,10 @@ static sft_status load_device(const sft_data_desc* d, const double* t_start, con
       std::vector<int32_t> grows;
       build_groups(t_start, d->n_sft, h->T, tmid, grows, h->nd);
       h->n_groups = (int32_t)tmid.size();
+      std::vector<double> rmid(d->n_sft);
+      for (int32_t r = 0; r < d->n_sft; ++r) rmid[r] = t_start[r] + 0.5 * h->T;
+      if ((e = hipMalloc(&h->row_tmid, rmid.size() * sizeof(double))) != hipSuccess) break;
+      if ((e = hipMemcpyAsync(h->row_tmid, rmid.data(), rmid.size() * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess) break;
       if ((e = hipMalloc(&h->g_tmid, tmid.size() * sizeof(double))) != hipSuccess) break;
       if ((e = hipMalloc(&h->g_rows, grows.size() * sizeof(int32_t))) != hipSuccess) break;
       if ((e = hipMemcpyAsync(h->g_tmid, tmid.data(), tmid.size() * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess) break;
@@ -426,6 +432,7 @@ extern "C" void sft_free_data(sft_data* h)
   if (h->fp) (void)hipFree(h->fp);
   if (h->fx) (void)hipFree(h->fx);
   if (h->g_eph) (void)hipFree(h->g_eph);
+  if (h->row_tmid) (void)hipFree(h->row_tmid);
   delete h;
 }
 
@@ -537,17 +544,19 @@ __device__ inline double fstat_2f(double x0, double x1, double x2, double x3, do
 }
 
 // Per template: the partials of the chunks in chunk order (FP64), rho (Eq. det_short), the
-// flags, and with nacc = 7 the cross norm and the F-statistic.
+// flags, and with nacc = 7 the cross norm and the F-statistic.  m is the template's position
+// in the scanned order; its results go to position perm[m] of the outputs (perm null: m).
 __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ part, const uint32_t* __restrict__ pflags,
                                                        int64_t n, int32_t n_chunks, int32_t nacc, double a_plus,
                                                        double a_cross, double* __restrict__ zp, double* __restrict__ zx,
                                                        double* __restrict__ hhp, double* __restrict__ hhx,
                                                        double* __restrict__ rho, uint32_t* __restrict__ flags,
                                                        const uint32_t* __restrict__ xflags, double* __restrict__ hhpx,
-                                                       double* __restrict__ twoF)
+                                                       double* __restrict__ twoF, const int32_t* __restrict__ perm)
 {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
+  const int64_t w = perm ? (int64_t)perm[m] : m;
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
   uint32_t fl = 0;
   for (int c = 0; c < n_chunks; ++c) {
@@ -574,19 +583,19 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
     const double f2 = fstat_2f(v[0], v[2], v[1], v[3], v[4], v[5], v[6], deg);
     if (deg) fl |= SFT_FLAG_FSTAT_DEGENERATE;
     fin = fin && isfinite(v[6]) && isfinite(f2);
-    if (hhpx) hhpx[m] = v[6];
-    if (twoF) twoF[m] = f2;
+    if (hhpx) hhpx[w] = v[6];
+    if (twoF) twoF[w] = f2;
   }
   if (!fin) fl |= kFlagNonfinite;
   if (xflags) fl |= xflags[m];
-  zp[2 * m] = v[0];
-  zp[2 * m + 1] = v[1];
-  zx[2 * m] = v[2];
-  zx[2 * m + 1] = v[3];
-  hhp[m] = v[4];
-  hhx[m] = v[5];
-  rho[m] = r;
-  flags[m] = fl;
+  zp[2 * w] = v[0];
+  zp[2 * w + 1] = v[1];
+  zx[2 * w] = v[2];
+  zx[2 * w + 1] = v[3];
+  hhp[w] = v[4];
+  hhx[w] = v[5];
+  rho[w] = r;
+  flags[w] = fl;
 }
 
 // wf: WF_NEWTON, WF_PN35 or WF_TABLE (the surrogate path); fs: the F-statistic form
@@ -692,6 +701,8 @@ static sft_status validate_tuning(const sft_tuning* t)
     return fail(SFT_E_RANGE, "tuning: block must be 0, 64, 128 or 256 (got %d)", t->block);
   if (t->chunk_groups < 0) return fail(SFT_E_RANGE, "tuning: chunk_groups must be >= 0");
   if (t->persistent != 0 && t->persistent != 1) return fail(SFT_E_RANGE, "tuning: persistent must be 0 or 1");
+  if (t->order != SFT_ORDER_GIVEN && t->order != SFT_ORDER_TRACK)
+    return fail(SFT_E_RANGE, "tuning: order must be SFT_ORDER_GIVEN or SFT_ORDER_TRACK (got %d)", t->order);
   return SFT_OK;
 }
 
@@ -700,12 +711,24 @@ struct Prepared {
   ScanArgs a;
   ScanFn fn;
   const uint32_t* xflags;  // extra per-template flags ORed in by the finalize kernel (or null)
+  const int32_t* perm;     // output position of each scanned template (or null: the given order)
   dim3 grid, block;
   int32_t nacc;            // partial sums per template and chunk: 6, or 7 in the F-statistic form
   size_t part_bytes, flag_bytes, counter_off, ws_bytes;
   int64_t n;
   double a_plus, a_cross;
 };
+
+static void bind_bank(ScanArgs& a, const sft_bank& b)
+{
+  a.mc = b.mc;
+  a.q = b.q;
+  a.t_c = b.t_c;
+  a.phi_c = b.phi_c;
+  a.a_first = b.a_first;
+  a.a_last = b.a_last;
+  a.sky = b.sky;
+}
 
 static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t n, const sft_opts* o,
                                const sft_tuning& t, Prepared& P, bool fs, int wf = -1, const double* wtab = nullptr,
@@ -731,17 +754,12 @@ static sft_status prepare_scan(const sft_data* d, const sft_bank* bank, int64_t 
   a.beta_switch = o->kernel == SFT_KERNEL_AUTO ? o->beta_switch : 0.0;
   a.tsun = o->tsun;
   a.delta_max = o->delta_max;
-  a.mc = bank->mc;
-  a.q = bank->q;
-  a.t_c = bank->t_c;
-  a.phi_c = bank->phi_c;
-  a.a_first = bank->a_first;
-  a.a_last = bank->a_last;
-  a.sky = bank->sky;
+  bind_bank(a, *bank);
   a.g_eph = d->g_eph;
   a.n_tmpl = n;
   a.wtab = wtab;
   P.xflags = xflags;
+  P.perm = nullptr;
   P.fn = pick_kernel(d, o, wf >= 0 ? wf : o->waveform, fs, bank->sky != nullptr);
   P.nacc = fs ? 7 : 6;
   const int B = t.block ? t.block : 256;
@@ -803,8 +821,111 @@ static hipError_t enqueue_scan(Prepared& P, void* ws, sft_out* out, hipStream_t 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, a.part, a.pflags, P.n,
                      a.n_chunks, P.nacc, P.a_plus, P.a_cross, out->zp, out->zx, out->hhp, out->hhx, out->rho,
-                     out->flags, P.xflags, P.nacc == 7 ? out->hhpx : nullptr, P.nacc == 7 ? out->twoF : nullptr);
+                     out->flags, P.xflags, P.nacc == 7 ? out->hhpx : nullptr, P.nacc == 7 ? out->twoF : nullptr,
+                     P.perm);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- bank order
+// Workspace of SFT_ORDER_TRACK: the permutation, the sort's keys, indices and temporary
+// storage, and the bank gathered into the sorted order.  Offsets are 256-byte aligned.
+struct BankOrder {
+  int64_t n = 0;
+  size_t temp_bytes = 0, bytes = 0;
+  size_t o_perm = 0, o_ka = 0, o_kb = 0, o_idx = 0, o_temp = 0;
+  size_t o_mc = 0, o_q = 0, o_tc = 0, o_phi = 0, o_af = 0, o_al = 0, o_sky = 0;
+  sft_bank given{};
+  sft_bank sorted{};
+  char* base = nullptr;
+  int32_t* perm = nullptr;
+};
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static sft_status order_layout(const sft_bank* bank, int64_t n, BankOrder& B)
+{
+  B.n = n;
+  B.given = *bank;
+  hipError_t e = sort_temp_bytes(n, &B.temp_bytes);
+  if (e != hipSuccess) return fail(SFT_E_DEVICE, "scan (track order): radix sort size: %s", hipGetErrorString(e));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  const size_t u = (size_t)n;
+  B.o_perm = take(u * sizeof(int32_t));
+  B.o_ka = take(u * sizeof(uint64_t));
+  B.o_kb = take(u * sizeof(uint64_t));
+  B.o_idx = take(u * sizeof(int32_t));
+  B.o_temp = take(B.temp_bytes);
+  B.o_mc = take(u * sizeof(double));
+  B.o_tc = take(u * sizeof(double));
+  if (bank->q) B.o_q = take(u * sizeof(double));
+  if (bank->phi_c) B.o_phi = take(u * sizeof(double));
+  if (bank->a_first) B.o_af = take(u * sizeof(int32_t));
+  if (bank->a_last) B.o_al = take(u * sizeof(int32_t));
+  if (bank->sky) B.o_sky = take(3 * u * sizeof(double));
+  B.bytes = off;
+  return SFT_OK;
+}
+
+static void order_bind(BankOrder& B, void* base)
+{
+  char* c = (char*)base;
+  B.base = c;
+  B.perm = (int32_t*)(c + B.o_perm);
+  B.sorted = sft_bank{};
+  B.sorted.mc = (const double*)(c + B.o_mc);
+  B.sorted.t_c = (const double*)(c + B.o_tc);
+  if (B.given.q) B.sorted.q = (const double*)(c + B.o_q);
+  if (B.given.phi_c) B.sorted.phi_c = (const double*)(c + B.o_phi);
+  if (B.given.a_first) B.sorted.a_first = (const int32_t*)(c + B.o_af);
+  if (B.given.a_last) B.sorted.a_last = (const int32_t*)(c + B.o_al);
+  if (B.given.sky) B.sorted.sky = (const double*)(c + B.o_sky);
+}
+
+// the order of the given bank (keys, radix sort) into B.perm
+static hipError_t order_sort(const sft_data* d, const sft_opts* o, BankOrder& B, hipStream_t st)
+{
+  SortKeyArgs k;
+  k.mc = B.given.mc;
+  k.t_c = B.given.t_c;
+  k.a_first = B.given.a_first;
+  k.a_last = B.given.a_last;
+  k.row_tmid = d->row_tmid;
+  k.n_sft = d->n_sft;
+  k.T = d->T;
+  k.tsun = o->tsun;
+  k.n = B.n;
+  return sort_by_track(k, B.base + B.o_temp, B.temp_bytes, (uint64_t*)(B.base + B.o_ka), (uint64_t*)(B.base + B.o_kb),
+                       (int32_t*)(B.base + B.o_idx), B.perm, st);
+}
+
+// the given bank's arrays gathered into the order B.perm
+static hipError_t order_gather(const BankOrder& B, hipStream_t st)
+{
+  const sft_bank& g = B.given;
+  const sft_bank& s = B.sorted;
+  hipError_t e = gather_f64(g.mc, B.perm, B.n, 1, (double*)s.mc, st);
+  if (e == hipSuccess) e = gather_f64(g.t_c, B.perm, B.n, 1, (double*)s.t_c, st);
+  if (e == hipSuccess && g.q) e = gather_f64(g.q, B.perm, B.n, 1, (double*)s.q, st);
+  if (e == hipSuccess && g.phi_c) e = gather_f64(g.phi_c, B.perm, B.n, 1, (double*)s.phi_c, st);
+  if (e == hipSuccess && g.a_first) e = gather_i32(g.a_first, B.perm, B.n, (int32_t*)s.a_first, st);
+  if (e == hipSuccess && g.a_last) e = gather_i32(g.a_last, B.perm, B.n, (int32_t*)s.a_last, st);
+  if (e == hipSuccess && g.sky) e = gather_f64(g.sky, B.perm, B.n, 3, (double*)s.sky, st);
+  return e;
+}
+
+// scan P over the bank in the order B (bound to its workspace): gather, scan, finalize with perm
+static hipError_t enqueue_ordered(Prepared& P, BankOrder& B, void* ws, sft_out* out, hipStream_t st, bool timed)
+{
+  hipError_t e = order_gather(B, st);
+  if (e != hipSuccess) return e;
+  bind_bank(P.a, B.sorted);
+  P.perm = B.perm;
+  return enqueue_scan(P, ws, out, st, timed);
 }
 
 // ============================================================================ surrogate
@@ -1114,9 +1235,19 @@ extern "C" sft_status sft_template_bank_scan(const sft_data* d, const sft_bank* 
   if (o->waveform == SFT_WF_SURROGATE) return surrogate_scan(d, bank, n, o, out, st);
   Prepared P;
   if ((s = prepare_scan(d, bank, n, o, d->tune, P, out->twoF != nullptr)) != SFT_OK) return s;
+  const bool track = d->tune.order == SFT_ORDER_TRACK && n > 1;
+  BankOrder B;
+  if (track && (s = order_layout(bank, n, B)) != SFT_OK) return s;
   void* ws = nullptr;
-  HIP_OR_FAIL(hipMallocAsync(&ws, P.ws_bytes, st));
-  hipError_t e = enqueue_scan(P, ws, out, st, true);
+  HIP_OR_FAIL(hipMallocAsync(&ws, P.ws_bytes + (track ? B.bytes : 0), st));
+  hipError_t e;
+  if (track) {
+    order_bind(B, (char*)ws + P.ws_bytes);
+    e = order_sort(d, o, B, st);
+    if (e == hipSuccess) e = enqueue_ordered(P, B, ws, out, st, true);
+  } else {
+    e = enqueue_scan(P, ws, out, st, true);
+  }
   hipError_t e2 = hipFreeAsync(ws, st);
   if (e != hipSuccess) return fail(SFT_E_DEVICE, "scan: launch failed: %s", hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(SFT_E_DEVICE, "scan: hipFreeAsync: %s", hipGetErrorString(e2));
@@ -1199,7 +1330,6 @@ extern "C" sft_status sft_set_tuning(sft_data* d, const sft_tuning* t)
   sft_status s = validate_tuning(t);
   if (s != SFT_OK) return s;
   d->tune = *t;
-  d->tune.reserved = 0;
   return SFT_OK;
 }
 
@@ -1258,13 +1388,48 @@ extern "C" sft_status sft_autotune(sft_data* d, const sft_bank* bank, int64_t n,
       bi = i;
     }
   }
+  hipError_t e2 = hipFreeAsync(ws, st);
+  ws = nullptr;
+  // the fastest tuning again with the bank sorted by track (the sort timed with it)
+  sft_tuning bt = cand[bi];
+  BankOrder B;
+  if (e == hipSuccess && e2 == hipSuccess && n > 1) {
+    if ((s = order_layout(bank, n, B)) != SFT_OK) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return s;
+    }
+    Prepared P = preps[bi];
+    e = hipMallocAsync(&ws, P.ws_bytes + B.bytes, st);
+    if (e == hipSuccess) {
+      order_bind(B, (char*)ws + P.ws_bytes);
+      hipError_t el = order_sort(d, o, B, st);
+      if (el == hipSuccess) el = enqueue_ordered(P, B, ws, out, st, false);   // warm-up
+      if (el == hipSuccess) el = hipEventRecord(e0, st);
+      for (int r = 0; r < reps && el == hipSuccess; ++r) {
+        el = order_sort(d, o, B, st);
+        if (el == hipSuccess) el = enqueue_ordered(P, B, ws, out, st, false);
+      }
+      if (el == hipSuccess) el = hipEventRecord(e1, st);
+      if (el == hipSuccess) el = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (el == hipSuccess) el = hipEventElapsedTime(&ms, e0, e1);
+      if (el == hipSuccess && ms / (float)reps < bms) {
+        bms = ms / (float)reps;
+        bt.order = SFT_ORDER_TRACK;
+      } else if (el == hipSuccess) {
+        el = enqueue_scan(preps[bi], ws, out, st, false);   // outputs of the kept tuning
+      }
+      e = el;
+      e2 = hipFreeAsync(ws, st);
+    }
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  hipError_t e2 = hipFreeAsync(ws, st);
   if (e != hipSuccess) return fail(SFT_E_DEVICE, "sft_autotune: %s", hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(SFT_E_DEVICE, "sft_autotune: hipFreeAsync: %s", hipGetErrorString(e2));
-  d->tune = cand[bi];
-  if (best) *best = cand[bi];
+  d->tune = bt;
+  if (best) *best = bt;
   if (best_ms) *best_ms = bms;
   return SFT_OK;
 }
@@ -1276,6 +1441,8 @@ struct sft_plan {
   sft_out out;
   hipGraph_t graph;
   hipGraphExec_t exec;
+  BankOrder B;   // with SFT_ORDER_TRACK: the order fixed at creation (B.perm) and the gathered bank
+  bool track;
 };
 
 extern "C" void sft_plan_destroy(sft_plan* p)
@@ -1308,24 +1475,38 @@ extern "C" sft_status sft_plan_create(const sft_data* d, const sft_bank* bank, i
     delete p;
     return s;
   }
-  hipError_t e = hipMalloc(&p->ws, p->P.ws_bytes);
+  p->track = d->tune.order == SFT_ORDER_TRACK && n > 1;
+  if (p->track && (s = order_layout(bank, n, p->B)) != SFT_OK) {
+    delete p;
+    return s;
+  }
+  hipError_t e = hipMalloc(&p->ws, p->P.ws_bytes + (p->track ? p->B.bytes : 0));
   if (e != hipSuccess) {
     sft_plan_destroy(p);
     return fail(e == hipErrorOutOfMemory ? SFT_E_NOMEM : SFT_E_DEVICE, "sft_plan_create: hipMalloc: %s", hipGetErrorString(e));
   }
   hipStream_t cs = nullptr;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess && p->track) {
+    // the order of the bank's contents now (work queued on other streams finished first);
+    // the radix sort stays outside the graph
+    order_bind(p->B, (char*)p->ws + p->P.ws_bytes);
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = order_sort(d, o, p->B, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
+  }
   if (e == hipSuccess) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t el = enqueue_scan(p->P, p->ws, &p->out, cs, false);
+      hipError_t el = p->track ? enqueue_ordered(p->P, p->B, p->ws, &p->out, cs, false)
+                               : enqueue_scan(p->P, p->ws, &p->out, cs, false);
       hipGraph_t g = nullptr;
       e = hipStreamEndCapture(cs, &g);
       p->graph = g;
       if (el != hipSuccess) e = el;
     }
-    (void)hipStreamDestroy(cs);
   }
+  if (cs) (void)hipStreamDestroy(cs);
   if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     sft_plan_destroy(p);

@@ -67,12 +67,16 @@ class SurrogateDesc(ctypes.Structure):
                 ("judge_tol", ctypes.c_double)]
 
 
+ORDER = {"given": 0, "track": 1}
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("chunk_groups", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("order", ctypes.c_int32)]
 
     def as_dict(self):
-        return {"block": self.block, "chunk_groups": self.chunk_groups, "persistent": self.persistent}
+        return {"block": self.block, "chunk_groups": self.chunk_groups, "persistent": self.persistent,
+                "order": {v: k for k, v in ORDER.items()}.get(self.order, self.order)}
 
 
 EXPORTS = ["sft_load_data", "sft_free_data", "sft_default_opts", "sft_template_bank_scan",
@@ -439,8 +443,9 @@ def get_tuning(data: SFTData) -> Tuning:
     return t
 
 
-def set_tuning(data: SFTData, block=0, chunk_groups=0, persistent=0):
-    t = Tuning(int(block), int(chunk_groups), int(persistent), 0)
+def set_tuning(data: SFTData, block=0, chunk_groups=0, persistent=0, order="given"):
+    """Launch shape and bank order ("given" or "track": sorted on the device) of the handle."""
+    t = Tuning(int(block), int(chunk_groups), int(persistent), ORDER[order] if isinstance(order, str) else int(order))
     _check(lib().sft_set_tuning(data.handle, ctypes.byref(t)))
 
 

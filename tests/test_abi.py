@@ -36,6 +36,7 @@ def test_version_and_defaults():
     assert o.surrogate is None
     assert ctypes.sizeof(sft.DataDesc) == 32 and ctypes.sizeof(sft.Opts) == 72
     assert ctypes.sizeof(sft.Out) == 72 and ctypes.sizeof(sft.SurrogateDesc) == 88
+    assert ctypes.sizeof(sft.Tuning) == 16
 
 
 def test_load_data_rejects_bad_descriptors():
