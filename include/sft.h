@@ -425,8 +425,11 @@ void sft_plan_destroy(sft_plan* plan);
  * y2 = ln(A_3.5PN / A_Newton) / c_amp.
  * Judge: per template, over the SFT rows it uses, the match of the surrogate against
  * the 3.5PN waveform in the SFT picture, mismatch = 1 - |sum_a w_a exp(i dphi_a)
- * sinc(T df_a)| / sum_a w_a with w_a = A_3.5PN,a^2, dphi and df the surrogate minus
- * 3.5PN phase and frequency at the SFT midpoint.  A template whose mismatch is not
+ * sinc(T df_a)| / sum_a w_a with w_a = A_3.5PN,a^2 T / S_a(f_3.5PN,a) (the row's share of
+ * <h,h>, S_a interpolated like the norm; a row whose PSD is masked or outside the stored band
+ * there has no weight), dphi and df the surrogate minus 3.5PN phase and frequency at the SFT
+ * midpoint.  With F32 storage the weights use the stored FP32 PSD (mismatch within ~1e-7 of
+ * the FP64 value).  A template whose mismatch is not
  * <= judge_tol is evaluated with the 3.5PN waveform and flagged
  * SFT_FLAG_SURROGATE_FALLBACK.  The scan evaluates the network in FP64 (from the FP32
  * parameters, or from their BF16 roundings when weights_bf16 = 1).

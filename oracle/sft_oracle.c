@@ -607,6 +607,21 @@ static int orc_whitened_bin(const orc_data *D, long a, long k, double complex *o
   return 1;
 }
 
+/* S_a(kappa) of SFT a at kappa bins (reading R11): linear interpolation between the stored
+ * PSD bins floor(kappa) and floor(kappa) + 1.  Returns 0, or -1 when either bin is outside
+ * the stored band or not positive and finite. */
+static int orc_psd_at(const orc_data *D, long a, double kappa, double *S)
+{
+  double kf = floor(kappa);
+  double w = kappa - kf;
+  long i0 = (long)kf - D->k_lo;
+  if (i0 < 0 || i0 + 1 >= D->n_bins) return -1;
+  double S0 = D->psd[a * D->n_bins + i0], S1 = D->psd[a * D->n_bins + i0 + 1];
+  if (!(S0 > 0.0) || !(S1 > 0.0) || !isfinite(S0) || !isfinite(S1)) return -1;
+  *S = (1.0 - w) * S0 + w * S1;
+  return 0;
+}
+
 typedef struct {
   int K;          /* window half-width; K < 0 => all n bins (test-only) */
   int kernel;     /* ORC_K_* */
@@ -736,13 +751,8 @@ static void orc_template_sum(const orc_data *D, const orc_opts *o,
     orc_sum_add(&zxr, fxa * creal(term));
     orc_sum_add(&zxi, fxa * cimag(term));
     /* ⟨h,h⟩ per SFT (reading R11): A^2 T / S_a(f_a), S linearly interpolated. */
-    double kf = floor(kappa);
-    double w = kappa - kf;
-    long i0 = (long)kf - D->k_lo;
-    if (i0 < 0 || i0 + 1 >= D->n_bins) { fl |= ORC_F_OUT_OF_BAND; continue; }
-    double S0 = D->psd[a * D->n_bins + i0], S1 = D->psd[a * D->n_bins + i0 + 1];
-    if (!(S0 > 0.0) || !(S1 > 0.0) || !isfinite(S0) || !isfinite(S1)) { fl |= ORC_F_OUT_OF_BAND; continue; }
-    double S = (1.0 - w) * S0 + w * S1;
+    double S;
+    if (orc_psd_at(D, a, kappa, &S) != 0) { fl |= ORC_F_OUT_OF_BAND; continue; }
     double hterm = A[a] * A[a] * T / S;
     orc_sum_add(&hp, fpa * fpa * hterm);
     orc_sum_add(&hx, fxa * fxa * hterm);
@@ -838,8 +848,9 @@ int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
       if (wf == ORC_WF_SURROGATE) {
         /* surrogate judge (reading R23): match of the surrogate against the 3.5PN
          * waveform in the SFT framework, |sum_a w_a e^{i dphi_a} sinc(T df_a)| / sum_a w_a,
-         * w_a = A_PN,a^2 over the template's SFTs; mismatch above the tolerance selects
-         * the 3.5PN waveform for this template. */
+         * w_a = A_PN,a^2 T / S_a(f_PN,a) (the SFT's share of <h,h>, reading R11) over the
+         * template's SFTs, no weight where S_a is masked or outside the band; mismatch above
+         * the tolerance selects the 3.5PN waveform for this template. */
         double sr = 0.0, si = 0.0, sw = 0.0;
         for (long a = lo; a <= hi && a < n_sft; a++) {
           if (a < 0) continue;
@@ -850,7 +861,9 @@ int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
           if (orc_pn35(mc[m], qm, t_c[m], pc, tref, tsun, wp) != 0) continue;
           double dk = (ws[2] - wp[2]) * T;
           double snc = fabs(dk) < 1e-8 ? 1.0 - ORC_PI * ORC_PI * dk * dk / 6.0 : sin(ORC_PI * dk) / (ORC_PI * dk);
-          double w = wp[0] * wp[0];
+          double S;
+          if (orc_psd_at(&D, a, wp[2] * T, &S) != 0) continue;
+          double w = wp[0] * wp[0] * T / S;
           sr += w * cos(ws[1] - wp[1]) * snc;
           si += w * sin(ws[1] - wp[1]) * snc;
           sw += w;

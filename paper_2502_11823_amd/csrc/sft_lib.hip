@@ -1036,9 +1036,28 @@ __global__ __launch_bounds__(256) void sur_inputs_kernel(SurArgs sa, const doubl
   U[3 * r + 2] = u[2];
 }
 
+// S_r(kappa) of SFT row r, linearly interpolated between the stored PSD bins floor(kappa) and
+// floor(kappa) + 1 (the interpolation of the norm); 0 when either bin is outside the stored
+// band or masked (stored as 0).
+template <typename PS>
+__device__ inline double psd_at(const PS* __restrict__ psd, int r, double kappa, int32_t k_lo, int32_t n_bins)
+{
+  const double kf = floor(kappa);
+  const double i0 = kf - (double)k_lo;
+  if (!(i0 >= 0.0 && i0 + 1.0 < (double)n_bins)) return 0.0;
+  const PS* p = psd + (int64_t)r * n_bins + (int64_t)i0;
+  const double S0 = (double)p[0], S1 = (double)p[1];
+  if (!(S0 > 0.0) || !(S1 > 0.0)) return 0.0;
+  const double w = kappa - kf;
+  return (1.0 - w) * S0 + w * S1;
+}
+
 // One lane per template of the batch: the surrogate chirp of every group the template
 // uses (Newtonian chirp plus the network's corrections), the judge against the 3.5PN
 // chirp, and the chirp table the scan reads (the 3.5PN chirps for a rejected template).
+// The judge's weight of SFT row r is A_PN^2 T / S_r(f_PN) (the row's share of <h,h>); rows
+// whose PSD is masked or outside the stored band at f_PN carry no weight.
+template <typename PS>
 __global__ __launch_bounds__(256) void sur_post_kernel(SurArgs sa, const double* __restrict__ mc,
                                                        const double* __restrict__ q, const double* __restrict__ t_c,
                                                        const double* __restrict__ phi_c, const int32_t* __restrict__ a_first,
@@ -1047,7 +1066,8 @@ __global__ __launch_bounds__(256) void sur_post_kernel(SurArgs sa, const double*
                                                        int64_t nb, int32_t n_groups, double T,
                                                        const double* __restrict__ Y, const double* __restrict__ dY,
                                                        double* __restrict__ tab, uint32_t* __restrict__ xflags,
-                                                       double* __restrict__ mismatch)
+                                                       double* __restrict__ mismatch, const PS* __restrict__ psd,
+                                                       int32_t k_lo, int32_t n_bins)
 {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= nb) return;
@@ -1094,11 +1114,18 @@ __global__ __launch_bounds__(256) void sur_post_kernel(SurArgs sa, const double*
     w[2 * ps] = cs.amp;
     w[3 * ps] = cs.beta;
     w[4 * ps] = cs.dres;
-    // judge term: A_PN^2 exp(i dphi) sinc(dkappa) per SFT row
+    // judge term: A_PN^2 T / S_r(f_PN) exp(i dphi) sinc(dkappa), summed over the group's rows
     const Chirp cp = pn35_chirp(tau, pm.nu, pm.inv5Mnu, pm.Mt, pm.nu25, phic, T, pc);
     const double dk = cs.kappa - cp.kappa;
     const double snc = fabs(dk) < 1e-8 ? 1.0 - kPi * kPi * dk * dk / 6.0 : sin(kPi * dk) / (kPi * dk);
-    const double wt = cp.amp * cp.amp * (double)n_act;
+    double inv_s = 0.0;
+    for (int d = 0; d < SFT_GROUP_MAX; ++d) {
+      const int rr = g_rows[g * SFT_GROUP_MAX + d];
+      if (rr < 0 || rr < lo || rr > hi) continue;
+      const double S = psd_at(psd, rr, cp.kappa, k_lo, n_bins);
+      if (S > 0.0) inv_s += 1.0 / S;
+    }
+    const double wt = cp.amp * cp.amp * T * inv_s;
     double sd, cd;
     sincos(cs.phase - cp.phase, &sd, &cd);
     sr += wt * cd * snc;
@@ -1209,9 +1236,14 @@ static sft_status surrogate_scan(const sft_data* d, const sft_bank* bank, int64_
                        d->g_tmid, nb, d->n_groups, U);
     if ((e = hipGetLastError()) != hipSuccess) break;
     if ((e = mlp_infer(sur, U, rows, Y, dY, ws + off_nn, chunk, st)) != hipSuccess) break;
-    hipLaunchKernelGGL(sur_post_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, sa, b.mc, b.q, b.t_c,
-                       b.phi_c, b.a_first, b.a_last, d->g_tmid, d->g_rows, nb, d->n_groups, d->T, Y, dY, tab, xf,
-                       ob.mismatch);
+    if (d->storage == SFT_STORE_F64)
+      hipLaunchKernelGGL(sur_post_kernel<double>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, sa, b.mc, b.q,
+                         b.t_c, b.phi_c, b.a_first, b.a_last, d->g_tmid, d->g_rows, nb, d->n_groups, d->T, Y, dY, tab,
+                         xf, ob.mismatch, (const double*)d->psd, d->k_lo, d->n_bins);
+    else
+      hipLaunchKernelGGL(sur_post_kernel<float>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, sa, b.mc, b.q,
+                         b.t_c, b.phi_c, b.a_first, b.a_last, d->g_tmid, d->g_rows, nb, d->n_groups, d->T, Y, dY, tab,
+                         xf, ob.mismatch, (const float*)d->psd, d->k_lo, d->n_bins);
     if ((e = hipGetLastError()) != hipSuccess) break;
     Prepared P;
     if ((s = prepare_scan(d, &b, nb, o, d->tune, P, false, WF_TABLE, tab, xf)) != SFT_OK) break;
