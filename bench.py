@@ -681,6 +681,23 @@ def surrogate_leg(args):
     flags = out["flags"].cpu().numpy()
     mm = out["mismatch"].cpu().numpy()
     fb = float(np.mean((flags & sft.FLAG_SURROGATE_FALLBACK) > 0))
+    z64 = out["zp"].cpu().numpy()
+    nz64 = np.sqrt(out["hhp"].cpu().numpy())
+    # the same trained parameters evaluated on the BF16 matrix cores
+    par = s.get_params()
+    lowp = {}
+    for mode in ("bf16x3", "bf16"):
+        sb = sft.Surrogate(par, hidden=hidden, layers=layers, judge_tol=1e-4, inference=mode, **SUR_CFG)
+        t_b = timed(sft.make_opts(waveform="surrogate", surrogate=sb, **common))
+        fl_b = out["flags"].cpu().numpy()
+        dz = np.abs(out["zp"].cpu().numpy() - z64).max(axis=1) / np.maximum(np.abs(z64).max(axis=1), nz64)
+        lowp[mode] = {"value": n / t_b, "ms_per_step": 1e3 * t_b, "over_fp64_network": t_sur / t_b,
+                      "fallback_frac": float(np.mean((fl_b & sft.FLAG_SURROGATE_FALLBACK) > 0)),
+                      "mismatch_median": float(np.median(out["mismatch"].cpu().numpy())),
+                      "max_dz_vs_fp64_network": float(dz.max()), "median_dz_vs_fp64_network": float(np.median(dz))}
+        print("surrogate scan, %s network: %.1f ms, fallback %.4f, max dz %.2e" % (
+            mode, 1e3 * t_b, lowp[mode]["fallback_frac"], dz.max()), file=sys.stderr, flush=True)
+        sb.close()
     evals = n * w.n_sft
     mlp_flop = evals * 2 * 2 * (3 * hidden + (layers - 1) * hidden * hidden + hidden * 2)
     res = {"workload": "tiny data (256 SFTs x 64 s, 1 detector, K=4 Dirichlet, FP32 Kahan sums), %d templates "
@@ -690,7 +707,7 @@ def surrogate_leg(args):
            "plain_newton_value": n / t_plain, "pn35_value": n / t_pn,
            "surrogate_over_plain": t_plain / t_sur, "surrogate_over_pn35": t_pn / t_sur,
            "network_evals_per_step": evals, "network_fp64_tflop_per_step": mlp_flop / 1e12,
-           "fallback_frac": fb, "judge_tol": 1e-4,
+           "fallback_frac": fb, "judge_tol": 1e-4, "network_bf16": lowp,
            "mismatch_median": float(np.median(mm)), "mismatch_p99": float(np.quantile(mm, 0.99)),
            "train": {"samples": args.surrogate_samples, "epochs": args.surrogate_epochs, "batch": 4096,
                      "targets_s": t_targets, "train_s": t_train, "epoch_loss": [float(v) for v in hist]}}

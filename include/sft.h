@@ -431,14 +431,27 @@ void sft_plan_destroy(sft_plan* plan);
  * midpoint.  With F32 storage the weights use the stored FP32 PSD (mismatch within ~1e-7 of
  * the FP64 value).  A template whose mismatch is not
  * <= judge_tol is evaluated with the 3.5PN waveform and flagged
- * SFT_FLAG_SURROGATE_FALLBACK.  The scan evaluates the network in FP64 (from the FP32
- * parameters, or from their BF16 roundings when weights_bf16 = 1).
+ * SFT_FLAG_SURROGATE_FALLBACK.  The judge itself is always FP64.
+ * Inference arithmetic of the network (sft_surrogate_desc.inference):
+ *   SFT_INFER_FP64       FP64 evaluation of the FP32 parameters (FP64 matrix cores when
+ *                        hidden is a multiple of 16 up to 128);
+ *   SFT_INFER_FP64_BF16W FP64 evaluation of the parameters rounded to BF16;
+ *   SFT_INFER_BF16X3     BF16 matrix cores with FP32 accumulation and FP32 activations, every
+ *                        operand split into two BF16 numbers (16 significant bits) and each
+ *                        product taken as three BF16 products: network outputs within ~1e-5 of
+ *                        FP64;
+ *   SFT_INFER_BF16       BF16 matrix cores, operands rounded to BF16 (8 significant bits),
+ *                        FP32 accumulation: outputs within ~1e-2, for speed studies; the judge
+ *                        rejects what this costs in phase.
+ * The BF16 modes need hidden = 32, 64, 96 or 128 (SFT_E_UNSUPPORTED otherwise).
  */
+enum { SFT_INFER_FP64 = 0, SFT_INFER_FP64_BF16W = 1, SFT_INFER_BF16X3 = 2, SFT_INFER_BF16 = 3 };
+
 typedef struct {
   int32_t hidden;        /* hidden width, 8 .. 256 */
   int32_t layers;        /* hidden layers, 1 .. 8 */
   int32_t head;          /* 1: analytic 1PN + 1.5PN phase head; 0: the network carries it */
-  int32_t weights_bf16;  /* 1: inference with BF16-rounded parameters */
+  int32_t inference;     /* SFT_INFER_* */
   double mc_lo, mc_hi;   /* input ranges of the normalisation */
   double q_lo, q_hi;
   double lt_lo, lt_hi;   /* range of ln(tau / s) */

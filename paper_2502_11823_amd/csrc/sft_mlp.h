@@ -16,6 +16,7 @@ struct sft_surrogate {
   float* mom1;        // [P] Adam first moment
   float* mom2;        // [P] Adam second moment
   double* par_inf;    // [P] inference copy: FP64 values of the FP32 (or BF16-rounded) parameters
+  void* frag;         // BF16 inference: the hidden-to-hidden weights as packed MFMA fragments (or null)
   int32_t step;       // Adam step count
   int device;
 };

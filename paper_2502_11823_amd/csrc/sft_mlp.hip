@@ -409,6 +409,194 @@ static hipError_t mlp_fused(const sft_surrogate* s, const double* U, int64_t n, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------- BF16 fused inference
+// The same network for 16 rows per wavefront on the BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation), activations in FP32 registers.  Operand
+// layouts of that instruction: A[i][k] in lane i + 16 (k / 8), element k % 8; B[k][j] in lane
+// j + 16 (k / 8), element k % 8; D[i][j] in lane j + 16 (i / 4), element i % 4.  Lane l (row
+// j = l % 16, group g = l / 16) therefore holds the units 16 m + 4 g + v (v = 0..3) of row j,
+// and as its B operand of K step s it supplies the units 32 s + 16 (e / 4) + 4 g + e % 4
+// (element e = 0..7), which it already holds (tiles 2 s and 2 s + 1).  The weight fragments
+// are packed in that permuted K order whenever the parameters change (pack_bf16_kernel), one
+// 16-byte fragment per lane, hi and lo parts: fragment index
+// (((layer - 1) NT + mo) S + s) 2 + part, times 64, plus the lane.
+// SPLIT: every operand x is the sum of two BF16 numbers hi = bf16(x), lo = bf16(x - hi) (16
+// significant bits) and each product takes three MFMAs, hi.hi + lo.hi + hi.lo (lo.lo is below
+// 2^-16 relative).  Without SPLIT: one MFMA of the rounded operands.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+static bool mlp_bf16_ok(int hidden) { return hidden % 32 == 0 && hidden >= 32 && hidden <= 128; }
+
+// fragments of one hidden-to-hidden layer (16 bytes each)
+static int64_t bf16_frags_per_layer(int hidden) { return (int64_t)(hidden / 16) * (hidden / 32) * 2 * 64; }
+
+__global__ __launch_bounds__(256) void pack_bf16_kernel(const float* __restrict__ par, int H, int layers,
+                                                        bf16x8* __restrict__ frag)
+{
+  const int NT = H / 16, S = H / 32;
+  const int64_t nf = (int64_t)(layers - 1) * NT * S * 2 * 64;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nf) return;
+  int64_t f = t;
+  const int lane = (int)(f % 64);
+  f /= 64;
+  const int part = (int)(f % 2);
+  f /= 2;
+  const int s = (int)(f % S);
+  f /= S;
+  const int mo = (int)(f % NT);
+  const int l = 1 + (int)(f / NT);
+  const float* W = par + 4 * (int64_t)H + (int64_t)(l - 1) * (H * H + H);   // [H][H], input-major
+  const int i = lane & 15, g = lane >> 4;
+  bf16x8 v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int kin = 32 * s + 16 * (e >> 2) + 4 * g + (e & 3);
+    const float w = W[(int64_t)kin * H + 16 * mo + i];
+    const __bf16 hi = (__bf16)w;
+    v[e] = part ? (__bf16)(w - (float)hi) : hi;
+  }
+  frag[t] = v;
+}
+
+// SiLU and its derivative times the tangent, FP32: reciprocal from the hardware estimate and
+// one Newton step; the exponent is capped so that 1 + e^-z stays finite.
+__device__ inline void silu_tangent_f32(float z, float zt, float& h, float& t)
+{
+  const float d = 1.0f + __expf(fminf(-z, 80.0f));
+  float s = __builtin_amdgcn_rcpf(d);
+  s = fmaf(s, fmaf(-d, s, 1.0f), s);
+  h = z * s;
+  t = s * (1.0f + z * (1.0f - s)) * zt;
+}
+
+template <int NT, bool SPLIT>
+__global__ __launch_bounds__(256) void mlp_bf16_kernel(const double* __restrict__ U, int64_t n,
+                                                       const float* __restrict__ par,
+                                                       const bf16x8* __restrict__ frag, int layers,
+                                                       double* __restrict__ Y, double* __restrict__ dY)
+{
+  constexpr int H = 16 * NT, S = H / 32;
+  constexpr int NF = NT * S * 2 * 64;   // fragments of one layer (a multiple of 256)
+  __shared__ bf16x8 wl[NF];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int64_t r = ((int64_t)blockIdx.x * 4 + wave) * 16 + j;
+  const bool valid = r < n;
+  float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
+  if (valid) {
+    u0 = (float)U[3 * r];
+    u1 = (float)U[3 * r + 1];
+    u2 = (float)U[3 * r + 2];
+  }
+  float av[NT][4], at[NT][4];
+  {
+    const float* W = par;           // [3][H]
+    const float* b = par + 3 * H;   // [H]
+#pragma unroll
+    for (int m = 0; m < NT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int u = 16 * m + 4 * g + v;
+        const float z = fmaf(W[2 * H + u], u2, fmaf(W[H + u], u1, fmaf(W[u], u0, b[u])));
+        silu_tangent_f32(z, W[2 * H + u], av[m][v], at[m][v]);
+      }
+  }
+  int64_t off = 4 * H;
+  for (int l = 1; l < layers; ++l) {
+    const float* b = par + off + H * H;
+    const bf16x8* F = frag + (int64_t)(l - 1) * NF;
+    __syncthreads();   // every wavefront is done with the previous layer's fragments
+    // direct global -> LDS copies: a wavefront fills 1 KiB at its wave-uniform base, lane i at base + 16 i
+#pragma unroll
+    for (int c = 0; c < NF / 256; ++c)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(F + 256 * c + threadIdx.x),
+                                       (__attribute__((address_space(3))) void*)(wl + 256 * c + 64 * wave), 16, 0, 0);
+    // meanwhile the B operands of every K step: this lane's activations in the permuted order
+    bf16x8 bvh[S], bvl[S], bth[S], btl[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = av[2 * s + (e >> 2)][e & 3], y = at[2 * s + (e >> 2)][e & 3];
+        const __bf16 xh = (__bf16)x, yh = (__bf16)y;
+        bvh[s][e] = xh;
+        bth[s][e] = yh;
+        if constexpr (SPLIT) {
+          bvl[s][e] = (__bf16)(x - (float)xh);
+          btl[s][e] = (__bf16)(y - (float)yh);
+        }
+      }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+#pragma unroll
+    for (int mo = 0; mo < NT; ++mo) {
+      flt4 cv = {0.0f, 0.0f, 0.0f, 0.0f}, ct = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const bf16x8 ah = wl[((mo * S + s) * 2) * 64 + lane];
+        cv = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bvh[s], cv, 0, 0, 0);
+        ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bth[s], ct, 0, 0, 0);
+        if constexpr (SPLIT) {
+          const bf16x8 al = wl[((mo * S + s) * 2 + 1) * 64 + lane];
+          cv = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bvh[s], cv, 0, 0, 0);
+          cv = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bvl[s], cv, 0, 0, 0);
+          ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bth[s], ct, 0, 0, 0);
+          ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, btl[s], ct, 0, 0, 0);
+        }
+      }
+      // the B operands hold this layer's inputs: the outputs may overwrite av, at
+#pragma unroll
+      for (int v = 0; v < 4; ++v) silu_tangent_f32(cv[v] + b[16 * mo + 4 * g + v], ct[v], av[mo][v], at[mo][v]);
+    }
+    off += (int64_t)H * H + H;
+  }
+  const float* W = par + off;   // [H][2]
+  const float* b = W + 2 * H;
+  float y0 = 0.0f, y1 = 0.0f, t0 = 0.0f, t1 = 0.0f;
+#pragma unroll
+  for (int m = 0; m < NT; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int u = 16 * m + 4 * g + v;
+      y0 = fmaf(W[2 * u], av[m][v], y0);
+      y1 = fmaf(W[2 * u + 1], av[m][v], y1);
+      t0 = fmaf(W[2 * u], at[m][v], t0);
+      t1 = fmaf(W[2 * u + 1], at[m][v], t1);
+    }
+  y0 += __shfl_xor(y0, 16);
+  y1 += __shfl_xor(y1, 16);
+  t0 += __shfl_xor(t0, 16);
+  t1 += __shfl_xor(t1, 16);
+  y0 += __shfl_xor(y0, 32);
+  y1 += __shfl_xor(y1, 32);
+  t0 += __shfl_xor(t0, 32);
+  t1 += __shfl_xor(t1, 32);
+  if (g == 0 && valid) {
+    Y[2 * r] = (double)(y0 + b[0]);
+    Y[2 * r + 1] = (double)(y1 + b[1]);
+    dY[2 * r] = (double)t0;
+    dY[2 * r + 1] = (double)t1;
+  }
+}
+
+template <bool SPLIT>
+static hipError_t mlp_bf16_launch(const sft_surrogate* s, const double* U, int64_t n, double* Y, double* dY,
+                                  hipStream_t st)
+{
+  const dim3 grid((unsigned)((n + 63) / 64)), block(256);
+  const int L = s->d.layers;
+  const bf16x8* F = (const bf16x8*)s->frag;
+  switch (s->d.hidden / 32) {
+  case 1: hipLaunchKernelGGL((mlp_bf16_kernel<2, SPLIT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
+  case 2: hipLaunchKernelGGL((mlp_bf16_kernel<4, SPLIT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
+  case 3: hipLaunchKernelGGL((mlp_bf16_kernel<6, SPLIT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
+  default: hipLaunchKernelGGL((mlp_bf16_kernel<8, SPLIT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
+  }
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------- inference
 size_t mlp_infer_scratch_bytes(int hidden, int64_t chunk)
 {
@@ -420,6 +608,8 @@ hipError_t mlp_infer(const sft_surrogate* s, const double* U, int64_t n, double*
                      int64_t chunk, hipStream_t st)
 {
   const int H = s->d.hidden, L = s->d.layers;
+  if (s->d.inference == SFT_INFER_BF16X3) return n > 0 ? mlp_bf16_launch<true>(s, U, n, Y, dY, st) : hipSuccess;
+  if (s->d.inference == SFT_INFER_BF16) return n > 0 ? mlp_bf16_launch<false>(s, U, n, Y, dY, st) : hipSuccess;
   if (mlp_fused_ok(H)) return n > 0 ? mlp_fused(s, U, n, Y, dY, st) : hipSuccess;
   double* b0 = (double*)scratch;
   double* b1 = b0 + (size_t)(2 * chunk) * std::max(H, 3);
@@ -566,7 +756,12 @@ __global__ void inference_copy_kernel(const float* __restrict__ p, double* __res
 static hipError_t refresh_inference_copy(sft_surrogate* s, hipStream_t st)
 {
   hipLaunchKernelGGL(inference_copy_kernel, dim3(nblk(s->P)), dim3(256), 0, st, s->par, s->par_inf, s->P,
-                     s->d.weights_bf16);
+                     s->d.inference == SFT_INFER_FP64_BF16W ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !s->frag) return e;
+  const int64_t nf = (int64_t)(s->d.layers - 1) * bf16_frags_per_layer(s->d.hidden);
+  hipLaunchKernelGGL(pack_bf16_kernel, dim3(nblk(nf)), dim3(256), 0, st, s->par, s->d.hidden, s->d.layers,
+                     (bf16x8*)s->frag);
   return hipGetLastError();
 }
 
@@ -584,6 +779,7 @@ extern "C" void sft_surrogate_free(sft_surrogate* s)
   if (s->mom1) (void)hipFree(s->mom1);
   if (s->mom2) (void)hipFree(s->mom2);
   if (s->par_inf) (void)hipFree(s->par_inf);
+  if (s->frag) (void)hipFree(s->frag);
   delete s;
 }
 
@@ -596,6 +792,11 @@ extern "C" sft_status sft_surrogate_create(const sft_surrogate_desc* d, const fl
   if (!(d->mc_hi > d->mc_lo) || !(d->q_hi > d->q_lo) || !(d->lt_hi > d->lt_lo) || !(d->c_phi != 0.0) ||
       !(d->c_amp != 0.0) || !(d->judge_tol >= 0.0))
     return mlp_fail(SFT_E_INVALID, "sft_surrogate_create: bad ranges or scales");
+  if (d->inference < SFT_INFER_FP64 || d->inference > SFT_INFER_BF16)
+    return mlp_fail(SFT_E_INVALID, "sft_surrogate_create: unknown inference mode");
+  const bool bf16 = d->inference == SFT_INFER_BF16X3 || d->inference == SFT_INFER_BF16;
+  if (bf16 && !mlp_bf16_ok(d->hidden))
+    return mlp_fail(SFT_E_UNSUPPORTED, "sft_surrogate_create: BF16 inference needs hidden = 32, 64, 96 or 128");
   sft_surrogate* s = new sft_surrogate();
   std::memset(s, 0, sizeof(*s));
   s->d = *d;
@@ -606,6 +807,8 @@ extern "C" sft_status sft_surrogate_create(const sft_surrogate_desc* d, const fl
   if (e == hipSuccess) e = hipMalloc(&s->mom1, s->P * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&s->mom2, s->P * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&s->par_inf, s->P * sizeof(double));
+  if (e == hipSuccess && bf16 && d->layers > 1)
+    e = hipMalloc(&s->frag, (size_t)(d->layers - 1) * bf16_frags_per_layer(d->hidden) * sizeof(bf16x8));
   if (e == hipSuccess) e = hipMemcpy(s->par, params, s->P * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(s->grad, 0, s->P * sizeof(float));
   if (e == hipSuccess) e = hipMemset(s->mom1, 0, s->P * sizeof(float));

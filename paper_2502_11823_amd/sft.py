@@ -61,7 +61,7 @@ class Out(ctypes.Structure):
 
 class SurrogateDesc(ctypes.Structure):
     _fields_ = [("hidden", ctypes.c_int32), ("layers", ctypes.c_int32), ("head", ctypes.c_int32),
-                ("weights_bf16", ctypes.c_int32), ("mc_lo", ctypes.c_double), ("mc_hi", ctypes.c_double),
+                ("inference", ctypes.c_int32), ("mc_lo", ctypes.c_double), ("mc_hi", ctypes.c_double),
                 ("q_lo", ctypes.c_double), ("q_hi", ctypes.c_double), ("lt_lo", ctypes.c_double),
                 ("lt_hi", ctypes.c_double), ("c_phi", ctypes.c_double), ("c_amp", ctypes.c_double),
                 ("judge_tol", ctypes.c_double)]
@@ -495,16 +495,22 @@ def surrogate_param_count(hidden: int, layers: int) -> int:
     return int(lib().sft_surrogate_param_count(int(hidden), int(layers)))
 
 
+INFERENCE = {"fp64": 0, "fp64_bf16w": 1, "bf16x3": 2, "bf16": 3}
+
+
 class Surrogate:
     """The learned-surrogate network (owns an sft_surrogate handle on the current device).
 
     params: FP32 values (any float array) packed layer by layer, W [n_in][n_out] then b.
     Ranges: mc, q and ln(tau) of the input normalisation; c_phi, c_amp output scales;
-    head = 1 adds the analytic 1PN + 1.5PN phase; judge_tol the mismatch tolerance."""
+    head = 1 adds the analytic 1PN + 1.5PN phase; judge_tol the mismatch tolerance.
+    inference: "fp64", "fp64_bf16w" (FP64 evaluation of BF16-rounded weights), "bf16x3"
+    (BF16 matrix cores with split operands) or "bf16"; weights_bf16 = 1 is "fp64_bf16w"."""
 
     def __init__(self, params, hidden=128, layers=4, head=1, weights_bf16=0, mc=(1.19, 1.21), q=(1.0, 2.0),
-                 ln_tau=(6.39, 9.74), c_phi=1.0, c_amp=1.0, judge_tol=1e-4):
-        self.desc = SurrogateDesc(int(hidden), int(layers), int(head), int(weights_bf16), float(mc[0]),
+                 ln_tau=(6.39, 9.74), c_phi=1.0, c_amp=1.0, judge_tol=1e-4, inference=None):
+        mode = INFERENCE[inference] if inference is not None else (1 if weights_bf16 else 0)
+        self.desc = SurrogateDesc(int(hidden), int(layers), int(head), mode, float(mc[0]),
                                   float(mc[1]), float(q[0]), float(q[1]), float(ln_tau[0]), float(ln_tau[1]),
                                   float(c_phi), float(c_amp), float(judge_tol))
         self.P = surrogate_param_count(hidden, layers)
@@ -551,7 +557,8 @@ class Surrogate:
         return buf
 
     def infer(self, u64, stream=None):
-        """The scan's FP64 network evaluation: u [n][3] -> y [n][2], dy/du_tau [n][2] (device)."""
+        """The scan's network evaluation (in the handle's inference mode): u [n][3] -> y [n][2],
+        dy/du_tau [n][2] (device, FP64)."""
         import torch
         n = int(u64.shape[0])
         y = torch.empty((n, 2), dtype=torch.float64, device=u64.device)

@@ -77,10 +77,11 @@ def test_surrogate_host_validation(orc):
     assert sft.surrogate_param_count(0, 4) == 0
     h = ctypes.c_void_p()
     par = (ctypes.c_float * 16)()
-    good = dict(hidden=32, layers=2, head=1, weights_bf16=0, mc_lo=1.0, mc_hi=2.0, q_lo=1.0, q_hi=2.0,
+    good = dict(hidden=32, layers=2, head=1, inference=0, mc_lo=1.0, mc_hi=2.0, q_lo=1.0, q_hi=2.0,
                 lt_lo=6.0, lt_hi=9.0, c_phi=1.0, c_amp=0.01, judge_tol=1e-4)
     for bad, code in [(dict(hidden=4), -4), (dict(layers=9), -4), (dict(mc_hi=1.0), -1),
-                      (dict(lt_hi=5.0), -1), (dict(c_phi=0.0), -1), (dict(judge_tol=-1.0), -1)]:
+                      (dict(lt_hi=5.0), -1), (dict(c_phi=0.0), -1), (dict(judge_tol=-1.0), -1),
+                      (dict(inference=7), -1), (dict(inference=2, hidden=48), -5), (dict(inference=3, hidden=256), -5)]:
         d = sft.SurrogateDesc(**dict(good, **bad))
         assert L.sft_surrogate_create(ctypes.byref(d), par, ctypes.byref(h)) == code, bad
         assert sft.last_error().startswith("sft_surrogate_create")

@@ -35,11 +35,11 @@ CFG = dict(mc_lo=1.19, mc_hi=1.21, q_lo=1.0, q_hi=2.0, lt_lo=float(np.log(600.0)
            c_phi=2.0, c_amp=0.01, head=1)
 
 
-def make_surrogate(params, hidden, layers, tol=1e-4, bf16=0, cfg=CFG):
+def make_surrogate(params, hidden, layers, tol=1e-4, bf16=0, cfg=CFG, inference=None):
     return sft.Surrogate(params, hidden=hidden, layers=layers, head=cfg["head"], weights_bf16=bf16,
                          mc=(cfg["mc_lo"], cfg["mc_hi"]), q=(cfg["q_lo"], cfg["q_hi"]),
                          ln_tau=(cfg["lt_lo"], cfg["lt_hi"]), c_phi=cfg["c_phi"], c_amp=cfg["c_amp"],
-                         judge_tol=tol)
+                         judge_tol=tol, inference=inference)
 
 
 def bf16_round(x):
@@ -73,6 +73,65 @@ def test_fp64_inference_matches_oracle_forward(hidden, layers, n, bf16):
     if bf16:   # the BF16 network is a different function: its distance is reported, not hidden
         yf, _ = oracle.mlp_forward(par, u, hidden, layers)
         print("  BF16 vs FP32 parameters: max |dy| = %.2e" % np.max(np.abs(yf - yo)))
+    s.close()
+
+
+@pytest.mark.parametrize("hidden,layers,n", [(32, 2, 1000), (64, 3, 70000), (96, 2, 4097), (128, 4, 70000),
+                                             (128, 1, 333)])
+def test_bf16_matrix_core_inference_error_against_fp64(hidden, layers, n):
+    """The network on the BF16 matrix cores (FP32 accumulation and activations) against the
+    FP64 oracle's forward pass, values and tangents; the error is reported and bounded.
+    bf16x3 (split operands): a product is within 3 * 2^-16 of exact relative to |w||x| (hi
+    rounding 2^-8, the lo rounding 2^-8 of that, the dropped lo.lo term 2^-16); with a growth
+    margin of 4 per layer the outputs stay within (L + 1) * 12 * 2^-16 of max |y|.  bf16 (one
+    product of rounded operands): 2 * 2^-8 per product, bound (L + 1) * 8 * 2^-8."""
+    par = synth.mlp_init(7, hidden, layers)
+    u = synth.rng(11).uniform(-1.0, 1.0, (n, 3))
+    yo, dyo = oracle.mlp_forward(par, u, hidden, layers)
+    for mode, per_layer in (("bf16x3", 12 * 2.0**-16), ("bf16", 8 * 2.0**-8)):
+        s = make_surrogate(par, hidden, layers, inference=mode)
+        y, dy = s.infer(dev(u))
+        torch.cuda.synchronize()
+        ey = np.max(np.abs(y.cpu().numpy() - yo)) / np.max(np.abs(yo))
+        ed = np.max(np.abs(dy.cpu().numpy() - dyo)) / np.max(np.abs(dyo))
+        print("infer %s h=%d l=%d n=%d: max rel err y %.2e dy %.2e (bound %.1e)"
+              % (mode, hidden, layers, n, ey, ed, (layers + 1) * per_layer))
+        assert ey < (layers + 1) * per_layer and ed < (layers + 1) * per_layer
+        assert np.all(np.isfinite(y.cpu().numpy()))
+        s.close()
+
+
+def test_surrogate_scan_with_bf16x3_network(tiny_q):
+    """The bank scan with the network on the BF16 matrix cores (split operands) against the
+    FP64 oracle, whose network is FP64.  The network error dy (~1e-5) moves the surrogate phase
+    by c_phi Theta_N^p dy1 (~3e-4 rad here): the inner products differ at that level (reported,
+    bound 1e-2 in noise units), the FP64 judge sees mismatches within 1e-3 of the oracle's, and
+    the fallback decisions agree for every template farther than that from the tolerance."""
+    w, bank = tiny_q
+    hidden, layers = 128, 4
+    par = synth.mlp_init(13, hidden, layers)
+    cfg = dict(CFG, judge_tol=2.0)
+    oracle.set_surrogate(par, cfg, hidden, layers)
+    kw = dict(K=4, kernel="dirichlet", waveform="surrogate")
+    o0 = orc_scan(w, bank, **kw)
+    tol = _judge_split(o0["mismatch"])
+    cfg["judge_tol"] = tol
+    oracle.set_surrogate(par, cfg, hidden, layers)
+    o = orc_scan(w, bank, **kw)
+    s = make_surrogate(par, hidden, layers, tol=tol, inference="bf16x3")
+    data = sft.SFTData.from_workload(w, storage="f32")
+    g = gpu_scan(data, bank, mismatch=True, precision="fp32_kahan", surrogate=s, **kw)
+    dm = np.abs(g["mismatch"] - o["mismatch"])
+    far = np.abs(o["mismatch"] - tol) > 1e-3
+    fb_g = (g["flags"] & oracle.F_SURROGATE_FALLBACK) > 0
+    fb_o = (o["flags"] & oracle.F_SURROGATE_FALLBACK) > 0
+    hh = np.sqrt(o["hhp"])
+    ez = np.abs(g["zp"] - o["zp"]) / np.maximum(np.abs(o["zp"]), hh)
+    print("bf16x3 network scan: max |dmismatch| %.2e, fallbacks %d (oracle %d), e(z+) max %.2e median %.2e"
+          % (dm.max(), fb_g.sum(), fb_o.sum(), ez.max(), np.median(ez)))
+    assert dm.max() < 1e-3
+    assert np.array_equal(fb_g[far], fb_o[far])
+    assert ez.max() < 1e-2
     s.close()
 
 
