@@ -502,13 +502,16 @@ sft_status sft_surrogate_loss_grad(sft_surrogate* s, const float* u, const float
 sft_status sft_surrogate_adam(sft_surrogate* s, float lr, void* hip_stream);
 
 /*
- * sft_surrogate_train -- epochs of mini-batch Adam over device u [n][3], y [n][2] in order
- * (batches of `batch` consecutive rows, the last partial batch dropped; shuffle between
- * calls if wanted), learning rate on a cosine schedule from lr to lr_min over the call.
+ * sft_surrogate_train -- epochs of mini-batch Adam over device u [n][3], y [n][2], the rows
+ * shuffled afresh every epoch: epoch e visits the rows in the order of a keyed bijection of
+ * [0, n) (a four-round Feistel network on the indices with cycle walking, keyed by e and the
+ * network's Adam step count; deterministic), in batches of `batch` rows, n mod batch rows left
+ * out per epoch; learning rate on a cosine schedule from lr to lr_min over the call.  The
+ * GEMMs of the forward and backward passes run on the FP32 matrix cores.
  * epoch_loss (host [epochs], may be NULL) receives the mean batch loss of each epoch.
  * Synchronises hip_stream; refreshes the inference copy of the parameters.
- * Errors: SFT_E_INVALID, SFT_E_RANGE (batch outside [16, min(n, 2^20)], epochs < 1),
- * SFT_E_NOMEM, SFT_E_DEVICE.
+ * Errors: SFT_E_INVALID, SFT_E_RANGE (batch outside [16, min(n, 2^20)], epochs < 1,
+ * n > 2^31), SFT_E_NOMEM, SFT_E_DEVICE.
  */
 sft_status sft_surrogate_train(sft_surrogate* s, const float* u, const float* y, int64_t n, int32_t batch,
                                int32_t epochs, float lr, float lr_min, void* hip_stream, float* epoch_loss);

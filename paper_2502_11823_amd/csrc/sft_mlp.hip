@@ -1,13 +1,13 @@
 // sft_mlp.hip -- the learned surrogate's network on gfx950: training (FP32 forward,
-// backward, Adam) and inference (FP64 forward with the forward-mode derivative along
-// the ln(tau) input), built from one tiled GEMM kernel and small element-wise kernels.
+// backward, Adam, epoch shuffling) and inference (forward pass with the forward-mode
+// derivative along the ln(tau) input: fused FP64 or BF16 matrix-core kernels, or a
+// layer-by-layer path), built from tiled GEMM kernels and small element-wise kernels.
 //
 // GEMM: C[M][N] = op(A)[M][K] op(B)[K][N] for a 64 x 64 tile per 256-thread workgroup,
-// 4 x 4 outputs per thread, K staged through LDS in steps of 16 (vector FMA: FP64 has
-// the same dense peak on the vector units as on the matrix cores of gfx950, and the
-// FP32 training GEMMs are a small, off-scan cost); a grid z-dimension
-// splits K into slices written to separate C planes (summed by a reduction kernel),
-// which gives the weight gradients (K = batch) enough workgroups.
+// K staged through LDS in steps of 16; FP32 (training) on the matrix cores, FP64 (the
+// layer-by-layer inference of odd widths) with 4 x 4 vector FMAs per thread.  A grid
+// z-dimension splits K into slices written to separate C planes (summed by a reduction
+// kernel), which gives the weight gradients (K = batch) enough workgroups.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -106,7 +106,89 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const T*
   }
 }
 
-// C = op(A) op(B) with k split into `splits` planes of C (plane stride c_plane)
+// FP32 GEMM on the matrix cores (v_mfma_f32_16x16x4f32): the same tile, staging and K slices
+// as gemm_kernel, each wavefront computing a 32 x 32 quarter of the 64 x 64 tile as 2 x 2
+// blocks of 16 x 16.  Operand layouts (checked with an in-bounds probe): A[i][k] in lane
+// i + 16 k, B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i / 4), element i % 4.
+typedef float flt4m __attribute__((ext_vector_type(4)));
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                        const float* __restrict__ B, int ldb, float* __restrict__ C,
+                                                        int ldc, int k_slice, int64_t c_plane)
+{
+  __shared__ float As[16][64 + 4];
+  __shared__ float Bs[16][64 + 4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wi = 32 * (wave >> 1), wj = 32 * (wave & 1);   // the wavefront's quarter of the tile
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int kb = blockIdx.z * k_slice;
+  const int ke = min(K, kb + k_slice);
+  flt4m acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = flt4m{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      int ii, kk;
+      if (TA) { ii = e & 63; kk = e >> 6; } else { ii = e >> 4; kk = e & 15; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      float v = 0.0f;
+      if (gi < M && gk < ke) v = TA ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk];
+      As[kk][ii] = v;
+    }
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      int jj, kk;
+      if (TB) { jj = e >> 4; kk = e & 15; } else { jj = e & 63; kk = e >> 6; }
+      const int gj = j0 + jj, gk = k0 + kk;
+      float v = 0.0f;
+      if (gj < N && gk < ke) v = TB ? B[(int64_t)gj * ldb + gk] : B[(int64_t)gk * ldb + gj];
+      Bs[kk][jj] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+      const float a0 = As[k4 + lk][wi + li], a1 = As[k4 + lk][wi + 16 + li];
+      const float b0 = Bs[k4 + lk][wj + li], b1 = Bs[k4 + lk][wj + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float* Cp = C + (int64_t)blockIdx.z * c_plane;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int gj = j0 + wj + 16 * b + li;
+      if (gj >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + wi + 16 * a + 4 * lk + v;
+        if (gi < M) Cp[(int64_t)gi * ldc + gj] = acc[a][b][v];
+      }
+    }
+}
+
+// C = op(A) op(B) with k split into `splits` planes of C (plane stride c_plane); FP32 on the
+// matrix cores, FP64 on the vector units
+static hipError_t gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb,
+                       float* C, int ldc, int splits, int64_t c_plane, hipStream_t st)
+{
+  const int k_slice = ((K + splits - 1) / splits + 15) / 16 * 16;
+  const int z = (K + k_slice - 1) / k_slice;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, z);
+  if (!ta && !tb) hipLaunchKernelGGL((gemm_mfma_kernel<false, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, k_slice, c_plane);
+  else if (ta && !tb) hipLaunchKernelGGL((gemm_mfma_kernel<true, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, k_slice, c_plane);
+  else if (!ta && tb) hipLaunchKernelGGL((gemm_mfma_kernel<false, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, k_slice, c_plane);
+  else hipLaunchKernelGGL((gemm_mfma_kernel<true, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, k_slice, c_plane);
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t gemm(bool ta, bool tb, int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
                        int splits, int64_t c_plane, hipStream_t st)
@@ -684,7 +766,7 @@ static hipError_t loss_grad(sft_surrogate* s, const float* U, const float* Tg, i
   for (int l = 0; l <= L; ++l) {
     const MlpLayer ly = mlp_layer(H, L, l);
     float* Z = t.Z + (size_t)l * B * H;
-    if ((e = gemm<float>(false, false, (int)B, ly.n_out, ly.n_in, hin, ly.n_in, s->par + ly.w_off, ly.n_out, Z,
+    if ((e = gemm(false, false, (int)B, ly.n_out, ly.n_in, hin, ly.n_in, s->par + ly.w_off, ly.n_out, Z,
                          ly.n_out, 1, 0, st)) != hipSuccess)
       return e;
     if (l < L) {
@@ -712,7 +794,7 @@ static hipError_t loss_grad(sft_surrogate* s, const float* U, const float* Tg, i
     }
     // dW = Hl^T G  (K = B, split into planes), db = column sums of G
     const int planes = gemm_planes((int)B, t.splits);
-    if ((e = gemm<float>(true, false, ly.n_in, ly.n_out, (int)B, Hl, ly.n_in, G, ly.n_out, t.plane, ly.n_out,
+    if ((e = gemm(true, false, ly.n_in, ly.n_out, (int)B, Hl, ly.n_in, G, ly.n_out, t.plane, ly.n_out,
                          t.splits, (int64_t)ly.n_in * ly.n_out, st)) != hipSuccess)
       return e;
     hipLaunchKernelGGL(sum_planes_kernel, dim3(nblk((int64_t)ly.n_in * ly.n_out)), dim3(256), 0, st, t.plane, planes,
@@ -721,13 +803,60 @@ static hipError_t loss_grad(sft_surrogate* s, const float* U, const float* Tg, i
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (l > 0) {
       // G_prev = G W^T
-      if ((e = gemm<float>(false, true, (int)B, ly.n_in, ly.n_out, G, ly.n_out, s->par + ly.w_off, ly.n_out, Gn,
+      if ((e = gemm(false, true, (int)B, ly.n_in, ly.n_out, G, ly.n_out, s->par + ly.w_off, ly.n_out, Gn,
                            ly.n_in, 1, 0, st)) != hipSuccess)
         return e;
       std::swap(G, Gn);
     }
   }
   return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------- epoch shuffling
+// A keyed bijection of [0, 2^(2h)): a four-round Feistel network on the two h-bit halves with
+// the 32-bit integer hash "lowbias32" (C. Wellons' published finaliser) as round function.
+// Cycle walking (apply again while the image is >= n) restricts it to a bijection of [0, n);
+// with 2^(2h) < 4 n a walk takes fewer than 4 steps on average and always ends, since the
+// cycle through x < n returns to x.
+__device__ inline uint32_t hash32(uint32_t x)
+{
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ inline uint32_t feistel(uint32_t x, int h, uint32_t key)
+{
+  const uint32_t mask = (1u << h) - 1u;
+  uint32_t L = x >> h, R = x & mask;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t t = L ^ (hash32(R ^ (key + 0x9e3779b9u * (uint32_t)(r + 1))) & mask);
+    L = R;
+    R = t;
+  }
+  return (L << h) | R;
+}
+
+// the rows first .. first + B - 1 of the shuffled order, copied into the batch buffers
+__global__ __launch_bounds__(256) void gather_batch_kernel(const float* __restrict__ u, const float* __restrict__ y,
+                                                           uint32_t n, int64_t first, int64_t B, int h, uint32_t key,
+                                                           float* __restrict__ ub, float* __restrict__ yb)
+{
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= B) return;
+  uint32_t x = (uint32_t)(first + r);
+  do {
+    x = feistel(x, h, key);
+  } while (x >= n);
+  ub[3 * r] = u[3 * (int64_t)x];
+  ub[3 * r + 1] = u[3 * (int64_t)x + 1];
+  ub[3 * r + 2] = u[3 * (int64_t)x + 2];
+  yb[2 * r] = y[2 * (int64_t)x];
+  yb[2 * r + 1] = y[2 * (int64_t)x + 1];
 }
 
 // ---------------------------------------------------------------------------- C ABI
@@ -836,7 +965,7 @@ extern "C" sft_status sft_surrogate_loss_grad(sft_surrogate* s, const float* u, 
   if (!s || !u || !y || !loss) return mlp_fail(SFT_E_INVALID, "sft_surrogate_loss_grad: null argument");
   if (n < 1 || n > (1 << 21)) return mlp_fail(SFT_E_RANGE, "sft_surrogate_loss_grad: n outside [1, 2^21]");
   hipStream_t st = (hipStream_t)hip_stream;
-  const int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, n / 256));
+  const int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, n / 64));
   void* ws = nullptr;
   hipError_t e = hipMallocAsync(&ws, train_bytes(s->d.hidden, s->d.layers, n, splits), st);
   if (e != hipSuccess) return mlp_fail(SFT_E_NOMEM, "sft_surrogate_loss_grad", e);
@@ -867,26 +996,35 @@ extern "C" sft_status sft_surrogate_train(sft_surrogate* s, const float* u, cons
                                           int32_t epochs, float lr, float lr_min, void* hip_stream, float* epoch_loss)
 {
   if (!s || !u || !y) return mlp_fail(SFT_E_INVALID, "sft_surrogate_train: null argument");
-  if (batch < 16 || batch > (1 << 20) || n < batch || epochs < 1)
-    return mlp_fail(SFT_E_RANGE, "sft_surrogate_train: need 16 <= batch <= n and epochs >= 1");
+  if (batch < 16 || batch > (1 << 20) || n < batch || epochs < 1 || n > ((int64_t)1 << 31))
+    return mlp_fail(SFT_E_RANGE, "sft_surrogate_train: need 16 <= batch <= n <= 2^31 and epochs >= 1");
   hipStream_t st = (hipStream_t)hip_stream;
-  const int splits = std::min(64, std::max(1, batch / 256));
+  const int splits = std::min(64, std::max(1, batch / 64));   // K slices of the weight-gradient GEMMs
   const int64_t steps = n / batch;
+  int h = 1;   // half width of the shuffling bijection: 2^(2h) >= n
+  while (((int64_t)1 << (2 * h)) < n) ++h;
+  const size_t tb = train_bytes(s->d.hidden, s->d.layers, batch, splits);
   void* ws = nullptr;
   float* dloss = nullptr;
-  hipError_t e = hipMallocAsync(&ws, train_bytes(s->d.hidden, s->d.layers, batch, splits) + steps * sizeof(float), st);
+  hipError_t e = hipMallocAsync(&ws, tb + steps * sizeof(float) + (size_t)batch * 5 * sizeof(float) + 256, st);
   if (e != hipSuccess) return mlp_fail(SFT_E_NOMEM, "sft_surrogate_train", e);
   TrainBuf t;
   train_layout(ws, s->d.hidden, s->d.layers, batch, splits, t);
-  dloss = (float*)((char*)ws + train_bytes(s->d.hidden, s->d.layers, batch, splits));
+  dloss = (float*)((char*)ws + tb);
+  float* ub = (float*)((char*)ws + (tb + steps * sizeof(float) + 255) / 256 * 256);   // [batch][3]
+  float* yb = ub + (size_t)batch * 3;                                                  // [batch][2]
   std::vector<float> hl(steps);
   const double total = (double)epochs * steps;
   int64_t it = 0;
   for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+    const uint32_t key = 0x243f6a88u * (uint32_t)(ep + 1) ^ (uint32_t)s->step * 0x85a308d3u;
     for (int64_t k = 0; k < steps && e == hipSuccess; ++k, ++it) {
       // cosine learning-rate schedule from lr to lr_min
       const float lrt = lr_min + 0.5f * (lr - lr_min) * (1.0f + (float)cos(M_PI * (double)it / total));
-      e = loss_grad(s, u + k * batch * 3, y + k * batch * 2, batch, dloss + k, t, st);
+      hipLaunchKernelGGL(gather_batch_kernel, dim3(nblk(batch)), dim3(256), 0, st, u, y, (uint32_t)n, k * batch,
+                         (int64_t)batch, h, key, ub, yb);
+      if ((e = hipGetLastError()) != hipSuccess) break;
+      e = loss_grad(s, ub, yb, batch, dloss + k, t, st);
       if (e != hipSuccess) break;
       s->step += 1;
       const float c1 = 1.0f - powf(0.9f, (float)s->step), c2 = 1.0f - powf(0.999f, (float)s->step);

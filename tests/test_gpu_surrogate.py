@@ -233,6 +233,30 @@ def test_training_reduces_loss():
     s.close()
 
 
+def test_training_epoch_visits_every_row_once():
+    """The shuffled order of an epoch is a bijection of the rows: with lr = 0 the parameters stay
+    put, so when batch divides n the epoch's mean batch loss equals the loss over all rows (each
+    batch has the same size), for any order.  The targets carry a few rows 1e3 times larger, so a
+    row visited twice or missed moves the mean far beyond FP32 rounding."""
+    hidden, layers = 32, 2
+    n, batch = 1 << 14, 512
+    g = synth.rng(44)
+    u = dev(g.uniform(-1.0, 1.0, (n, 3)), torch.float32)
+    yh = g.normal(size=(n, 2))
+    yh[g.choice(n, 7, replace=False)] *= 1e3
+    y = dev(yh, torch.float32)
+    s = make_surrogate(synth.mlp_init(5, hidden, layers), hidden, layers)
+    full, _ = s.loss_grad(u, y)
+    hist = s.train(u, y, batch=batch, epochs=2, lr=0.0, lr_min=0.0)
+    full = float(full.cpu().numpy()[0])
+    print("epoch losses %s, full-data loss %.7e" % (hist, full))
+    assert np.allclose(hist, full, rtol=1e-5, atol=0)
+    # one batch of half the rows: its loss is not the full-data loss (the check above has teeth)
+    half = s.train(u, y, batch=n // 2 + 1, epochs=1, lr=0.0, lr_min=0.0)
+    assert not np.allclose(half, full, rtol=1e-3)
+    s.close()
+
+
 # ----------------------------------------------------------------------------- surrogate scan
 @pytest.fixture(scope="module")
 def tiny_q():
