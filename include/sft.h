@@ -50,7 +50,9 @@ enum { SFT_STORE_F64 = 0, SFT_STORE_F32 = 1, SFT_STORE_BF16 = 2 };
 /* kernel choice (Sec. III.C, App. B) */
 enum { SFT_KERNEL_DIRICHLET = 0, SFT_KERNEL_FRESNEL = 1, SFT_KERNEL_AUTO = 2 };
 /* arithmetic of the bin contraction and of the sums over SFTs; the waveform
- * phase, its reduction mod 2 pi and the bin split are FP64 in every mode */
+ * phase, its reduction mod 2 pi and the bin split are FP64 in every mode.  FP64 forms the
+ * Fresnel weights from FP64 Fresnel integrals (power series, continued fraction of erfcx;
+ * ~1e-15) bin by bin: a reference mode, much slower than the FP32 modes with Fresnel. */
 enum { SFT_PREC_FP64 = 0, SFT_PREC_FP32_KAHAN = 1, SFT_PREC_FP32_NAIVE = 2 };
 /* waveform model: leading-order (Newtonian) chirp, the 3.5PN closed-form inspiral, or
  * the learned surrogate (opts.surrogate) with the 3.5PN waveform as judge and fallback.

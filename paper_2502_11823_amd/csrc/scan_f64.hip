@@ -3,11 +3,11 @@
 
 using namespace sftk;
 
-ScanFn scan_pick_f64(int wf, int K, int nd)
+ScanFn scan_pick_f64(int wf, int kern, int K, int nd)
 {
   switch (wf) {
-  case WF_PN35: return pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_PN35>(K, nd);
-  case WF_TABLE: return pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_TABLE>(K, nd);
-  default: return pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_NEWTON>(K, nd);
+  case WF_PN35: return pick_kern<double2, SFT_PREC_FP64, WF_PN35>(kern, K, nd);
+  case WF_TABLE: return pick_kern<double2, SFT_PREC_FP64, WF_TABLE>(kern, K, nd);
+  default: return pick_kern<double2, SFT_PREC_FP64, WF_NEWTON>(kern, K, nd);
   }
 }

@@ -7,6 +7,6 @@ using namespace sftk;
 
 ScanFn scan_pick_fstat(int prec, int kern, int K, int nd)
 {
-  if (prec == SFT_PREC_FP64) return pick_k<double2, SFT_PREC_FP64, KERN_DIRICHLET, WF_NEWTON, 1>(K, nd);
+  if (prec == SFT_PREC_FP64) return pick_kern<double2, SFT_PREC_FP64, WF_NEWTON, 1>(kern, K, nd);
   return pick_kern<float2, SFT_PREC_FP32_KAHAN, WF_NEWTON, 1>(kern, K, nd);
 }

@@ -605,7 +605,7 @@ static ScanFn pick_kernel(const sft_data* d, const sft_opts* o, int wf, bool fs,
   if (dop) return scan_pick_doppler(o->precision, fs ? 1 : 0, kern, o->K);
   if (o->t_ref == SFT_REF_START) return scan_pick_start(d->storage, o->precision, wf, kern, d->nd, fs ? 1 : 0);
   if (fs) return scan_pick_fstat(o->precision, kern, o->K, d->nd);
-  if (o->precision == SFT_PREC_FP64) return scan_pick_f64(wf, o->K, d->nd);
+  if (o->precision == SFT_PREC_FP64) return scan_pick_f64(wf, kern, o->K, d->nd);
   if (d->storage == SFT_STORE_F32) {
     const bool kahan = o->precision == SFT_PREC_FP32_KAHAN;
     switch (wf) {
@@ -646,7 +646,6 @@ static sft_status validate_scan(const sft_data* d, const sft_opts* o)
     return fail(SFT_E_UNSUPPORTED, "scan: the surrogate waveform is evaluated at the SFT midpoints only");
   if (o->precision == SFT_PREC_FP64) {
     if (d->storage != SFT_STORE_F64) return fail(SFT_E_UNSUPPORTED, "scan: FP64 precision needs F64 storage");
-    if (o->kernel != SFT_KERNEL_DIRICHLET) return fail(SFT_E_UNSUPPORTED, "scan: FP64 precision supports the Dirichlet kernel only");
   } else if (o->precision == SFT_PREC_FP32_KAHAN || o->precision == SFT_PREC_FP32_NAIVE) {
     if (d->storage == SFT_STORE_F64) return fail(SFT_E_UNSUPPORTED, "scan: FP32 precision needs F32 or BF16 storage");
   } else {

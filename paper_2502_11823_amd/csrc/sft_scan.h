@@ -410,6 +410,58 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       };
       if (stg) drun(std::true_type{});
       else drun(std::false_type{});
+    } else if constexpr (KERN == KERN_FRESNEL && PREC == SFT_PREC_FP64) {
+      // FP64 Fresnel weights, bin by bin.  With b = |beta|, the mirror x' = ds - jj (ds = +-delta,
+      // jj = +-j, the lower signs for beta < 0, where F(x, beta) = conj F(-x, b)) and
+      // p-+ = x' -+ b / 2:
+      //   H_j = (-1)^j F(x, beta) = cj[ e(p-) E- - e(p+) E+
+      //                                 + [p- < 0 <= p+] (-1)^jj (1+i) exp(-i pi x'^2 / b) / sqrt(2 b) ],
+      // e(p) = sgn(p) G(sqrt(2 / b) |p|) / sqrt(2 b), E-+ = exp(i pi (-+ds + b / 4)), cj the
+      // conjugate for beta < 0, G from fresnel_aux64.
+      const bool neg = ch.beta < 0.0;
+      const double b = fabs(ch.beta);
+      const double ds = neg ? -delta : delta;
+      const double isq2b = 1.0 / sqrt(2.0 * b), sq2ob = sqrt(2.0 / b);
+      double emr, emi, epr, epi;
+      sincos(kPi * (0.25 * b - ds), &emi, &emr);
+      sincos(kPi * (0.25 * b + ds), &epi, &epr);
+      auto frun = [&](auto stgc) {
+        constexpr bool STG = decltype(stgc)::value;
+        for (int t = 0; t <= 2 * K; ++t) {
+          const int j = bin_order(t, K);
+          const int idx = i0 + j + K;
+          if (!STG && !inband && (idx < 0 || idx >= a.n_ext)) {
+            fl |= kFlagOOB;
+            continue;
+          }
+          const int jj = neg ? -j : j;
+          const double xq = ds - (double)jj;
+          const double pm = xq - 0.5 * b, pp = xq + 0.5 * b;
+          const double2 gm = fresnel_aux64(fabs(pm) * sq2ob), gp = fresnel_aux64(fabs(pp) * sq2ob);
+          const double sm = pm < 0.0 ? -isq2b : isq2b, sq = pp < 0.0 ? -isq2b : isq2b;
+          double hr = sm * (gm.x * emr - gm.y * emi) - sq * (gp.x * epr - gp.y * epi);
+          double hi = sm * (gm.x * emi + gm.y * emr) - sq * (gp.x * epi + gp.y * epr);
+          if (pm < 0.0 && pp >= 0.0) {
+            // |x'| <= b / 2 here, so x'^2 / b <= b / 4 needs no special reduction
+            double st, ct;
+            sincos(kPi * (xq * xq / b), &st, &ct);
+            const double sg = (jj & 1) ? -isq2b : isq2b;
+            hr = fma(sg, ct + st, hr);
+            hi = fma(sg, ct - st, hi);
+          }
+          if (neg) hi = -hi;
+#pragma unroll
+          for (int d = 0; d < ND; ++d) {
+            R bre, bim;
+            if constexpr (STG) BinIO<Bin>::load(sw + d * WST + (idx - sb), bre, bim);
+            else BinIO<Bin>::load(rp[d] + idx, bre, bim);
+            cre[d] = fma(bre, hr, fma(-bim, hi, cre[d]));
+            cim[d] = fma(bre, hi, fma(bim, hr, cim[d]));
+          }
+        }
+      };
+      if (stg) frun(std::true_type{});
+      else frun(std::false_type{});
     } else if constexpr (KERN == KERN_FRESNEL) {
       // Fresnel weights; beta < 0 through F(x, beta) = conj F(-x, -beta).  The endpoint
       // phasors E-+ are common to all bins, so the bins accumulate b e(p-) and b e(p+)
@@ -737,18 +789,18 @@ static ScanFn pick_nd(int nd)
 template <typename Bin, int PREC, int WF, int FS = 0>
 static ScanFn pick_start(int kern, int nd)
 {
-  if constexpr (PREC == SFT_PREC_FP64) {
-    return pick_nd<Bin, PREC, KERN_DIRICHLET, -1, WF, FS, 1>(nd);
-  } else {
-    return kern == KERN_DIRICHLET ? pick_nd<Bin, PREC, KERN_DIRICHLET, -1, WF, FS, 1>(nd)
-                                  : pick_nd<Bin, PREC, KERN_FRESNEL, -1, WF, FS, 1>(nd);
-  }
+  return kern == KERN_DIRICHLET ? pick_nd<Bin, PREC, KERN_DIRICHLET, -1, WF, FS, 1>(nd)
+                                : pick_nd<Bin, PREC, KERN_FRESNEL, -1, WF, FS, 1>(nd);
 }
 
+// FP64: the Dirichlet kernel with a compile-time window for K = 4 and a run-time one otherwise;
+// the FP64 Fresnel weights (a reference mode, dominated by their special functions) with the
+// run-time window only.
 template <typename Bin, int PREC, int KERN, int WF, int FS = 0>
 static ScanFn pick_k(int K, int nd)
 {
   if constexpr (PREC == SFT_PREC_FP64) {
+    if constexpr (KERN == KERN_FRESNEL) return pick_nd<Bin, PREC, KERN, -1, WF, FS>(nd);
     return K == 4 ? pick_nd<Bin, PREC, KERN, 4, WF, FS>(nd) : pick_nd<Bin, PREC, KERN, -1, WF, FS>(nd);
   } else {
     // one-row Fresnel scans with K = 32 (space-like banks) get a compile-time window too
@@ -770,6 +822,7 @@ template <typename Bin, int PREC, int KERN, int FS>
 static ScanFn pick_doppler_k(int K)
 {
   if constexpr (PREC == SFT_PREC_FP64) {
+    if constexpr (KERN == KERN_FRESNEL) return scan_kernel<Bin, PREC, KERN, -1, 1, WF_NEWTON, FS, 1>;
     return K == 4 ? scan_kernel<Bin, PREC, KERN, 4, 1, WF_NEWTON, FS, 1> : scan_kernel<Bin, PREC, KERN, -1, 1, WF_NEWTON, FS, 1>;
   } else {
     if constexpr (KERN == KERN_FRESNEL)

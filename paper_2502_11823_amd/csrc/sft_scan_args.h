@@ -50,7 +50,7 @@ using ScanFn = void (*)(ScanArgs);
 // Scan kernel for one arithmetic form, chosen by waveform (WF_*), kernel (KERN_*), window
 // half-width K and the largest timestamp-group size nd.  Each is defined in its own
 // translation unit (scan_*.hip), so that the kernel instantiations compile in parallel.
-ScanFn scan_pick_f64(int wf, int K, int nd);
+ScanFn scan_pick_f64(int wf, int kern, int K, int nd);
 ScanFn scan_pick_f32k_newton(int kern, int K, int nd);
 ScanFn scan_pick_f32k_pn35(int kern, int K, int nd);
 ScanFn scan_pick_f32k_table(int kern, int K, int nd);

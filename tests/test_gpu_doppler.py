@@ -56,6 +56,23 @@ def test_doppler_ground_three_sites():
     assert np.max(np.abs(o0["zp"] - o["zp"]) / np.sqrt(o["hhp"])) > 1e-2
 
 
+def test_doppler_fp64_fresnel_ground():
+    """The Doppler form with FP64 Fresnel weights (and the F-statistic) on the three-site
+    ground data, against the oracle within 1e-9."""
+    w = synth.ground(seed=6, n_templates=300, n_slots=96, n_det=3, k_lo=40, k_hi=470, t_end_pad=300.0)
+    eph = _ground_eph(w)
+    w.bank["sky"] = _sky(300, 2)
+    data = sft.SFTData.from_workload(w, storage="f64")
+    data.set_ephemeris(eph)
+    kw = dict(K=8, kernel="auto", precision="fp64", a_plus=1.0, a_cross=1.0)
+    for fs in (False, True):
+        g = gpu_scan(data, w.bank, fstat=fs, **kw)
+        o = orc_scan(w, w.bank, eph=eph, sky=w.bank["sky"], fstat=fs, **kw)
+        compare(g, o, label="doppler fp64 fresnel fstat=%d" % fs, tol_z=1e-9, tol_rho=1e-9, tol_hh=1e-9)
+        if fs:
+            compare_fstat(g, o, tol_f=1e-9, tol_hh=1e-9, label="doppler fp64 fresnel 2F")
+
+
 def test_doppler_fp64_fast_orbit_and_zero_limit():
     w = synth.tiny(seed=1, n_templates=400)
     tm = w.t_start + 0.5 * w.t_sft

@@ -22,7 +22,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 from paper_2502_11823_amd import sft  # noqa: E402
 
-from parity_helpers import KERN, compare, gpu_scan, orc_scan  # noqa: E402,F401
+from parity_helpers import KERN, compare, compare_fstat, gpu_scan, orc_scan  # noqa: E402,F401
 
 
 # ----------------------------------------------------------------------------- fixtures
@@ -363,6 +363,60 @@ def test_precision_sweep_tiny_data_1e5_templates(tiny):
     assert rows[2][2] <= 1e-6 and rows[2][5] <= 1e-5
     assert rows[1][2] < 1e-5
     assert rows[3][2] < 3e-2
+
+
+@pytest.mark.parametrize("workload", ["ground_small", "space"])
+def test_precision_sweep_fresnel_data(ground_small, workload):
+    """The four arithmetic variants on Fresnel data: the three-detector ground bank (K = 8,
+    AUTO kernel, drifts of a few bins) and the ragged space-based bank (K = 32, drifts up to
+    ~30 bins, DC mirror), every template against the FP64 oracle.  FP64 (Fresnel weights
+    from FP64 Fresnel integrals) within 1e-9, FP32 compensated sums within the 1e-6 bar, plain
+    FP32 sums within 1e-5, BF16-stored bins reported (bound 3e-2)."""
+    if workload == "space":
+        w = synth.space(n_templates=999)
+        kw = dict(K=32, kernel="auto", a_plus=1.0, a_cross=1.0)
+    else:
+        w = ground_small
+        kw = dict(K=8, kernel="auto", a_plus=1.0, a_cross=1.0)
+    o = orc_scan(w, w.bank, **kw)
+    ok = o["tie"] > 1e-9
+    rows = []
+    for storage, prec in [("f64", "fp64"), ("f32", "fp32_naive"), ("f32", "fp32_kahan"), ("bf16", "fp32_kahan")]:
+        data = sft.SFTData.from_workload(w, storage=storage)
+        g = gpu_scan(data, w.bank, precision=prec, **kw)
+        e = np.abs(g["zp"] - o["zp"]) / np.maximum(np.abs(o["zp"]), np.sqrt(o["hhp"]))
+        er = np.abs(g["rho"] - o["rho"]) / np.maximum(o["rho"], 1.0)
+        e, er = e[ok], er[ok]
+        rows.append((storage, prec, e.max(), er.max()))
+        print("%s precision %-4s %-10s e: max %.3e median %.3e | rho: max %.3e"
+              % (workload, storage, prec, e.max(), np.median(e), er.max()))
+        assert np.array_equal(g["flags"][ok], o["flags"][ok])
+        data.close()
+    assert rows[0][2] < 1e-9 and rows[0][3] < 1e-9
+    assert rows[2][2] <= 1e-6 and rows[2][3] <= 1e-5
+    assert rows[1][2] < 1e-5
+    assert rows[3][2] < 3e-2
+
+
+def test_fp64_fresnel_forms(ground_small):
+    """FP64 Fresnel weights in every scan form that has them: the 3.5PN waveform (the
+    four-row group kernel), the F-statistic, and the start reference (both waveforms),
+    against the oracle within 1e-9 on z, rho, the norms and 2F."""
+    w = ground_small
+    data = sft.SFTData.from_workload(w, storage="f64")
+    tight = dict(tol_z=1e-9, tol_rho=1e-9, tol_hh=1e-9)
+    base = dict(K=8, kernel="auto", precision="fp64", a_plus=1.0, a_cross=1.0)
+    bank = _with_q(w.bank, 9)
+    for label, extra, fstat in [("pn35", dict(waveform="pn35"), False),
+                                ("fstat", dict(), True),
+                                ("start newton", dict(t_ref="start"), False),
+                                ("start pn35", dict(t_ref="start", waveform="pn35"), False)]:
+        kw = dict(base, **extra)
+        g = gpu_scan(data, bank, fstat=fstat, **kw)
+        o = orc_scan(w, bank, fstat=fstat, **kw)
+        compare(g, o, label="fp64 fresnel " + label, **tight)
+        if fstat:
+            compare_fstat(g, o, tol_f=1e-9, tol_hh=1e-9, label="fp64 fresnel 2F")
 
 
 # ----------------------------------------------------------------------------- 3.5PN waveform
