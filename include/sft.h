@@ -290,6 +290,8 @@ typedef struct {
   double* mismatch;
   double* hhpx;
   double* twoF;
+  int32_t* n_used;  /* [n] or NULL: SFT rows that entered the template's sum (rows of its range
+                       whose reference time precedes t_c) */
 } sft_out;
 
 /*

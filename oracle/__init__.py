@@ -71,7 +71,7 @@ def _load():
                                   Int, Int, Int, D, D, D, D, Int, Int, P, P, P]
     lib.orc_scan.argtypes = [L, L, D, L, L, P, P, P, P, P,
                              L, Int, P, P, P, P, P, P,
-                             Int, Int, Int, D, D, D, D, D, Int, Int, P, P, P, P, P, P]
+                             Int, Int, Int, D, D, D, D, D, Int, Int, P, P, P, P, P, P, P]
     lib.orc_doppler_waveform.argtypes = [Int, D, D, D, D, D, D, P, P, P]
     lib.orc_set_surrogate.argtypes = [Int, Int, P, P]
     lib.orc_mlp_param_count.argtypes = [Int, Int]
@@ -285,7 +285,7 @@ def scan(data: SFTData, mc, t_c, phi_c=None, q=None, a_first=None, a_last=None, 
     detector at the SFT midpoint, sky [n, 3] unit vectors toward the sources.
 
     Returns a dict of numpy arrays: zp, zx (complex), hhp, hhx, rho, flags, tie, mismatch,
-    and with fstat=True the cross norm hhpx and the F-statistic twoF (Sec. II.B)."""
+    n_used (SFT rows in the template's sum), and with fstat=True the cross norm hhpx and the F-statistic twoF (Sec. II.B)."""
     mc = _f64(np.atleast_1d(mc))
     m = mc.size
     t_c = _f64(np.broadcast_to(t_c, (m,)))
@@ -297,6 +297,7 @@ def scan(data: SFTData, mc, t_c, phi_c=None, q=None, a_first=None, a_last=None, 
     fl = np.zeros(m, np.uint32)
     tie = np.zeros(m)
     mm = np.zeros(m)
+    nu = np.zeros(m, np.int32)
     eph = None if eph is None else np.ascontiguousarray(np.reshape(eph, (data.n_sft, 9)), dtype=np.float64)
     sky = None if sky is None else np.ascontiguousarray(np.broadcast_to(np.reshape(sky, (-1, 3)), (m, 3)),
                                                         dtype=np.float64)
@@ -305,14 +306,14 @@ def scan(data: SFTData, mc, t_c, phi_c=None, q=None, a_first=None, a_last=None, 
                           _ptr(t_c), _ptr(phi_c), _ptr(af), _ptr(al), int(K), int(kernel),
                           int(t_ref), float(beta_switch), float(a_plus), float(a_cross),
                           float(tsun), float(delta_max), int(compensated), int(bool(fstat)),
-                          _ptr(eph), _ptr(sky), _ptr(out), _ptr(fl), _ptr(tie), _ptr(mm))
+                          _ptr(eph), _ptr(sky), _ptr(out), _ptr(fl), _ptr(tie), _ptr(mm), _ptr(nu))
     if rc == -2:
         raise ValueError("Doppler needs eph and sky, the midpoint reference and a closed-form waveform")
     if rc != 0:
         raise MemoryError("oracle scan failed")
     res = {"zp": out[:, 0] + 1j * out[:, 1], "zx": out[:, 2] + 1j * out[:, 3],
            "hhp": out[:, 4], "hhx": out[:, 5], "rho": out[:, 6], "flags": fl, "tie": tie,
-           "mismatch": mm}
+           "mismatch": mm, "n_used": nu}
     if fstat:
         res["hhpx"] = out[:, 7]
         res["twoF"] = out[:, 8]

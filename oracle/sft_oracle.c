@@ -822,7 +822,7 @@ int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
              int K, int kernel, int t_ref, double beta_switch, double a_plus, double a_cross,
              double tsun, double delta_max, int compensated, int fstat,
              const double *eph, const double *sky,
-             double *out, uint32_t *flags, double *tie, double *mismatch)
+             double *out, uint32_t *flags, double *tie, double *mismatch, int32_t *n_used)
 {
   /* Doppler: eph [n_sft][9] at each SFT's midpoint, sky [n_tmpl][3] (midpoint reference and
    * the closed-form waveforms only) */
@@ -890,6 +890,12 @@ int orc_scan(long n_sft, long n, double T, long k_lo, long n_bins,
         use[a] = 1;
       }
       orc_template_sum(&D, &o, A, ph, fr, fd, fdd, use, out + 9 * m, flags + m, tie ? tie + m : NULL);
+      if (n_used) {
+        /* the SFT rows that entered the sum of Eq. efficient: in range, reference time before t_c */
+        int32_t cnt = 0;
+        for (long a = 0; a < n_sft; a++) cnt += use[a] ? 1 : 0;
+        n_used[m] = cnt;
+      }
       flags[m] |= extra;
     }
     free(buf);

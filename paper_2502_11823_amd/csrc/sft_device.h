@@ -46,6 +46,9 @@ enum : uint32_t {
   kFlagSurrogateFallback = 32u,
   kFlagEmpty = 64u
 };
+// The per-chunk flag words of the scan carry, above the flag bits, the count of SFT rows that
+// entered the template's sum in that chunk (rows in its range with tau > 0).
+constexpr int kUsedShift = 8;
 
 // ---------------------------------------------------------------- storage types
 struct bf16x2 { uint16_t re, im; };

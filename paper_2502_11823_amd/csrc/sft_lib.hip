@@ -305,6 +305,7 @@ static sft_status validate_desc(const sft_data_desc* d)
 {
   if (d->n_sft < 1 || d->n_samples < 2 || (d->n_samples & 1) || !(d->t_sft > 0.0) || d->reserved != 0)
     return fail(SFT_E_INVALID, "sft_load_data: bad descriptor (n_sft=%d n=%d T=%g)", d->n_sft, d->n_samples, d->t_sft);
+  if (d->n_sft >= (1 << 24)) return fail(SFT_E_RANGE, "sft_load_data: n_sft=%d, at most 2^24 - 1 SFT rows", d->n_sft);
   if (d->k_lo < 0 || d->n_bins < 1 || d->k_lo + d->n_bins - 1 > d->n_samples / 2)
     return fail(SFT_E_INVALID, "sft_load_data: band [%d, %d) outside [0, n/2]", d->k_lo, d->k_lo + d->n_bins);
   if (d->storage != SFT_STORE_F64 && d->storage != SFT_STORE_F32 && d->storage != SFT_STORE_BF16)
@@ -552,20 +553,25 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
                                                        double* __restrict__ hhp, double* __restrict__ hhx,
                                                        double* __restrict__ rho, uint32_t* __restrict__ flags,
                                                        const uint32_t* __restrict__ xflags, double* __restrict__ hhpx,
-                                                       double* __restrict__ twoF, const int32_t* __restrict__ perm)
+                                                       double* __restrict__ twoF, const int32_t* __restrict__ perm,
+                                                       int32_t* __restrict__ n_used)
 {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   const int64_t w = perm ? (int64_t)perm[m] : m;
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
   uint32_t fl = 0;
+  int64_t used = 0;
   for (int c = 0; c < n_chunks; ++c) {
     const double* p = part + (int64_t)c * nacc * n + m;
 #pragma unroll
     for (int q = 0; q < 6; ++q) v[q] += p[q * n];
     if (nacc == 7) v[6] += p[6 * n];
-    fl |= pflags[(int64_t)c * n + m];
+    const uint32_t pf = pflags[(int64_t)c * n + m];
+    fl |= pf & ((1u << kUsedShift) - 1u);
+    used += pf >> kUsedShift;
   }
+  if (n_used) n_used[w] = (int32_t)used;
   const double re = a_plus * v[0] + a_cross * v[3];
   const double im = a_plus * v[1] - a_cross * v[2];
   const double hh = a_plus * a_plus * v[4] + a_cross * a_cross * v[5];
@@ -821,7 +827,7 @@ static hipError_t enqueue_scan(Prepared& P, void* ws, sft_out* out, hipStream_t 
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, a.part, a.pflags, P.n,
                      a.n_chunks, P.nacc, P.a_plus, P.a_cross, out->zp, out->zx, out->hhp, out->hhx, out->rho,
                      out->flags, P.xflags, P.nacc == 7 ? out->hhpx : nullptr, P.nacc == 7 ? out->twoF : nullptr,
-                     P.perm);
+                     P.perm, out->n_used);
   return hipGetLastError();
 }
 
@@ -1231,6 +1237,7 @@ static sft_status surrogate_scan(const sft_data* d, const sft_bank* bank, int64_
     ob.rho += m0;
     ob.flags += m0;
     if (ob.mismatch) ob.mismatch += m0;
+    if (ob.n_used) ob.n_used += m0;
     hipLaunchKernelGGL(sur_inputs_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, sa, b.mc, b.q, b.t_c,
                        d->g_tmid, nb, d->n_groups, U);
     if ((e = hipGetLastError()) != hipSuccess) break;

@@ -294,6 +294,12 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       fl |= kFlagTau;
       continue;
     }
+    {
+      uint32_t nact = 0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) nact += act[d] ? 1u : 0u;
+      fl += nact << kUsedShift;
+    }
     Chirp ch;
     if constexpr (WF == WF_PN35) {
       ch = pn35_chirp(tau, nu, inv5Mnu, Mt, nu25, phic, T, pcf);

@@ -56,7 +56,8 @@ class Bank(ctypes.Structure):
 class Out(ctypes.Structure):
     _fields_ = [("zp", ctypes.c_void_p), ("zx", ctypes.c_void_p), ("hhp", ctypes.c_void_p),
                 ("hhx", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("flags", ctypes.c_void_p),
-                ("mismatch", ctypes.c_void_p), ("hhpx", ctypes.c_void_p), ("twoF", ctypes.c_void_p)]
+                ("mismatch", ctypes.c_void_p), ("hhpx", ctypes.c_void_p), ("twoF", ctypes.c_void_p),
+                ("n_used", ctypes.c_void_p)]
 
 
 class SurrogateDesc(ctypes.Structure):
@@ -354,7 +355,8 @@ def alloc_out(n: int, device="cuda", mismatch=False, fstat=False):
            "hhp": torch.empty(n, dtype=torch.float64, device=device),
            "hhx": torch.empty(n, dtype=torch.float64, device=device),
            "rho": torch.empty(n, dtype=torch.float64, device=device),
-           "flags": torch.empty(n, dtype=torch.int32, device=device)}
+           "flags": torch.empty(n, dtype=torch.int32, device=device),
+           "n_used": torch.empty(n, dtype=torch.int32, device=device)}
     if mismatch:
         out["mismatch"] = torch.zeros(n, dtype=torch.float64, device=device)
     if fstat:
@@ -380,7 +382,8 @@ def _bank_struct(bank_t):
 
 def _out_struct(out):
     return Out(_tp(out["zp"]), _tp(out["zx"]), _tp(out["hhp"]), _tp(out["hhx"]), _tp(out["rho"]),
-               _tp(out["flags"]), _tp(out.get("mismatch")), _tp(out.get("hhpx")), _tp(out.get("twoF")))
+               _tp(out["flags"]), _tp(out.get("mismatch")), _tp(out.get("hhpx")), _tp(out.get("twoF")),
+               _tp(out.get("n_used")))
 
 
 def template_bank_scan(data: SFTData, bank_t, opts: Opts, out=None, stream=None, n=None):

@@ -62,6 +62,8 @@ def compare(g, o, idx=None, tol_z=1e-6, tol_rho=1e-5, tol_hh=1e-6, label="", noi
               % (w, g["flags"][w], o["flags"][w], g["zp"][w], o["zp"][w], g["hhp"][w], o["hhp"][w],
                  g["rho"][w], o["rho"][w]))
     assert np.array_equal(g["flags"][ok], o["flags"][ok]), (g["flags"][ok], o["flags"][ok])
+    if "n_used" in g and "n_used" in o:
+        assert np.array_equal(g["n_used"], o["n_used"]), "SFT rows used differ"
     assert ep[ok].max() <= tol_z
     assert ex[ok].max() <= tol_z
     assert eh[ok].max() <= tol_hh

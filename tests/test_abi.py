@@ -35,7 +35,7 @@ def test_version_and_defaults():
     assert abs(o.tsun - 4.925490947641267e-6) < 1e-20
     assert o.surrogate is None
     assert ctypes.sizeof(sft.DataDesc) == 32 and ctypes.sizeof(sft.Opts) == 72
-    assert ctypes.sizeof(sft.Out) == 72 and ctypes.sizeof(sft.SurrogateDesc) == 88
+    assert ctypes.sizeof(sft.Out) == 80 and ctypes.sizeof(sft.SurrogateDesc) == 88
     assert ctypes.sizeof(sft.Tuning) == 16
 
 

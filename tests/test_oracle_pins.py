@@ -567,6 +567,24 @@ def test_p14_judge_weights_follow_the_psd(orc):
     assert np.allclose(mm(7.3 * flat, w.n_sft - 1), m_all, rtol=1e-12, atol=0)
 
 
+def test_n_used_counts_the_rows_in_the_sum(orc):
+    """n_used is the number of SFT rows of the template's range [a_first, a_last] whose reference
+    time (midpoint, or start with the start reference) precedes t_c: the SFTs that enter the sum
+    of Eq. efficient.  Templates coalescing inside the data and ragged ranges."""
+    w = synth.tiny(seed=3, n_templates=6, n_sft=40, noise_series=False)
+    od = orc.SFTData(w.t_start, w.n_samples, w.t_sft, w.k_lo, w.x_bins, w.psd)
+    mc = np.full(6, 1.2)
+    tc = np.array([3000.0, 1000.0, 1312.0, 5000.0, -10.0, 2600.0])
+    af = np.array([0, 3, 0, 10, 0, 39], np.int32)
+    al = np.array([39, 30, 39, 12, 39, 39], np.int32)
+    for t_ref, off in ((orc.REF_MID, 0.5 * w.t_sft), (orc.REF_START, 0.0)):
+        r = orc.scan(od, mc, tc, a_first=af, a_last=al, K=4, kernel=orc.K_DIRICHLET, t_ref=t_ref)
+        tref = w.t_start + off
+        want = [int(np.sum((np.arange(40) >= a) & (np.arange(40) <= b) & (tref < c))) for a, b, c in zip(af, al, tc)]
+        assert r["n_used"].tolist() == want
+        assert r["n_used"][4] == 0 and r["flags"][4] & orc.F_EMPTY
+
+
 # --------------------------------------------------------------------------- rho with both polarisations
 def test_rho_both_polarisations_equals_phase_maximised_time_domain_product(orc):
     """Eq. det_short (reading R12) with A_x != 0: the oracle's rho sqrt(A+^2 hh+ + Ax^2 hhx)
