@@ -553,7 +553,13 @@ __device__ inline void silu_tangent_f32(float z, float zt, float& h, float& t)
   t = s * (1.0f + z * (1.0f - s)) * zt;
 }
 
-template <int NT, bool SPLIT>
+// RT row tiles of 16 per wavefront (16 RT rows): each weight fragment read from LDS serves RT
+// tiles, and the fragments staged per workgroup serve 64 RT rows.  With split operands the
+// fragments are double buffered: layer l + 1's are loaded into LDS while layer l runs (the
+// layer's biases are read into registers before that prefetch is issued, so that waiting for
+// them does not wait for it).  The plain kernel keeps one buffer (its registers leave room for
+// two wavefronts per SIMD, which 128 KiB of LDS per workgroup would not).
+template <int NT, bool SPLIT, int RT>
 __global__ __launch_bounds__(256) void mlp_bf16_kernel(const double* __restrict__ U, int64_t n,
                                                        const float* __restrict__ par,
                                                        const bf16x8* __restrict__ frag, int layers,
@@ -561,120 +567,166 @@ __global__ __launch_bounds__(256) void mlp_bf16_kernel(const double* __restrict_
 {
   constexpr int H = 16 * NT, S = H / 32;
   constexpr int NF = NT * S * 2 * 64;   // fragments of one layer (a multiple of 256)
-  __shared__ bf16x8 wl[NF];
+  constexpr bool DB = SPLIT;
+  __shared__ bf16x8 wl2[(DB ? 2 : 1) * NF];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
-  const int64_t r = ((int64_t)blockIdx.x * 4 + wave) * 16 + j;
-  const bool valid = r < n;
-  float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
-  if (valid) {
-    u0 = (float)U[3 * r];
-    u1 = (float)U[3 * r + 1];
-    u2 = (float)U[3 * r + 2];
-  }
-  float av[NT][4], at[NT][4];
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16 * RT + j;   // row of tile t: r0 + 16 t
+  // direct global -> LDS copies of a layer's fragments: a wavefront fills 1 KiB at its
+  // wave-uniform base, lane i at base + 16 i
+  auto stage = [&](const bf16x8* F, bf16x8* dst) {
+#pragma unroll
+    for (int c = 0; c < NF / 256; ++c)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(F + 256 * c + threadIdx.x),
+                                       (__attribute__((address_space(3))) void*)(dst + 256 * c + 64 * wave), 16, 0, 0);
+  };
+  if (DB && layers > 1) stage(frag, wl2);   // layer 1, behind the first layer's work
+  float av[RT][NT][4], at[RT][NT][4];
   {
     const float* W = par;           // [3][H]
     const float* b = par + 3 * H;   // [H]
 #pragma unroll
-    for (int m = 0; m < NT; ++m)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int u = 16 * m + 4 * g + v;
-        const float z = fmaf(W[2 * H + u], u2, fmaf(W[H + u], u1, fmaf(W[u], u0, b[u])));
-        silu_tangent_f32(z, W[2 * H + u], av[m][v], at[m][v]);
+    for (int t = 0; t < RT; ++t) {
+      const int64_t r = r0 + 16 * t;
+      float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
+      if (r < n) {
+        u0 = (float)U[3 * r];
+        u1 = (float)U[3 * r + 1];
+        u2 = (float)U[3 * r + 2];
       }
+#pragma unroll
+      for (int m = 0; m < NT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int u = 16 * m + 4 * g + v;
+          const float z = fmaf(W[2 * H + u], u2, fmaf(W[H + u], u1, fmaf(W[u], u0, b[u])));
+          silu_tangent_f32(z, W[2 * H + u], av[t][m][v], at[t][m][v]);
+        }
+    }
   }
   int64_t off = 4 * H;
   for (int l = 1; l < layers; ++l) {
-    const float* b = par + off + H * H;
-    const bf16x8* F = frag + (int64_t)(l - 1) * NF;
-    __syncthreads();   // every wavefront is done with the previous layer's fragments
-    // direct global -> LDS copies: a wavefront fills 1 KiB at its wave-uniform base, lane i at base + 16 i
-#pragma unroll
-    for (int c = 0; c < NF / 256; ++c)
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(F + 256 * c + threadIdx.x),
-                                       (__attribute__((address_space(3))) void*)(wl + 256 * c + 64 * wave), 16, 0, 0);
-    // meanwhile the B operands of every K step: this lane's activations in the permuted order
-    bf16x8 bvh[S], bvl[S], bth[S], btl[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float x = av[2 * s + (e >> 2)][e & 3], y = at[2 * s + (e >> 2)][e & 3];
-        const __bf16 xh = (__bf16)x, yh = (__bf16)y;
-        bvh[s][e] = xh;
-        bth[s][e] = yh;
-        if constexpr (SPLIT) {
-          bvl[s][e] = (__bf16)(x - (float)xh);
-          btl[s][e] = (__bf16)(y - (float)yh);
-        }
-      }
-    __builtin_amdgcn_s_waitcnt(0);
+    // double buffer: this layer's fragments are in buffer (l - 1) % 2, and every wavefront is
+    // done with layer l - 1, whose buffer takes layer l + 1.  Single buffer: every wavefront is
+    // done with layer l - 1, and this layer's fragments are loaded now.
+    if constexpr (DB) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    const bf16x8* wl = wl2 + (DB ? ((l - 1) & 1) * NF : 0);
+    float bl[NT][4];
+#pragma unroll
+    for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bl[mo][v] = par[off + H * H + 16 * mo + 4 * g + v];
+    if constexpr (DB) {
+      if (l + 1 < layers) stage(frag + (int64_t)l * NF, wl2 + (l & 1) * NF);
+    } else {
+      stage(frag + (int64_t)(l - 1) * NF, wl2);
+    }
+    // meanwhile the B operands of every K step: this lane's activations in the permuted order
+    bf16x8 bvh[RT][S], bvl[RT][S], bth[RT][S], btl[RT][S];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float x = av[t][2 * s + (e >> 2)][e & 3], y = at[t][2 * s + (e >> 2)][e & 3];
+          const __bf16 xh = (__bf16)x, yh = (__bf16)y;
+          bvh[t][s][e] = xh;
+          bth[t][s][e] = yh;
+          if constexpr (SPLIT) {
+            bvl[t][s][e] = (__bf16)(x - (float)xh);
+            btl[t][s][e] = (__bf16)(y - (float)yh);
+          }
+        }
+    if constexpr (!DB) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
 #pragma unroll
     for (int mo = 0; mo < NT; ++mo) {
-      flt4 cv = {0.0f, 0.0f, 0.0f, 0.0f}, ct = {0.0f, 0.0f, 0.0f, 0.0f};
+      flt4 cv[RT], ct[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) cv[t] = ct[t] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const bf16x8 ah = wl[((mo * S + s) * 2) * 64 + lane];
-        cv = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bvh[s], cv, 0, 0, 0);
-        ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bth[s], ct, 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          cv[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bvh[t][s], cv[t], 0, 0, 0);
+          ct[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bth[t][s], ct[t], 0, 0, 0);
+        }
         if constexpr (SPLIT) {
           const bf16x8 al = wl[((mo * S + s) * 2 + 1) * 64 + lane];
-          cv = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bvh[s], cv, 0, 0, 0);
-          cv = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bvl[s], cv, 0, 0, 0);
-          ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bth[s], ct, 0, 0, 0);
-          ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, btl[s], ct, 0, 0, 0);
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            cv[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bvh[t][s], cv[t], 0, 0, 0);
+            cv[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bvl[t][s], cv[t], 0, 0, 0);
+            ct[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bth[t][s], ct[t], 0, 0, 0);
+            ct[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, btl[t][s], ct[t], 0, 0, 0);
+          }
         }
       }
       // the B operands hold this layer's inputs: the outputs may overwrite av, at
 #pragma unroll
-      for (int v = 0; v < 4; ++v) silu_tangent_f32(cv[v] + b[16 * mo + 4 * g + v], ct[v], av[mo][v], at[mo][v]);
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          silu_tangent_f32(cv[t][v] + bl[mo][v], ct[t][v], av[t][mo][v], at[t][mo][v]);
     }
     off += (int64_t)H * H + H;
   }
   const float* W = par + off;   // [H][2]
   const float* b = W + 2 * H;
-  float y0 = 0.0f, y1 = 0.0f, t0 = 0.0f, t1 = 0.0f;
 #pragma unroll
-  for (int m = 0; m < NT; ++m)
+  for (int t = 0; t < RT; ++t) {
+    float y0 = 0.0f, y1 = 0.0f, t0 = 0.0f, t1 = 0.0f;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int u = 16 * m + 4 * g + v;
-      y0 = fmaf(W[2 * u], av[m][v], y0);
-      y1 = fmaf(W[2 * u + 1], av[m][v], y1);
-      t0 = fmaf(W[2 * u], at[m][v], t0);
-      t1 = fmaf(W[2 * u + 1], at[m][v], t1);
+    for (int m = 0; m < NT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int u = 16 * m + 4 * g + v;
+        y0 = fmaf(W[2 * u], av[t][m][v], y0);
+        y1 = fmaf(W[2 * u + 1], av[t][m][v], y1);
+        t0 = fmaf(W[2 * u], at[t][m][v], t0);
+        t1 = fmaf(W[2 * u + 1], at[t][m][v], t1);
+      }
+    y0 += __shfl_xor(y0, 16);
+    y1 += __shfl_xor(y1, 16);
+    t0 += __shfl_xor(t0, 16);
+    t1 += __shfl_xor(t1, 16);
+    y0 += __shfl_xor(y0, 32);
+    y1 += __shfl_xor(y1, 32);
+    t0 += __shfl_xor(t0, 32);
+    t1 += __shfl_xor(t1, 32);
+    const int64_t r = r0 + 16 * t;
+    if (g == 0 && r < n) {
+      Y[2 * r] = (double)(y0 + b[0]);
+      Y[2 * r + 1] = (double)(y1 + b[1]);
+      dY[2 * r] = (double)t0;
+      dY[2 * r + 1] = (double)t1;
     }
-  y0 += __shfl_xor(y0, 16);
-  y1 += __shfl_xor(y1, 16);
-  t0 += __shfl_xor(t0, 16);
-  t1 += __shfl_xor(t1, 16);
-  y0 += __shfl_xor(y0, 32);
-  y1 += __shfl_xor(y1, 32);
-  t0 += __shfl_xor(t0, 32);
-  t1 += __shfl_xor(t1, 32);
-  if (g == 0 && valid) {
-    Y[2 * r] = (double)(y0 + b[0]);
-    Y[2 * r + 1] = (double)(y1 + b[1]);
-    dY[2 * r] = (double)t0;
-    dY[2 * r + 1] = (double)t1;
   }
 }
+
+// rows per wavefront of the BF16 kernel: 16 * MLP_BF16_RT
+#ifndef MLP_BF16_RT
+#define MLP_BF16_RT 2
+#endif
 
 template <bool SPLIT>
 static hipError_t mlp_bf16_launch(const sft_surrogate* s, const double* U, int64_t n, double* Y, double* dY,
                                   hipStream_t st)
 {
-  const dim3 grid((unsigned)((n + 63) / 64)), block(256);
+  constexpr int RT = MLP_BF16_RT;
+  const dim3 grid((unsigned)((n + 64 * RT - 1) / (64 * RT))), block(256);
   const int L = s->d.layers;
   const bf16x8* F = (const bf16x8*)s->frag;
   switch (s->d.hidden / 32) {
-  case 1: hipLaunchKernelGGL((mlp_bf16_kernel<2, SPLIT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
-  case 2: hipLaunchKernelGGL((mlp_bf16_kernel<4, SPLIT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
-  case 3: hipLaunchKernelGGL((mlp_bf16_kernel<6, SPLIT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
-  default: hipLaunchKernelGGL((mlp_bf16_kernel<8, SPLIT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
+  case 1: hipLaunchKernelGGL((mlp_bf16_kernel<2, SPLIT, RT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
+  case 2: hipLaunchKernelGGL((mlp_bf16_kernel<4, SPLIT, RT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
+  case 3: hipLaunchKernelGGL((mlp_bf16_kernel<6, SPLIT, RT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
+  default: hipLaunchKernelGGL((mlp_bf16_kernel<8, SPLIT, RT>), grid, block, 0, st, U, n, s->par, F, L, Y, dY); break;
   }
   return hipGetLastError();
 }
