@@ -79,11 +79,20 @@ __global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
   if (tid == 0) s_bad = 0;
   __syncthreads();
   bool bad = false;
-  for (int m = tid; m < M; m += blockDim.x) {
-    const double re = xs[2 * m], im = xs[2 * m + 1];
-    bad = bad || !isfinite(re) || !isfinite(im);
-    const int r = (int)(__brev((unsigned)m) >> (32 - logM));
-    buf[r] = make_double2(re, im);
+  // z[m] = x[2m] + i x[2m+1]: one 16-byte load per point where the segment is 16-byte aligned
+  if ((reinterpret_cast<uintptr_t>(xs) & 15) == 0) {
+    const double2* xs2 = reinterpret_cast<const double2*>(xs);
+    for (int m = tid; m < M; m += blockDim.x) {
+      const double2 z = xs2[m];
+      bad = bad || !isfinite(z.x) || !isfinite(z.y);
+      buf[(int)(__brev((unsigned)m) >> (32 - logM))] = z;
+    }
+  } else {
+    for (int m = tid; m < M; m += blockDim.x) {
+      const double re = xs[2 * m], im = xs[2 * m + 1];
+      bad = bad || !isfinite(re) || !isfinite(im);
+      buf[(int)(__brev((unsigned)m) >> (32 - logM))] = make_double2(re, im);
+    }
   }
   if (staged)
     for (int j = tid; j < M / 2; j += blockDim.x) tws[j] = tw[j];
@@ -194,26 +203,24 @@ __global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
           wave_sync();
         }
       }
+      // every lane counts, along the sorted list, the entries inside its own block; its median
+      // is the entry at which that count reaches w + 1.  The list is read as broadcasts in a
+      // wave-uniform loop without an early exit, so the reads pipeline.
       const int i = c0 + lane;
-      if (i < n_bins) {
-        const int k = k_lo + i;
-        int s0 = k - w;
-        s0 = s0 < 0 ? 0 : s0;
-        s0 = s0 + 2 * w > M ? M - 2 * w : s0;
-        int cnt = 0;
-        double med = 0.0;
-        for (int q = 0; q < L; ++q) {
-          const int j = si[q];
-          if (j >= s0 && j < s0 + N) {
-            if (cnt == w) {
-              med = sv[q];
-              break;
-            }
-            ++cnt;
-          }
-        }
-        po[i] = psd_scale * (dt * dt) * med;
+      const int k = k_lo + i;
+      int s0 = k - w;
+      s0 = s0 < 0 ? 0 : s0;
+      s0 = s0 + 2 * w > M ? M - 2 * w : s0;
+      int cnt = 0;
+      double med = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < L; ++q) {
+        const int j = si[q];
+        const bool in = j >= s0 && j < s0 + N;
+        med = (in && cnt == w) ? sv[q] : med;
+        cnt += in ? 1 : 0;
       }
+      if (i < n_bins) po[i] = psd_scale * (dt * dt) * med;
       wave_sync();
     }
   } else {
