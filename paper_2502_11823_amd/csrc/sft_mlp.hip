@@ -110,12 +110,25 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const T*
 // as gemm_kernel, each wavefront computing a 32 x 32 quarter of the 64 x 64 tile as 2 x 2
 // blocks of 16 x 16.  Operand layouts (checked with an in-bounds probe): A[i][k] in lane
 // i + 16 k, B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i / 4), element i % 4.
+// Epilogues of the training passes (EPI):
+//   kEpiPlain   C = op(A) op(B);
+//   kEpiBiasAct forward layer: z = C + bias[j] stored in C (the pre-activation), SiLU(z) in out2;
+//   kEpiActBack input gradient of the layer below: C = (op(A) op(B)) * SiLU'(Zb) with Zb = in2
+//               (that layer's pre-activations, ld = ldc);
+//   kEpiColSum  weight gradient with the bias gradient: the workgroups of the first row tile
+//               also sum the columns of B over their K slice into row M of their C plane
+//               (the plane holds (M + 1) rows: W then b, as the parameters are packed).
 typedef float flt4m __attribute__((ext_vector_type(4)));
+enum { kEpiPlain = 0, kEpiBiasAct = 1, kEpiActBack = 2, kEpiColSum = 3 };
 
-template <bool TA, bool TB>
+__device__ inline float sigm_f(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+template <bool TA, bool TB, int EPI = kEpiPlain>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, const float* __restrict__ A, int lda,
                                                         const float* __restrict__ B, int ldb, float* __restrict__ C,
-                                                        int ldc, int k_slice, int64_t c_plane)
+                                                        int ldc, int k_slice, int64_t c_plane,
+                                                        const float* __restrict__ in2 = nullptr,
+                                                        float* __restrict__ out2 = nullptr)
 {
   __shared__ float As[16][64 + 4];
   __shared__ float Bs[16][64 + 4];
@@ -130,6 +143,8 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = flt4m{0.0f, 0.0f, 0.0f, 0.0f};
+  const bool csum = EPI == kEpiColSum && blockIdx.y == 0;
+  float colsum = 0.0f;   // thread t < 64: column j0 + t of B over this K slice
   for (int k0 = kb; k0 < ke; k0 += 16) {
     for (int e = threadIdx.x; e < 1024; e += 256) {
       int ii, kk;
@@ -148,6 +163,10 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
       Bs[kk][jj] = v;
     }
     __syncthreads();
+    if (csum && threadIdx.x < 64) {
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) colsum += Bs[kk][threadIdx.x];
+    }
 #pragma unroll
     for (int k4 = 0; k4 < 16; k4 += 4) {
       const float a0 = As[k4 + lk][wi + li], a1 = As[k4 + lk][wi + 16 + li];
@@ -169,9 +188,34 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gi = i0 + wi + 16 * a + 4 * lk + v;
-        if (gi < M) Cp[(int64_t)gi * ldc + gj] = acc[a][b][v];
+        if (gi >= M) continue;
+        const int64_t o = (int64_t)gi * ldc + gj;
+        float c = acc[a][b][v];
+        if constexpr (EPI == kEpiBiasAct) {
+          c += in2[gj];
+          out2[o] = c * sigm_f(c);
+        } else if constexpr (EPI == kEpiActBack) {
+          const float z = in2[o];
+          const float sg = sigm_f(z);
+          c *= sg * (1.0f + z * (1.0f - sg));
+        }
+        Cp[o] = c;
       }
     }
+  if (csum && threadIdx.x < 64 && j0 + (int)threadIdx.x < N) Cp[(int64_t)M * ldc + j0 + threadIdx.x] = colsum;
+}
+
+// the training passes' fused GEMMs (epilogues above), one K slice except kEpiColSum
+template <bool TA, bool TB, int EPI>
+static hipError_t gemm_epi(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
+                           int splits, int64_t c_plane, const float* in2, float* out2, hipStream_t st)
+{
+  const int k_slice = ((K + splits - 1) / splits + 15) / 16 * 16;
+  const int z = (K + k_slice - 1) / k_slice;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, z);
+  hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, k_slice,
+                     c_plane, in2, out2);
+  return hipGetLastError();
 }
 
 // C = op(A) op(B) with k split into `splits` planes of C (plane stride c_plane); FP32 on the
@@ -214,17 +258,6 @@ static int gemm_planes(int K, int splits)
 template <typename T>
 __device__ inline T sigm(T z) { return (T)1 / ((T)1 + exp(-z)); }
 
-// training forward epilogue: Z += b (in place), H = SiLU(Z)
-__global__ void bias_silu_kernel(float* __restrict__ Z, float* __restrict__ H, const float* __restrict__ b, int64_t rows,
-                                 int n)
-{
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows * n) return;
-  const float z = Z[i] + b[i % n];
-  Z[i] = z;
-  H[i] = z * sigm(z);
-}
-
 // output layer: Y = Z + b, residual r = Y - T, loss partials per block, G = 2 r / batch
 __global__ void out_loss_kernel(const float* __restrict__ Z, const float* __restrict__ b, const float* __restrict__ Tg,
                                 int64_t rows, float inv_b2, float* __restrict__ G, double* __restrict__ part)
@@ -261,40 +294,16 @@ __global__ void sum_parts_kernel(const double* __restrict__ part, int n, double 
   if (threadIdx.x == 0) out[0] = (float)(red[0] * scale);
 }
 
-// backward through SiLU: G *= SiLU'(Z)
-__global__ void silu_back_kernel(float* __restrict__ G, const float* __restrict__ Z, int64_t count)
-{
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const float z = Z[i];
-  const float s = sigm(z);
-  G[i] *= s * (1.0f + z * (1.0f - s));
-}
-
-// sum of `planes` planes of `count` values into dst (fixed order)
+// sum of `planes` planes of `count` values into dst (fixed order; the loop is unrolled so that
+// many planes' loads are in flight at once, the additions keep their order)
 __global__ void sum_planes_kernel(const float* __restrict__ src, int planes, int64_t count, float* __restrict__ dst)
 {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   float s = 0.f;
+#pragma unroll 16
   for (int p = 0; p < planes; ++p) s += src[(int64_t)p * count + i];
   dst[i] = s;
-}
-
-// db[j] = sum_r G[r][j], one workgroup per column (fixed-order tree)
-__global__ void col_sum_kernel(const float* __restrict__ G, int64_t rows, int n, float* __restrict__ db)
-{
-  __shared__ float red[256];
-  const int j = blockIdx.x;
-  float s = 0.f;
-  for (int64_t r = threadIdx.x; r < rows; r += 256) s += G[r * n + j];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) db[j] = red[0];
 }
 
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
@@ -786,7 +795,7 @@ struct TrainBuf {
 
 static size_t train_bytes(int H, int L, int64_t B, int splits)
 {
-  size_t f = (size_t)(L + 1) * B * H * 2 + (size_t)B * H * 2 + (size_t)splits * H * H;
+  size_t f = (size_t)(L + 1) * B * H * 2 + (size_t)B * H * 2 + (size_t)splits * (H + 1) * H;
   return f * sizeof(float) + (size_t)nblk(B * 2) * sizeof(double) + 1024;
 }
 
@@ -802,12 +811,18 @@ static void train_layout(void* ws, int H, int L, int64_t B, int splits, TrainBuf
   t.G2 = f;
   f += (size_t)B * H;
   t.plane = f;
-  f += (size_t)splits * H * H;
+  f += (size_t)splits * (H + 1) * H;
   t.part = (double*)(((uintptr_t)f + 255) / 256 * 256);
   t.splits = splits;
 }
 
-// loss (mean over the batch of the summed squared residuals) and its gradient into s->grad
+// loss (mean over the batch of the summed squared residuals) and its gradient into s->grad.
+// Forward: each hidden layer's GEMM adds the bias and applies SiLU in its epilogue (keeping the
+// pre-activations Z for the backward pass).  Backward, layer l from the output down, with G =
+// dL/dZ_l: the weight-gradient GEMM Hl^T G in K slices, whose first row tile also sums the
+// columns of G (the bias gradient) into the row after W of each slice; the slices are summed in
+// fixed order straight into W and b of the gradient (packed W then b); and the input-gradient
+// GEMM G W^T with SiLU'(Z_{l-1}) in its epilogue gives dL/dZ_{l-1}.
 static hipError_t loss_grad(sft_surrogate* s, const float* U, const float* Tg, int64_t B, float* loss, TrainBuf& t,
                             hipStream_t st)
 {
@@ -818,45 +833,42 @@ static hipError_t loss_grad(sft_surrogate* s, const float* U, const float* Tg, i
   for (int l = 0; l <= L; ++l) {
     const MlpLayer ly = mlp_layer(H, L, l);
     float* Z = t.Z + (size_t)l * B * H;
-    if ((e = gemm(false, false, (int)B, ly.n_out, ly.n_in, hin, ly.n_in, s->par + ly.w_off, ly.n_out, Z,
-                         ly.n_out, 1, 0, st)) != hipSuccess)
-      return e;
     if (l < L) {
       float* Hn = t.Hs + (size_t)(l + 1) * B * H;
-      hipLaunchKernelGGL(bias_silu_kernel, dim3(nblk(B * ly.n_out)), dim3(256), 0, st, Z, Hn, s->par + ly.b_off, B,
-                         ly.n_out);
+      if ((e = gemm_epi<false, false, kEpiBiasAct>((int)B, ly.n_out, ly.n_in, hin, ly.n_in, s->par + ly.w_off,
+                                                    ly.n_out, Z, ly.n_out, 1, 0, s->par + ly.b_off, Hn, st)) !=
+          hipSuccess)
+        return e;
       hin = Hn;
     } else {
+      if ((e = gemm(false, false, (int)B, ly.n_out, ly.n_in, hin, ly.n_in, s->par + ly.w_off, ly.n_out, Z, ly.n_out,
+                    1, 0, st)) != hipSuccess)
+        return e;
       hipLaunchKernelGGL(out_loss_kernel, dim3(nblk(B * 2)), dim3(256), 0, st, Z, s->par + ly.b_off, Tg, B,
                          2.0f / (float)B, t.G, t.part);
       hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, st, t.part, (int)nblk(B * 2), 1.0 / (double)B, loss);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  // backward: t.G holds dL/dY [B][2]
+  // backward: t.G holds dL/dY = dL/dZ_L [B][2]
   float* G = t.G;
   float* Gn = t.G2;
   for (int l = L; l >= 0; --l) {
     const MlpLayer ly = mlp_layer(H, L, l);
     const float* Hl = l == 0 ? U : t.Hs + (size_t)l * B * H;
-    if (l < L) {
-      hipLaunchKernelGGL(silu_back_kernel, dim3(nblk(B * ly.n_out)), dim3(256), 0, st, G, t.Z + (size_t)l * B * H,
-                         B * ly.n_out);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    // dW = Hl^T G  (K = B, split into planes), db = column sums of G
+    // dW = Hl^T G and db = column sums of G, per K slice ((n_in + 1) x n_out planes)
     const int planes = gemm_planes((int)B, t.splits);
-    if ((e = gemm(true, false, ly.n_in, ly.n_out, (int)B, Hl, ly.n_in, G, ly.n_out, t.plane, ly.n_out,
-                         t.splits, (int64_t)ly.n_in * ly.n_out, st)) != hipSuccess)
+    const int64_t pc = (int64_t)(ly.n_in + 1) * ly.n_out;
+    if ((e = gemm_epi<true, false, kEpiColSum>(ly.n_in, ly.n_out, (int)B, Hl, ly.n_in, G, ly.n_out, t.plane,
+                                                ly.n_out, t.splits, pc, nullptr, nullptr, st)) != hipSuccess)
       return e;
-    hipLaunchKernelGGL(sum_planes_kernel, dim3(nblk((int64_t)ly.n_in * ly.n_out)), dim3(256), 0, st, t.plane, planes,
-                       (int64_t)ly.n_in * ly.n_out, s->grad + ly.w_off);
-    hipLaunchKernelGGL(col_sum_kernel, dim3(ly.n_out), dim3(256), 0, st, G, B, ly.n_out, s->grad + ly.b_off);
+    hipLaunchKernelGGL(sum_planes_kernel, dim3(nblk(pc)), dim3(256), 0, st, t.plane, planes, pc, s->grad + ly.w_off);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (l > 0) {
-      // G_prev = G W^T
-      if ((e = gemm(false, true, (int)B, ly.n_in, ly.n_out, G, ly.n_out, s->par + ly.w_off, ly.n_out, Gn,
-                           ly.n_in, 1, 0, st)) != hipSuccess)
+      // dL/dZ_{l-1} = (G W^T) * SiLU'(Z_{l-1})
+      if ((e = gemm_epi<false, true, kEpiActBack>((int)B, ly.n_in, ly.n_out, G, ly.n_out, s->par + ly.w_off,
+                                                   ly.n_out, Gn, ly.n_in, 1, 0, t.Z + (size_t)(l - 1) * B * H,
+                                                   nullptr, st)) != hipSuccess)
         return e;
       std::swap(G, Gn);
     }
