@@ -142,7 +142,8 @@ typedef struct {
 
 /*
  * sft_make_sfts -- the SFTs and PSDs of every segment, asynchronously on hip_stream (returns
- * after the launch has been enqueued and its small host uploads are done).
+ * once the launch is enqueued; a device's first call for a segment length also builds that
+ * length's twiddle tables, tens of KB, and keeps them on the device until the process ends).
  *   x    : DEVICE [n_det][n_total] strain series (FP64), read only.
  *   bins : DEVICE out [n_det][n_seg][n_bins][2] x~ = dt sum_j x_j e^{-2 pi i j k / n} of the band.
  *   psd  : DEVICE out [n_det][n_seg][n_bins] the estimated one-sided PSD.

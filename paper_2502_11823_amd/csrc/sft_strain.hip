@@ -3,9 +3,9 @@
 // own periodogram), gaps detected as segments holding a non-finite sample.
 //
 // strain_sft_kernel: one workgroup per segment of n = 2M samples.  The real series is taken as
-// M complex points z[m] = x[2m] + i x[2m+1], loaded in bit-reversed order into LDS and
-// transformed in place by log2(M) radix-2 decimation-in-time stages (FP64); the n/2 + 1 bins of
-// the real transform follow from Z[k] and conj(Z[M - k]):
+// M complex points z[m] = x[2m] + i x[2m+1], loaded in natural order into LDS and transformed
+// in place by radix-8 decimation-in-frequency passes (FP64); the n/2 + 1 bins of the real
+// transform follow from Z[k] and conj(Z[M - k]):
 //   X[k] = (Z[k] + conj(Z[M-k])) / 2 - i e^{-2 pi i k / n} (Z[k] - conj(Z[M-k])) / 2.
 // The band bins are written as dt X[k]; the PSD of band bin k is 2 median(P) / (T B) over the
 // block of N = 2w+1 periodogram values P[j] = |dt X[j]|^2 centred on k (shifted at the ends of
@@ -16,6 +16,9 @@
 
 #include <cmath>
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "../../include/sft.h"
@@ -31,20 +34,18 @@ __device__ inline double2 cmul(double2 a, double2 b)
   return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
 
-__device__ inline double pw(const double2* X, int j)
-{
-  const double2 v = X[j];
-  return fma(v.x, v.x, v.y * v.y);
-}
-
 // Median of each lane's block by a wavefront-wide sort: the 64 lanes of a wavefront take 64
 // consecutive band bins, whose blocks of 2w+1 periodogram values lie in a union of at most
 // 64 + 2w <= 128 bins.  The union's (value, bin) pairs are sorted once per wavefront by a
-// bitonic network in the wavefront's LDS slot (one compare-exchange per lane and stage), then
-// every lane walks the sorted list and stops at the (w+1)-th entry that falls in its block:
-// the block's middle element in (value, bin) order, as a sort of the block itself gives.
+// bitonic network in the wavefront's LDS slot (one compare-exchange per lane and stage, the
+// 28 stages unrolled and free of branches), then every lane walks the sorted list and stops at
+// the (w+1)-th entry that falls in its block: the block's middle element in (value, bin) order,
+// as a sort of the block itself gives.
 constexpr int kSortN = 128;
 constexpr int kMaxSortW = (kSortN - 64) / 2;   // w <= 32
+// LDS bytes of the sort slots of a workgroup: kSortN values and kSortN bins (relative to the
+// union's first bin) per wavefront
+constexpr int kSortBytes = kStrainBlock / 64 * kSortN * (int)(sizeof(double) + sizeof(int));
 
 __device__ inline void wave_sync()
 {
@@ -55,120 +56,266 @@ __device__ inline void wave_sync()
 
 __device__ inline bool pair_less(double va, int ia, double vb, int ib)
 {
-  return va < vb || (va == vb && ia < ib);
+  return (va < vb) | ((va == vb) & (ia < ib));   // no short circuit: selects, not branches
 }
 
-__global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
-    const double* __restrict__ x, int64_t n_total, int32_t n_seg, int32_t logM, double dt, int32_t w, double psd_scale,
-    int32_t k_lo, int32_t n_bins, int32_t staged, double s_white, const double2* __restrict__ tw,
-    const double2* __restrict__ rtw, double* __restrict__ bins, double* __restrict__ psd, int32_t* __restrict__ keep)
+// Transform of the M = 2^LOGM complex points in LDS (natural order in, digit-reversed out), as
+// in-place decimation-in-frequency passes of radix 8 (and one of radix 2 or 4 for the leftover
+// bits).  Before pass i the data are M / L independent sub-transforms of length L = M / 8^i,
+// each contiguous; with L = R L', the work item (g, n1) of sub-transform g reads its R points
+// n1 + L' n2, forms their R-point DFT in registers, multiplies output k2 by W_L^{n1 k2} and
+// writes it back to the position it read point n2 = k2 from: sub-transform g R + k2, of length
+// L', holds the outputs R k1 + k2 of sub-transform g (its k1-th output after the later passes).
+// So X[k] ends at position pos(k), the digits of k (radix 8 from the least significant end)
+// in reverse order.
+template <int LOGM>
+struct FftShape {
+  static constexpr int M = 1 << LOGM;
+  static constexpr int NP = (LOGM + 2) / 3;                              // passes
+  static constexpr int lr(int i) { return i < LOGM / 3 ? 3 : LOGM % 3; }  // log2 of pass i's radix
+};
+
+// LDS slot of point i: the 16 points of an aligned run (one pass over the 64 banks, 16 bytes
+// each) are permuted by an XOR of higher index bits, so that the strided accesses of the later
+// passes and the digit-reversed reads of the unfolding spread over the banks (a model of the
+// 16-lane groups of a 16-byte LDS read puts their mean conflict degree at ~1.3 instead of ~4.3
+// for M = 2048).  A bijection on each run, the identity for M <= 16.
+__device__ inline int swz(int i) { return i ^ (((i >> 4) ^ (i >> 7) ^ (i >> 8)) & 15); }
+
+template <int LOGM>
+__device__ inline int fft_pos(int k)
 {
-  // LDS: buf[M + 1] complex; with staged = 1 a region of M + 1 doubles after it, holding the
-  // twiddles during the transform and the periodogram afterwards
+  int p = 0;
+#pragma unroll
+  for (int i = 0; i < FftShape<LOGM>::NP; ++i) {
+    const int l = FftShape<LOGM>::lr(i);
+    p |= ((k >> (3 * i)) & ((1 << l) - 1)) << (LOGM - 3 * i - l);
+  }
+  return p;
+}
+
+// in-place R-point DFT, v[k] <- sum_n v[n] e^{-2 pi i n k / R}, R = 2, 4 or 8
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 mul_mi(double2 a) { return make_double2(a.y, -a.x); }   // times -i
+
+__device__ inline void dft4(double2& u0, double2& u1, double2& u2, double2& u3)
+{
+  const double2 c0 = cadd(u0, u2), c1 = csub(u0, u2), c2 = cadd(u1, u3), c3 = mul_mi(csub(u1, u3));
+  u0 = cadd(c0, c2);
+  u1 = cadd(c1, c3);
+  u2 = csub(c0, c2);
+  u3 = csub(c1, c3);
+}
+
+template <int R>
+__device__ inline void dft_small(double2* v)
+{
+  if constexpr (R == 2) {
+    const double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    dft4(v[0], v[1], v[2], v[3]);
+  } else {
+    // radix-2 split: even outputs from a_n = v_n + v_{n+4}, odd ones from
+    // b_n = (v_n - v_{n+4}) e^{-2 pi i n / 8}, each by a 4-point DFT
+    constexpr double c = 0.70710678118654752440;
+    double2 a[4], b[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      a[n] = cadd(v[n], v[n + 4]);
+      b[n] = csub(v[n], v[n + 4]);
+    }
+    b[1] = make_double2(c * (b[1].x + b[1].y), c * (b[1].y - b[1].x));
+    b[2] = mul_mi(b[2]);
+    b[3] = make_double2(c * (b[3].y - b[3].x), -c * (b[3].x + b[3].y));
+    dft4(a[0], a[1], a[2], a[3]);
+    dft4(b[0], b[1], b[2], b[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[2 * k] = a[k];
+      v[2 * k + 1] = b[k];
+    }
+  }
+}
+
+template <int LOGM, int I>
+__device__ inline void fft_pass(double2* buf, const double2* __restrict__ tw, int tid)
+{
+  constexpr int M = 1 << LOGM;
+  constexpr int LR = FftShape<LOGM>::lr(I), R = 1 << LR;
+  constexpr int LOGL = LOGM - 3 * I, L = 1 << LOGL, LP = L >> LR;
+#pragma unroll
+  for (int t0 = 0; t0 < M / R; t0 += kStrainBlock) {
+    const int t = t0 + tid;
+    if (M / R % kStrainBlock == 0 || t < M / R) {
+      const int g = t >> (LOGL - LR), n1 = t & (LP - 1);
+      const int base = g * L + n1;
+      // W_L^{n1 k2} = W_M^{(M / L) n1 k2}; tw holds W_M^j for j < M / 2, W_M^{j + M/2} = -W_M^j.
+      // The twiddle loads are issued first, so that their latency overlaps the LDS reads and
+      // the R-point DFT.
+      double2 wv[R];
+      if constexpr (LP > 1) {
+#pragma unroll
+        for (int k2 = 1; k2 < R; ++k2) wv[k2] = tw[((n1 * k2) << (LOGM - LOGL)) & (M / 2 - 1)];
+      }
+      double2 v[R];
+#pragma unroll
+      for (int n2 = 0; n2 < R; ++n2) v[n2] = buf[swz(base + LP * n2)];
+      dft_small<R>(v);
+      if constexpr (LP > 1) {
+#pragma unroll
+        for (int k2 = 1; k2 < R; ++k2) {
+          const double sg = (((n1 * k2) << (LOGM - LOGL)) & (M / 2)) ? -1.0 : 1.0;
+          v[k2] = cmul(v[k2], make_double2(sg * wv[k2].x, sg * wv[k2].y));
+        }
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < R; ++k2) buf[swz(base + LP * k2)] = v[k2];
+    }
+  }
+  __syncthreads();
+  if constexpr (I + 1 < FftShape<LOGM>::NP) fft_pass<LOGM, I + 1>(buf, tw, tid);
+}
+
+// One workgroup per segment of n = 2M samples.  LDS: the M complex points (buf), then, once the
+// spectrum is in registers, the M + 1 periodogram values over it, the median's sort slots at
+// byte sort_off and one gap flag per wavefront at byte flag_off.  A segment with a non-finite
+// sample is transformed like any other (the values are discarded) and its gap is found after
+// the transform, so that no LDS word has to stay reserved through it.
+template <int LOGM>
+__global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
+    const double* __restrict__ x, int64_t n_total, int32_t n_seg, double dt, int32_t w, double psd_scale,
+    int32_t k_lo, int32_t n_bins, double s_white, const double2* __restrict__ tw, const double2* __restrict__ rtw,
+    double* __restrict__ bins, double* __restrict__ psd, int32_t* __restrict__ keep, int32_t sort_off,
+    int32_t flag_off)
+{
+  constexpr int M = 1 << LOGM;
   extern __shared__ double2 buf[];
-  __shared__ int s_bad;
-  __shared__ double s_val[kStrainBlock / 64][kSortN];
-  __shared__ int s_idx[kStrainBlock / 64][kSortN];
-  const int M = 1 << logM;
-  double* U = reinterpret_cast<double*>(buf + M + 1);
-  double2* tws = reinterpret_cast<double2*>(U);
+  double* U = reinterpret_cast<double*>(buf);   // the periodogram, after the transform
   const int row = blockIdx.x;
   const int det = row / n_seg, seg = row - det * n_seg;
   const double* xs = x + (int64_t)det * n_total + (int64_t)seg * 2 * M;
   const int tid = threadIdx.x;
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
   bool bad = false;
-  // z[m] = x[2m] + i x[2m+1]: one 16-byte load per point where the segment is 16-byte aligned
-  if ((reinterpret_cast<uintptr_t>(xs) & 15) == 0) {
+  // z[m] = x[2m] + i x[2m+1] (one 16-byte load per point where the segment is 16-byte
+  // aligned), in batches of up to 8 points per thread whose loads are all issued before the
+  // first is used
+  {
+    constexpr int NL = (M + kStrainBlock - 1) / kStrainBlock, NB = NL < 8 ? NL : 8;
+    const bool al = (reinterpret_cast<uintptr_t>(xs) & 15) == 0;
     const double2* xs2 = reinterpret_cast<const double2*>(xs);
-    for (int m = tid; m < M; m += blockDim.x) {
-      const double2 z = xs2[m];
-      bad = bad || !isfinite(z.x) || !isfinite(z.y);
-      buf[(int)(__brev((unsigned)m) >> (32 - logM))] = z;
-    }
-  } else {
-    for (int m = tid; m < M; m += blockDim.x) {
-      const double re = xs[2 * m], im = xs[2 * m + 1];
-      bad = bad || !isfinite(re) || !isfinite(im);
-      buf[(int)(__brev((unsigned)m) >> (32 - logM))] = make_double2(re, im);
+#pragma unroll
+    for (int r0 = 0; r0 < NL; r0 += NB) {
+      double2 z[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const int m = tid + (r0 + r) * kStrainBlock;
+        if (M % kStrainBlock == 0 || m < M) z[r] = al ? xs2[m] : make_double2(xs[2 * m], xs[2 * m + 1]);
+      }
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const int m = tid + (r0 + r) * kStrainBlock;
+        if (M % kStrainBlock == 0 || m < M) {
+          bad |= !(isfinite(z[r].x) && isfinite(z[r].y));
+          buf[swz(m)] = z[r];
+        }
+      }
     }
   }
-  if (staged)
-    for (int j = tid; j < M / 2; j += blockDim.x) tws[j] = tw[j];
-  if (bad) s_bad = 1;
   __syncthreads();
   double* bo = bins + (int64_t)row * 2 * n_bins;
   double* po = psd + (int64_t)row * n_bins;
-  if (s_bad) {
-    for (int i = tid; i < n_bins; i += blockDim.x) {
-      bo[2 * i] = 0.0;
-      bo[2 * i + 1] = 0.0;
-      po[i] = 0.0;
-    }
-    if (tid == 0) keep[row] = 0;
-    return;
+  fft_pass<LOGM, 0>(buf, tw, tid);
+  // real-transform bins, pair (k, M - k) per work item; rtw[k] = e^{-2 pi i k / n}, k <= M/2.
+  // The band bins go out as dt X[k]; the periodogram |X[k]|^2 stays in registers until every
+  // item has read the spectrum, then overlays it in LDS.
+  constexpr int NPAIR = (M / 2 + kStrainBlock) / kStrainBlock;   // ceil((M/2 + 1) / block)
+  double pk[NPAIR], pm[NPAIR];
+  double2 rtk[NPAIR];
+#pragma unroll
+  for (int r = 0; r < NPAIR; ++r) {
+    const int k = tid + r * kStrainBlock;
+    rtk[r] = rtw[k <= M / 2 ? k : M / 2];   // all issued before the first is used
   }
-  // radix-2 stages; tw[j] = e^{-2 pi i j / M}, j < M / 2
-  const double2* twp = staged ? tws : tw;
-  for (int s = 1; s <= logM; ++s) {
-    const int half = 1 << (s - 1);
-    const int tstride = M >> s;
-    for (int b = tid; b < M / 2; b += blockDim.x) {
-      const int k = b & (half - 1);
-      const int i = ((b >> (s - 1)) << s) + k;
-      const double2 u = buf[i];
-      const double2 v = cmul(buf[i + half], twp[k * tstride]);
-      buf[i] = make_double2(u.x + v.x, u.y + v.y);
-      buf[i + half] = make_double2(u.x - v.x, u.y - v.y);
-    }
-    __syncthreads();
-  }
-  // real-transform bins, in place, pair (k, M - k) per thread; rtw[k] = e^{-2 pi i k / n}, k <= M/2
-  for (int k = tid; k <= M / 2; k += blockDim.x) {
-    const int kk = (M - k) & (M - 1);  // M - k, with Z[M] = Z[0]
-    const double2 a = buf[k], b = buf[kk];
-    // X[k]
-    const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));   // (Z[k] + conj Z[M-k]) / 2
-    const double2 o = make_double2(0.5 * (a.x - b.x), 0.5 * (a.y + b.y));   // (Z[k] - conj Z[M-k]) / 2
-    const double2 ro = cmul(rtw[k], o);
-    const double2 Xk = make_double2(e.x + ro.y, e.y - ro.x);                // e - i ro
-    // X[M - k] from the same pair with the roles exchanged: e' = conj(e), o' = -conj(o),
-    // e^{-2 pi i (M-k)/n} = -conj(e^{-2 pi i k / n})
-    const double2 rc = make_double2(-rtw[k].x, rtw[k].y);
-    const double2 o2 = make_double2(-o.x, o.y);
-    const double2 ro2 = cmul(rc, o2);
-    const double2 Xm = make_double2(e.x + ro2.y, -e.y - ro2.x);
-    if (k == 0) {
-      buf[0] = Xk;
-      buf[M] = Xm;   // Nyquist bin
-    } else if (2 * k == M) {
-      buf[k] = Xk;   // the pair's two members coincide
-    } else {
-      buf[k] = Xk;
-      buf[M - k] = Xm;
+#pragma unroll
+  for (int r = 0; r < NPAIR; ++r) {
+    const int k = tid + r * kStrainBlock;
+    pk[r] = pm[r] = 0.0;
+    if (k <= M / 2) {
+      const int kk = (M - k) & (M - 1);  // M - k, with Z[M] = Z[0]
+      const double2 a = buf[swz(fft_pos<LOGM>(k))], b = buf[swz(fft_pos<LOGM>(kk))];
+      const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));   // (Z[k] + conj Z[M-k]) / 2
+      const double2 o = make_double2(0.5 * (a.x - b.x), 0.5 * (a.y + b.y));   // (Z[k] - conj Z[M-k]) / 2
+      const double2 rt = rtk[r];
+      const double2 ro = cmul(rt, o);
+      const double2 Xk = make_double2(e.x + ro.y, e.y - ro.x);                // e - i ro
+      // X[M - k] from the same pair with the roles exchanged: e' = conj(e), o' = -conj(o),
+      // e^{-2 pi i (M-k)/n} = -conj(e^{-2 pi i k / n})
+      const double2 ro2 = cmul(make_double2(-rt.x, rt.y), make_double2(-o.x, o.y));
+      const double2 Xm = make_double2(e.x + ro2.y, -e.y - ro2.x);
+      const int im = M - k - k_lo;   // band index of X[M - k] (the Nyquist bin for k = 0)
+      if (k - k_lo >= 0 && k - k_lo < n_bins) {
+        bo[2 * (k - k_lo)] = dt * Xk.x;
+        bo[2 * (k - k_lo) + 1] = dt * Xk.y;
+      }
+      if (2 * k != M && im >= 0 && im < n_bins) {
+        bo[2 * im] = dt * Xm.x;
+        bo[2 * im + 1] = dt * Xm.y;
+      }
+      pk[r] = fma(Xk.x, Xk.x, Xk.y * Xk.y);
+      pm[r] = fma(Xm.x, Xm.x, Xm.y * Xm.y);
     }
   }
   __syncthreads();
-  if (staged) {
-    // the periodogram, over the twiddles (the transform is done)
-    for (int j = tid; j <= M; j += blockDim.x) U[j] = pw(buf, j);
-    __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NPAIR; ++r) {
+    const int k = tid + r * kStrainBlock;
+    if (k <= M / 2) {
+      U[k] = pk[r];
+      if (2 * k != M) U[M - k] = pm[r];
+    }
   }
-  for (int i = tid; i < n_bins; i += blockDim.x) {
-    const double2 v = buf[k_lo + i];
-    bo[2 * i] = dt * v.x;
-    bo[2 * i + 1] = dt * v.y;
+  int* gap = reinterpret_cast<int*>(reinterpret_cast<char*>(buf) + flag_off);
+  const bool wave_bad = __ballot(bad) != 0;
+  if ((tid & 63) == 0) gap[tid >> 6] = wave_bad ? 1 : 0;
+  __syncthreads();
+  bool seg_bad = false;
+#pragma unroll
+  for (int v = 0; v < kStrainBlock / 64; ++v) seg_bad = seg_bad || gap[v] != 0;
+  if (seg_bad) {
+    // a gap: zeros over the band bins this thread wrote above (same addresses, same thread, so
+    // the zeros land last), a zero PSD and keep = 0
+#pragma unroll
+    for (int r = 0; r < NPAIR; ++r) {
+      const int k = tid + r * kStrainBlock;
+      if (k <= M / 2) {
+        const int im = M - k - k_lo;
+        if (k - k_lo >= 0 && k - k_lo < n_bins) {
+          bo[2 * (k - k_lo)] = 0.0;
+          bo[2 * (k - k_lo) + 1] = 0.0;
+        }
+        if (2 * k != M && im >= 0 && im < n_bins) {
+          bo[2 * im] = 0.0;
+          bo[2 * im + 1] = 0.0;
+        }
+      }
+    }
+    for (int i = tid; i < n_bins; i += kStrainBlock) po[i] = 0.0;
+    if (tid == 0) keep[row] = 0;
+    return;
   }
-  auto P = [&](int j) { return staged ? U[j] : pw(buf, j); };
+  auto P = [&](int j) { return U[j]; };
   const int N = 2 * w + 1;
   if (s_white > 0.0) {
     // a known white PSD: no estimate
     for (int i = tid; i < n_bins; i += blockDim.x) po[i] = s_white;
   } else if (w <= kMaxSortW) {
     const int lane = tid & 63, wv = tid >> 6;
-    double* sv = s_val[wv];
-    int* si = s_idx[wv];
+    double* sv = reinterpret_cast<double*>(reinterpret_cast<char*>(buf) + sort_off) + wv * kSortN;
+    int* si = reinterpret_cast<int*>(reinterpret_cast<char*>(buf) + sort_off + (kStrainBlock / 64) * kSortN * 8) +
+              wv * kSortN;
     // every wavefront walks its chunks of 64 band bins (wave-uniform loop)
     for (int c0 = wv * 64; c0 < n_bins; c0 += blockDim.x) {
       const int kb = k_lo + c0;
@@ -181,11 +328,16 @@ __global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
       const int L = u1 + N - u0;                // <= 64 + 2w <= kSortN
       for (int q = lane; q < kSortN; q += 64) {
         sv[q] = q < L ? P(u0 + q) : INFINITY;
-        si[q] = q < L ? u0 + q : 0x7fffffff;
+        si[q] = q < L ? q : 0x7fffffff;
       }
       wave_sync();
-      // bitonic sort of the kSortN pairs: lane l compare-exchanges one pair per stage
+      // bitonic sort of the kSortN pairs: lane l compare-exchanges one pair per stage.  The
+      // pairs of a stage are disjoint, so each lane writes both members back (exchanged or
+      // not) right after reading them; the sync orders the stage's writes before the next
+      // stage's reads.
+#pragma unroll
       for (int size = 2; size <= kSortN; size <<= 1) {
+#pragma unroll
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
           const int q = 2 * lane - (lane & (stride - 1));   // lower index of lane's pair
           const int r = q + stride;
@@ -193,33 +345,39 @@ __global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
           const double vq = sv[q], vr = sv[r];
           const int iq = si[q], ir = si[r];
           const bool swap = up ? pair_less(vr, ir, vq, iq) : pair_less(vq, iq, vr, ir);
-          wave_sync();
-          if (swap) {
-            sv[q] = vr;
-            si[q] = ir;
-            sv[r] = vq;
-            si[r] = iq;
-          }
+          sv[q] = swap ? vr : vq;
+          si[q] = swap ? ir : iq;
+          sv[r] = swap ? vq : vr;
+          si[r] = swap ? iq : ir;
           wave_sync();
         }
       }
       // every lane counts, along the sorted list, the entries inside its own block; its median
-      // is the entry at which that count reaches w + 1.  The list is read as broadcasts in a
-      // wave-uniform loop without an early exit, so the reads pipeline.
+      // is the entry at which that count reaches w + 1.  The bins are read as broadcasts, four
+      // per read, in a wave-uniform loop without an early exit (the pads past L are in no
+      // block), and the lane keeps the list position of its median, whose value it reads last.
       const int i = c0 + lane;
       const int k = k_lo + i;
       int s0 = k - w;
       s0 = s0 < 0 ? 0 : s0;
       s0 = s0 + 2 * w > M ? M - 2 * w : s0;
-      int cnt = 0;
-      double med = 0.0;
-#pragma unroll 8
-      for (int q = 0; q < L; ++q) {
-        const int j = si[q];
-        const bool in = j >= s0 && j < s0 + N;
-        med = (in && cnt == w) ? sv[q] : med;
-        cnt += in ? 1 : 0;
+      const unsigned s0r = (unsigned)(s0 - u0);   // the block's first bin in the union
+      int cnt = 0, mq = 0;
+      const int4* si4 = reinterpret_cast<const int4*>(si);
+#pragma unroll 4
+      for (int q4 = 0; q4 < (L + 3) / 4; ++q4) {
+        const int4 j4 = si4[q4];
+        auto step = [&](int j, int q) {
+          const bool in = (unsigned)j - s0r < (unsigned)N;
+          mq = (in && cnt == w) ? q : mq;
+          cnt += in ? 1 : 0;
+        };
+        step(j4.x, 4 * q4);
+        step(j4.y, 4 * q4 + 1);
+        step(j4.z, 4 * q4 + 2);
+        step(j4.w, 4 * q4 + 3);
       }
+      const double med = sv[mq];
       if (i < n_bins) po[i] = psd_scale * (dt * dt) * med;
       wave_sync();
     }
@@ -317,6 +475,70 @@ __global__ __launch_bounds__(kStrainBlock) void strain_dft_kernel(
 
 static sft_status strain_fail(sft_status st, const char* msg) { return sft_set_error(st, msg); }
 
+// Twiddle tables of a segment length n, in long double rounded once to FP64: for n a power of
+// two, tw[j] = e^{-2 pi i j / M} (j < M/2, M = n/2) and rtw[k] = e^{-2 pi i k / n} (k <= M/2);
+// otherwise W[m] = e^{-2 pi i m / n} (m < n).  Built on a device's first call for n and kept
+// there until the process ends (tens of KB per length), so that later calls only launch.
+struct TwTables {
+  double2* tw = nullptr;
+  double2* rtw = nullptr;
+  double2* W = nullptr;
+};
+
+static hipError_t upload(const std::vector<double2>& h, double2** d)
+{
+  hipError_t e = hipMalloc((void**)d, h.size() * sizeof(double2));
+  if (e == hipSuccess) e = hipMemcpy(*d, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice);
+  if (e != hipSuccess && *d) {
+    (void)hipFree(*d);
+    *d = nullptr;
+  }
+  return e;
+}
+
+static hipError_t twiddle_tables(int n, TwTables& out)
+{
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, TwTables> cache;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = cache.find({dev, n});
+  if (it != cache.end()) {
+    out = it->second;
+    return hipSuccess;
+  }
+  const long double pi = 3.141592653589793238462643383279502884L;
+  TwTables t;
+  if ((n & (n - 1)) != 0) {
+    std::vector<double2> W(n);
+    for (int m = 0; m < n; ++m) {
+      const long double a = -2.0L * pi * (long double)m / (long double)n;
+      W[m] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    e = upload(W, &t.W);
+  } else {
+    const int M = n / 2;
+    std::vector<double2> tw(M / 2 > 0 ? M / 2 : 1), rtw(M / 2 + 1);
+    for (int j = 0; j < M / 2; ++j) {
+      const long double a = -2.0L * pi * (long double)j / (long double)M;
+      tw[j] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    for (int k = 0; k <= M / 2; ++k) {
+      const long double a = -2.0L * pi * (long double)k / (long double)n;
+      rtw[k] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    e = upload(tw, &t.tw);
+    if (e == hipSuccess) e = upload(rtw, &t.rtw);
+    if (e != hipSuccess && t.tw) (void)hipFree(t.tw);
+  }
+  if (e != hipSuccess) return e;
+  cache[{dev, n}] = t;
+  out = t;
+  return hipSuccess;
+}
+
 extern "C" sft_status sft_make_sfts(const sft_strain_desc* d, const double* x, double* bins, double* psd, int32_t* keep,
                                     void* hip_stream)
 {
@@ -337,67 +559,64 @@ extern "C" sft_status sft_make_sfts(const sft_strain_desc* d, const double* x, d
   const int64_t n_seg = d->n_total / n;
   if (n_seg * d->n_det > INT32_MAX) return strain_fail(SFT_E_RANGE, "sft_make_sfts: too many segments");
   hipStream_t st = (hipStream_t)hip_stream;
-  const long double pi = 3.141592653589793238462643383279502884L;
+  TwTables tt;
+  hipError_t e = twiddle_tables(n, tt);
+  if (e != hipSuccess) return strain_fail(SFT_E_DEVICE, hipGetErrorString(e));
   if (!pow2) {
-    std::vector<double2> W(n);
-    for (int m = 0; m < n; ++m) {
-      const long double a = -2.0L * pi * (long double)m / (long double)n;
-      W[m] = make_double2((double)cosl(a), (double)sinl(a));
-    }
-    double2* d_W = nullptr;
-    hipError_t e = hipMallocAsync((void**)&d_W, n * sizeof(double2), st);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_W, W.data(), n * sizeof(double2), hipMemcpyHostToDevice, st);
     const size_t lds = (size_t)n * sizeof(double);
-    if (e == hipSuccess && lds > 65536)
+    if (lds > 65536)
       e = hipFuncSetAttribute((const void*)strain_dft_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess && n_seg > 0) {
       hipLaunchKernelGGL(strain_dft_kernel, dim3((unsigned)(n_seg * d->n_det)), dim3(kStrainBlock), lds, st, x,
-                         d->n_total, (int32_t)n_seg, n, d->dt, d->s_white, d->k_lo, d->n_bins, d_W, bins, psd, keep);
+                         d->n_total, (int32_t)n_seg, n, d->dt, d->s_white, d->k_lo, d->n_bins, tt.W, bins, psd, keep);
       e = hipGetLastError();
     }
-    hipError_t e2 = hipStreamSynchronize(st);   // W is read by the upload
-    if (d_W) (void)hipFreeAsync(d_W, st);
-    if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return strain_fail(SFT_E_DEVICE, hipGetErrorString(e));
     return SFT_OK;
   }
   int logM = 0;
   while ((1 << logM) < M) ++logM;
-  // twiddles in long double, rounded once
-  std::vector<double2> tw(M / 2 > 0 ? M / 2 : 1), rtw(M / 2 + 1);
-  for (int j = 0; j < M / 2; ++j) {
-    const long double a = -2.0L * pi * (long double)j / (long double)M;
-    tw[j] = make_double2((double)cosl(a), (double)sinl(a));
-  }
-  for (int k = 0; k <= M / 2; ++k) {
-    const long double a = -2.0L * pi * (long double)k / (long double)n;
-    rtw[k] = make_double2((double)cosl(a), (double)sinl(a));
-  }
+  double2* d_tw = tt.tw;
+  double2* d_rtw = tt.rtw;
   double B = 0.0;
   for (int i = 0; i <= d->psd_w; ++i) B += 1.0 / (double)(2 * d->psd_w + 1 - i);
   const double T = d->dt * n;
   const double psd_scale = 2.0 / (T * B);
-  double2 *d_tw = nullptr, *d_rtw = nullptr;
-  hipError_t e = hipMallocAsync((void**)&d_tw, tw.size() * sizeof(double2), st);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&d_rtw, rtw.size() * sizeof(double2), st);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_rtw, rtw.data(), rtw.size() * sizeof(double2), hipMemcpyHostToDevice, st);
-  // the twiddles and the periodogram are staged in LDS beside the spectrum when both fit
-  const int staged = M <= 4096 ? 1 : 0;
-  const size_t lds = (size_t)(M + 1) * (sizeof(double2) + (staged ? sizeof(double) : 0));
-  if (e == hipSuccess && lds > 65536)
-    e = hipFuncSetAttribute((const void*)strain_sft_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e == hipSuccess && n_seg > 0) {
-    hipLaunchKernelGGL(strain_sft_kernel, dim3((unsigned)(n_seg * d->n_det)), dim3(kStrainBlock), lds, st, x,
-                       d->n_total, (int32_t)n_seg, logM, d->dt, d->psd_w, psd_scale, d->k_lo, d->n_bins, staged,
-                       d->s_white, d_tw, d_rtw, bins, psd, keep);
-    e = hipGetLastError();
+  // LDS: the M complex points; the periodogram (M + 1 values), the median's sort slots and the
+  // gap flags (each 16-byte aligned after the previous) overlay them once the transform is done
+  size_t lds = (size_t)M * sizeof(double2);
+  int32_t sort_off = 0;
+  int32_t flag_off = (int32_t)(((size_t)(M + 1) * sizeof(double) + 15) / 16 * 16);
+  if (!(d->s_white > 0.0) && d->psd_w <= kMaxSortW) {
+    sort_off = flag_off;
+    flag_off = sort_off + kSortBytes;
   }
-  // the twiddle uploads read host vectors: finish before they go out of scope
-  hipError_t e2 = hipStreamSynchronize(st);
-  if (d_tw) (void)hipFreeAsync(d_tw, st);
-  if (d_rtw) (void)hipFreeAsync(d_rtw, st);
-  if (e == hipSuccess) e = e2;
+  if ((size_t)flag_off + 16 > lds) lds = (size_t)flag_off + 16;
+  const void* kern = nullptr;
+  switch (logM) {
+    case 3: kern = (const void*)strain_sft_kernel<3>; break;
+    case 4: kern = (const void*)strain_sft_kernel<4>; break;
+    case 5: kern = (const void*)strain_sft_kernel<5>; break;
+    case 6: kern = (const void*)strain_sft_kernel<6>; break;
+    case 7: kern = (const void*)strain_sft_kernel<7>; break;
+    case 8: kern = (const void*)strain_sft_kernel<8>; break;
+    case 9: kern = (const void*)strain_sft_kernel<9>; break;
+    case 10: kern = (const void*)strain_sft_kernel<10>; break;
+    case 11: kern = (const void*)strain_sft_kernel<11>; break;
+    case 12: kern = (const void*)strain_sft_kernel<12>; break;
+    case 13: kern = (const void*)strain_sft_kernel<13>; break;
+    default: break;
+  }
+  if (e == hipSuccess && !kern) e = hipErrorInvalidValue;   // n in [16, 16384] was checked above
+  if (e == hipSuccess && lds > 65536) e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess && n_seg > 0) {
+    int32_t a_nseg = (int32_t)n_seg, a_w = d->psd_w, a_klo = d->k_lo, a_nbins = d->n_bins;
+    int64_t a_ntot = d->n_total;
+    double a_dt = d->dt, a_scale = psd_scale, a_white = d->s_white;
+    void* args[] = {(void*)&x, &a_ntot, &a_nseg, &a_dt, &a_w, &a_scale, &a_klo, &a_nbins, &a_white,
+                    &d_tw, &d_rtw, &bins, &psd, &keep, &sort_off, &flag_off};
+    e = hipLaunchKernel(kern, dim3((unsigned)(n_seg * d->n_det)), dim3(kStrainBlock), args, lds, st);
+  }
   if (e != hipSuccess) return strain_fail(SFT_E_DEVICE, hipGetErrorString(e));
   return SFT_OK;
 }

@@ -51,6 +51,29 @@ def test_make_sfts_matches_oracle(n, w):
     _check(x, n, dt, n // 8, n // 4, w)        # an inner band
 
 
+@pytest.mark.parametrize("n", [16, 2048, 16384])
+def test_make_sfts_power_of_two_white_psd(n):
+    """A known white level (no estimate) on the FFT path: the band bins as with the estimate,
+    the PSD the given level everywhere, a gap zeroed; two calls in a row, the second with the
+    segment length's cached twiddle tables."""
+    g = np.random.default_rng(n + 1)
+    dt, S = 1.0 / 64.0, 0.25
+    n_seg = max(3, min(12, (1 << 16) // n))
+    x = g.normal(size=(1, n * n_seg))
+    x[0, n + 1] = np.nan
+    xt = torch.as_tensor(x, device="cuda")
+    ref = oracle.make_sfts(np.nan_to_num(x[0]), n, n_seg, dt)
+    for _ in range(2):
+        bins, psd, keep = sft.make_sfts(xt, n, dt, 1, n // 2 - 1, 0, s_white=S)
+        torch.cuda.synchronize()
+        bins, psd, keep = bins.cpu().numpy()[0], psd.cpu().numpy()[0], keep.cpu().numpy()[0]
+        assert keep[1] == 0 and keep.sum() == n_seg - 1
+        assert not bins[1].any() and not psd[1].any()
+        for a in np.nonzero(keep)[0]:
+            assert np.max(np.abs(bins[a] - ref[a, 1:n // 2])) <= 1e-12 * np.abs(ref[a]).max()
+            assert np.all(psd[a] == S)
+
+
 def test_scan_over_device_made_sfts():
     """Three detectors of white noise at 128 Hz with a Newtonian injection of network SNR ~20
     (about 1 per SFT, the regime of long-duration signals), 32 s SFTs made and whitened on the
