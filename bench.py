@@ -662,6 +662,13 @@ def surrogate_leg(args):
         args.surrogate_samples, args.surrogate_epochs, t_train, np.array2string(hist, precision=2)),
         file=sys.stderr, flush=True)
 
+    train = {"samples": args.surrogate_samples, "epochs": args.surrogate_epochs, "batch": 4096,
+             "targets_s": t_targets, "train_s": t_train, "epoch_loss": [float(v) for v in hist]}
+    if n <= 0:
+        # training only (no bank to scan)
+        s.close()
+        return {"workload": "surrogate training only: MLP 3-%dx%d-2 SiLU on %d 3.5PN samples"
+                            % (hidden, layers, args.surrogate_samples), "train": train}
     out = sft.alloc_out(n, mismatch=True)
     steps = max(1, min(args.steps, 3))
 
@@ -709,8 +716,7 @@ def surrogate_leg(args):
            "network_evals_per_step": evals, "network_fp64_tflop_per_step": mlp_flop / 1e12,
            "fallback_frac": fb, "judge_tol": 1e-4, "network_bf16": lowp,
            "mismatch_median": float(np.median(mm)), "mismatch_p99": float(np.quantile(mm, 0.99)),
-           "train": {"samples": args.surrogate_samples, "epochs": args.surrogate_epochs, "batch": 4096,
-                     "targets_s": t_targets, "train_s": t_train, "epoch_loss": [float(v) for v in hist]}}
+           "train": train}
     print("surrogate scan %.1f ms (plain %.2f ms, 3.5PN %.2f ms), fallback %.4f" % (
         1e3 * t_sur, 1e3 * t_plain, 1e3 * t_pn, fb), file=sys.stderr, flush=True)
     s.close()

@@ -517,11 +517,15 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       BS wre[ND], wim[ND];
 #pragma unroll
       for (int d = 0; d < ND; ++d) wre[d] = wim[d] = (BS)0;
-      // Outer bins: jj >= jup or jj <= jdn puts both endpoints of a lane at least one bin
-      // beyond the asymptotic threshold |p| = SFT_G_VASYM sqrt(beta / 2), with no stationary
-      // point inside the SFT (p- and p+ of one sign).  With the bounds taken over the active
-      // lanes of the wavefront, those bins take the asymptotic form directly, without the
-      // per-lane range test.  Lane bounds are clamped to the window, [-K-1, K+1].
+      // Outer bins: jj >= jup or jj <= jdn puts both endpoints of a lane at or beyond the
+      // asymptotic threshold |p| = SFT_G_VASYM sqrt(beta / 2), with no stationary point inside
+      // the SFT (p- and p+ of one sign): jj >= dp + SFT_G_VASYM sqrt(beta / 2) gives
+      // p+ = dp - jj <= -SFT_G_VASYM sqrt(beta / 2) (the rounding of the bound moves v by a
+      // few ulp, where the dropped series terms stay below 1e-8 of the term).  With the bounds
+      // taken over the active lanes of the wavefront, those bins take the asymptotic form
+      // directly, without the per-lane range test.  Lane bounds are clamped to the window,
+      // [-K-1, K+1], and keep the central bin jj = 0 out of the outer segments (it takes the
+      // table path, or the direct series of a small-drift lane).
       // The same bounds for the larger thresholds at which the series may stop after one or
       // no power of W (ju1/jd1, ju0/jd0) nest outside jup/jdn:
       //   jd0 <= jd1 <= jdn < 0 < jup <= ju1 <= ju0.
@@ -531,10 +535,10 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
       if (K >= SFT_OUTER_MIN_K) {
         const float shb = bp * isq2b;   // sqrt(beta / 2) = beta / sqrt(2 beta)
         auto up = [&](float vt) {
-          return (int)fminf(fmaxf(ceilf(fmaf(vt, shb, dp)) + 1.0f, (float)(-K - 1)), (float)(K + 1));
+          return (int)fminf(fmaxf(ceilf(fmaf(vt, shb, dp)), 1.0f), (float)(K + 1));
         };
         auto dn = [&](float vt) {
-          return -(int)fminf(fmaxf(floorf(fmaf(-vt, shb, dm)) - 1.0f, (float)(-K - 1)), (float)(K + 1));
+          return -(int)fmaxf(fminf(floorf(fmaf(-vt, shb, dm)), -1.0f), (float)(-K - 1));
         };
         jup = wave_max_active(up(SFT_G_VASYM), -K - 1, K + 1);
         jdn = -wave_max_active(dn(SFT_G_VASYM), -K - 1, K + 1);
