@@ -174,6 +174,19 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
+def issue_probe(achieved):
+    """The rates that plain wave64 VALU instructions sustain on this part (probe of 16
+    independent chains per lane), per clock per CU at the nominal 2.4 GHz, and the scan's census
+    rate against the FP32 FMA one: the practical ceiling with packed FP32 left off."""
+    from paper_2502_11823_amd import sft
+    per_clk = {op: sft.probe_issue_rate(op) / (256 * 2.4e9) for op in sft.PROBE}
+    ceiling = per_clk["v_fma_f32"] * 256 * 2.4e9 * 64 / 1e12   # FP32 slots/s of plain FMAs
+    print("issue probe (wave-instr/clk/CU): %s; FP32 FMA ceiling %.1f Tslot/s, scan at %.3f of it"
+          % ({k: round(v, 3) for k, v in per_clk.items()}, ceiling, achieved / ceiling), file=sys.stderr, flush=True)
+    return {"unit": "VALU wave-instructions per clock per CU at 2.4 GHz", "rates": per_clk,
+            "nominal_fp32_rate": 2.0, "fp32_fma_ceiling_tslot_s": ceiling, "frac_of_fma_ceiling": achieved / ceiling}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -200,6 +213,7 @@ def parse():
     p.add_argument("--no-doppler", action="store_true", help="skip the Doppler leg")
     p.add_argument("--no-strain", action="store_true", help="skip the SFT-creation leg")
     p.add_argument("--no-r-study", action="store_true", help="skip the accuracy-study leg")
+    p.add_argument("--no-issue-probe", action="store_true", help="skip the VALU issue-rate probe")
     p.add_argument("--strain-only", action="store_true", help="run only the SFT-creation leg")
     p.add_argument("--paper-shapes", action="store_true",
                    help="context only: time banks shaped like the paper's timing runs and exit")
@@ -328,6 +342,9 @@ def main():
         "graph_ms_per_step": graph_ms,
     }
     print("scan: %.3f ms/step (kernel %.3f ms), %.3e IP/s" % (ms_step, k_ms, value), file=sys.stderr, flush=True)
+    if not args.no_issue_probe:
+        res["roofline"]["issue_probe"] = issue_probe(achieved)
+        args.fma_ceiling = res["roofline"]["issue_probe"]["fp32_fma_ceiling_tslot_s"]
 
     if not args.no_cpu_baseline and args.cpu_sample > 0:
         res["cpu_baseline"] = cpu_baseline(w, out, args.cpu_sample, K, kernel)
@@ -578,7 +595,8 @@ def space_leg(args):
             "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
                          "frac": achieved / (PEAK_SLOTS / 1e12), "kernel": "scan_kernel", "kernel_ms": k_ms,
                          "alg_slots_per_launch": slots, "alg_slots_per_template_sft": slots / census["pairs"],
-                         "bins_by_series": {k: census[k] / census["pairs"] for k in ("w0", "w1", "w3", "table", "stat", "series")}},
+                         "bins_by_series": {k: census[k] / census["pairs"] for k in ("w0", "w1", "w3", "table", "stat", "series")},
+                         "frac_of_fma_ceiling": (achieved / args.fma_ceiling) if getattr(args, "fma_ceiling", None) else None},
             "tuning": best.as_dict(), "flagged_templates": int(np.sum(flags != 0))}
 
 

@@ -555,6 +555,20 @@ sft_status sft_inner_product(const sft_data* data, double mc, double q, double t
 sft_status sft_kernel_timing(int32_t n);
 int32_t sft_kernel_times(float* ms, int32_t max);
 
+/*
+ * Issue-rate probe of the vector ALU, for benchmarks: the scan's roofline counts FP32 slots
+ * against the nominal FP32 vector peak, which needs the packed FP32 instructions that this
+ * library does not use; the probe measures what plain wave64 instructions sustain on the part.
+ * One launch of 2048 workgroups of 256 lanes, each lane 16 independent chains of the chosen
+ * instruction for 4096 iterations (SFT_PROBE_FMA_F32_INT32: 8 FP32 FMA chains beside 8 chains
+ * of a 32-bit shift and xor), timed with HIP events on hip_stream after one warm-up launch, the
+ * best of three.  instr_per_s: host out, VALU wave-instructions per second over the launch.
+ * Synchronous on hip_stream; allocates and frees a 2 MiB device buffer.  Errors: SFT_E_INVALID
+ * (null, unknown probe), SFT_E_DEVICE.
+ */
+enum { SFT_PROBE_FMA_F32 = 0, SFT_PROBE_RCP_F32 = 1, SFT_PROBE_FMA_F64 = 2, SFT_PROBE_FMA_F32_INT32 = 3 };
+sft_status sft_probe_issue_rate(int32_t op, double* instr_per_s, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* sft_last_error(void);
 

@@ -86,7 +86,8 @@ EXPORTS = ["sft_load_data", "sft_free_data", "sft_default_opts", "sft_template_b
            "sft_plan_destroy", "sft_surrogate_param_count", "sft_surrogate_create", "sft_surrogate_free",
            "sft_surrogate_get_params", "sft_surrogate_targets", "sft_surrogate_loss_grad", "sft_surrogate_adam",
            "sft_surrogate_train", "sft_surrogate_infer", "sft_template_bank_scan_noalloc",
-           "sft_set_ephemeris", "sft_make_sfts", "sft_load_strain", "sft_waveform_series", "sft_td_product"]
+           "sft_set_ephemeris", "sft_make_sfts", "sft_load_strain", "sft_waveform_series", "sft_td_product",
+           "sft_probe_issue_rate"]
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 _lib = None
@@ -149,6 +150,8 @@ def lib():
     L.sft_kernel_timing.restype = ctypes.c_int32
     L.sft_kernel_times.argtypes = [P, ctypes.c_int32]
     L.sft_kernel_times.restype = ctypes.c_int32
+    L.sft_probe_issue_rate.argtypes = [ctypes.c_int32, P, P]
+    L.sft_probe_issue_rate.restype = ctypes.c_int32
     I32, I64, F32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     L.sft_surrogate_param_count.argtypes = [I32, I32]
     L.sft_surrogate_param_count.restype = I64
@@ -438,6 +441,17 @@ def kernel_times(max_records: int = 4096):
     buf = (ctypes.c_float * max_records)()
     n = lib().sft_kernel_times(ctypes.cast(buf, ctypes.c_void_p), max_records)
     return [buf[i] for i in range(min(n, max_records))]
+
+
+PROBE = {"v_fma_f32": 0, "v_rcp_f32": 1, "v_fma_f64": 2, "v_fma_f32+int32": 3}
+
+
+def probe_issue_rate(op: str, stream=None) -> float:
+    """VALU wave-instructions per second that one instruction sustains on the device (probe
+    of 16 independent chains per lane; see sft_probe_issue_rate)."""
+    r = ctypes.c_double()
+    _check(lib().sft_probe_issue_rate(PROBE[op], ctypes.cast(ctypes.byref(r), ctypes.c_void_p), _stream_ptr(stream)))
+    return r.value
 
 
 def get_tuning(data: SFTData) -> Tuning:

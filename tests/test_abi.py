@@ -63,6 +63,16 @@ def test_scan_rejects_bad_options():
     assert L.sft_inner_product(None, 1.2, 1.0, 100.0, 0.0, 0, 0, ctypes.byref(opts), z, z, None, None, None, None) == -1
 
 
+def test_issue_probe_host_validation():
+    L = sft.lib()
+    r = ctypes.c_double()
+    assert L.sft_probe_issue_rate(0, None, None) == -1
+    assert L.sft_probe_issue_rate(4, ctypes.cast(ctypes.byref(r), ctypes.c_void_p), None) == -1
+    assert L.sft_probe_issue_rate(-1, ctypes.cast(ctypes.byref(r), ctypes.c_void_p), None) == -1
+    assert sft.last_error().startswith("sft_probe_issue_rate")
+    assert sorted(sft.PROBE.values()) == [0, 1, 2, 3]
+
+
 def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(sft, "_lib", None)
     monkeypatch.setattr(sft, "LIB_PATH", "/nonexistent/libsft.so")

@@ -533,3 +533,13 @@ def test_start_reference_fresnel_ground(ground_small, waveform, K):
     # the two references differ (second order of the Taylor model), by far more than the bar
     m = gpu_scan(data, bank, **dict(kw, t_ref="mid"))
     assert np.max(np.abs(m["zp"] - g["zp"]) / np.sqrt(g["hhp"])) > 1e-3
+
+
+def test_issue_probe_rates():
+    """The VALU issue-rate probe runs and orders its instructions as the hardware does: a
+    quarter-rate transcendental below the plain FP32 FMA, FP64 FMA below FP32 FMA."""
+    per_clk = {op: sft.probe_issue_rate(op) / (256 * 2.4e9) for op in sft.PROBE}
+    print("issue probe, wave-instructions per clock per CU:", per_clk, flush=True)
+    assert all(0.05 < v < 8.0 for v in per_clk.values())
+    assert per_clk["v_rcp_f32"] < per_clk["v_fma_f32"]
+    assert per_clk["v_fma_f64"] < per_clk["v_fma_f32"]
