@@ -32,9 +32,10 @@ METRIC = "template inner products/s at ≤1e-6 rel err; surrogate+FP32 vs plain 
 # conversions, index and address arithmetic are not counted.
 # Peak: the FP32 vector rate, 157.3 TFLOP/s with an FMA as two flops, i.e. 256 CUs x 2.4 GHz
 # x 128 lanes per clock = 78.6e12 slots/s.  Packed FP32 is disabled at compile time; plain
-# wave64 FP32 instructions still issue faster than one per clock per CU: an issue-rate probe
-# with 16 independent FMA chains per lane sustains 1.37 wave-instructions per clock per CU,
-# MUL 1.46, FMA interleaved with 32-bit integer ops 1.58, of the 2.0 this peak implies.
+# wave64 FP32 instructions still issue faster than one per clock per CU: the library's issue-rate
+# probe (16 independent FMA chains per lane, run below right after the timed scan) sustains
+# about 1.5 wave-instructions per clock per CU of the 2.0 this peak implies, and the roofline
+# object also reports the scan against that practical FMA ceiling.
 #
 # Per (template, timestamp group), shared by the detector rows of the group:
 OPS_CHIRP = 2 * 34 + 2      # Newtonian chirp at the SFT midpoint in FP64 (tau, y, s = y^(-1/8)
