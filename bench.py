@@ -72,14 +72,24 @@ OPS_ROW_TAIL = 4 + 4 + 3 + 1 + 1 + 2 + 2
 OPS_ROW1_MAC = 8            # one-row kernel: b e(p-) and b e(p+) per bin (no H'), then
 OPS_ROW1_COMB = 10          # C = E-/2pi S- - E+/2pi S+ once
 SERIES_V = (76.0, 11.0, 4.5)
+# F-statistic form: per present row the cross-norm product F+ Fx and its FMA (FP32); per pair the
+# three norm sums in FP64 (one FP64 add each) instead of two FP32 compensated sums
+OPS_FSTAT_ROW = 2
+OPS_FSTAT_PAIR = 3 * 2 - 2 * 4
+# Doppler form, per (template, row): r.n, v.n, a.n (9 FP64 FMAs), then kappa (1 + v.n),
+# beta (1 + v.n)^2 + kappa a.n T and the fddot scaling (8 FP64 operations)
+OPS_DOPPLER = 2 * (9 + 8)
 OUTER_MIN_K = 4             # narrower windows use the table for every bin
 
 
 def scan_census(mc, t_c, g_tmid, g_rows, T, K, beta_switch, tsun, g_first=None, g_last=None, multi_row=True,
-                stride=64, chunk=256):
+                stride=64, chunk=256, fstat=False, eph=None, sky=None):
     """Algorithmic slots of one scan (the counts above), from the Newtonian chirp of every
     stride-th template at every timestamp group it uses, scaled to the whole bank.  g_rows:
-    SFT rows present per group; g_first/g_last: the template's group range (ragged banks)."""
+    SFT rows present per group; g_first/g_last: the template's group range (ragged banks);
+    fstat: the F-statistic form; eph [n_groups, 9] (r/c, v/c, a/c per group, one row each) and
+    sky [n, 3] (unit vectors toward the sources): the Doppler form, whose chirp is taken at the
+    emission time with f and fdot scaled by the delay's rates."""
     mc = np.asarray(mc, np.float64)
     n = mc.size
     pick = np.arange(0, n, stride)
@@ -90,6 +100,11 @@ def scan_census(mc, t_c, g_tmid, g_rows, T, K, beta_switch, tsun, g_first=None, 
         idx = pick[i0:i0 + chunk]
         M = mc[idx, None] * tsun
         tau = np.asarray(t_c, np.float64)[idx, None] - np.asarray(g_tmid, np.float64)[None, :]
+        if eph is not None:
+            nv = np.asarray(sky, np.float64)[idx]
+            e = np.asarray(eph, np.float64)
+            dl, dl1, dl2 = nv @ e[:, 0:3].T, nv @ e[:, 3:6].T, nv @ e[:, 6:9].T
+            tau = tau - dl
         use = tau > 0
         if g_first is not None:
             gi = np.arange(len(g_tmid))[None, :]
@@ -99,6 +114,10 @@ def scan_census(mc, t_c, g_tmid, g_rows, T, K, beta_switch, tsun, g_first=None, 
         fdot = 96.0 / 5.0 * np.pi ** (8.0 / 3.0) * M ** (5.0 / 3.0) * f ** (11.0 / 3.0)
         kap = f * T
         beta = fdot * T * T
+        if eph is not None:
+            g1 = 1.0 + dl1
+            beta = beta * g1 * g1 + kap * dl2 * T
+            kap = kap * g1
         delta = kap - np.floor(kap + 0.5)
         rows = np.broadcast_to(np.asarray(g_rows, np.float64)[None, :], use.shape)
         fres = use & (np.abs(beta) > beta_switch)
@@ -112,6 +131,10 @@ def scan_census(mc, t_c, g_tmid, g_rows, T, K, beta_switch, tsun, g_first=None, 
         ops = n_pairs * (OPS_CHIRP + OPS_SPLIT + OPS_TAIL) + float(fres.sum()) * OPS_FRESNEL
         ops += float(dirp.sum()) * (OPS_DIRICHLET + nb * OPS_BIN_DIR) + float((rows * dirp).sum()) * nb * 2
         ops += n_rows * OPS_ROW_TAIL
+        if fstat:
+            ops += n_rows * OPS_FSTAT_ROW + n_pairs * OPS_FSTAT_PAIR
+        if eph is not None:
+            ops += n_pairs * OPS_DOPPLER
         for jj in range(-K, K + 1):
             pm, pp = dm - jj, dp - jj
             v = np.minimum(np.abs(pm), np.abs(pp)) * s2b
@@ -173,6 +196,15 @@ def measured_traffic():
     if fields.get("kernel_source_sha256_16", "").strip() != h.hexdigest()[:16]:
         return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def _alu_roofline(achieved, k_ms, slots, args):
+    """Roofline object of a scan-kernel leg: census slots per second against the FP32 vector
+    peak, and against the probed FP32 FMA issue ceiling when the main leg measured it."""
+    ceiling = getattr(args, "fma_ceiling", None)
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
+            "frac": achieved / (PEAK_SLOTS / 1e12), "kernel": "scan_kernel", "kernel_ms": k_ms,
+            "alg_slots_per_launch": slots, "frac_of_fma_ceiling": (achieved / ceiling) if ceiling else None}
 
 
 def issue_probe(achieved):
@@ -433,6 +465,12 @@ def fstat_leg(args, w, data, bank, opts, K):
                       a_cross=1.0, fstat=True)
     err = float(np.max(np.abs(f2[idx] - ref["twoF"]) / np.maximum(ref["twoF"], 4.0)))
     value = w.n_templates * args.steps / elapsed
+    g_t, g_rows = np.unique(w.t_start, return_counts=True)
+    slots, _ = scan_census(w.bank["mc"], w.bank["t_c"], g_t + 0.5 * w.t_sft, g_rows, w.t_sft, K, 1e-7,
+                           sft.T_SUN, multi_row=True, fstat=True)
+    achieved = slots / (k_ms * 1e-3) / 1e12
+    print("fstat census: %.3e slots, %.1f Tslot/s, %.3f of the FP32 peak"
+          % (slots, achieved, achieved / (PEAK_SLOTS / 1e12)), file=sys.stderr, flush=True)
     print("fstat: %.3f ms/step (kernel %.3f ms), %.3e IP/s, max e(2F) %.2e on 40 templates"
           % (1e3 * elapsed / args.steps, k_ms, value, err), file=sys.stderr, flush=True)
     return {"workload": "F-statistic form of the ground scan (same data, bank, K, launch shape): z+, zx, "
@@ -440,7 +478,8 @@ def fstat_leg(args, w, data, bank, opts, K):
             "value": value, "unit": "IP/s", "ms_per_step": 1e3 * elapsed / args.steps, "kernel_ms": k_ms,
             "twoF_median": float(np.median(f2)), "twoF_mean": float(np.mean(f2)),
             "degenerate_frac": float(np.mean((flags & sft.FLAG_FSTAT_DEGENERATE) != 0)),
-            "max_err_2F_vs_oracle_40": err}
+            "max_err_2F_vs_oracle_40": err,
+            "roofline": _alu_roofline(achieved, k_ms, slots, args)}
 
 
 def r_study_leg():
@@ -541,10 +580,16 @@ def doppler_leg(args, w, opts, K):
     value = w.n_templates * args.steps / elapsed
     print("doppler: %.3f ms/step (kernel %.3f ms), %.3e IP/s" % (1e3 * elapsed / args.steps, k_ms, value),
           file=sys.stderr, flush=True)
+    # every SFT row its own group (one-row kernel), its chirp at the emission time
+    slots, _ = scan_census(w.bank["mc"], w.bank["t_c"], tm, np.ones(w.n_sft), w.t_sft, K, 1e-7, sft.T_SUN,
+                           multi_row=False, eph=eph, sky=bank_h["sky"], stride=128)
+    achieved = slots / (k_ms * 1e-3) / 1e12
+    print("doppler census: %.3e slots, %.1f Tslot/s, %.3f of the FP32 peak"
+          % (slots, achieved, achieved / (PEAK_SLOTS / 1e12)), file=sys.stderr, flush=True)
     return {"workload": "Doppler form of the ground scan: 3 detector sites (Earth orbit + rotation), "
                         "random sky position per template, one SFT row per timestamp group",
             "value": value, "unit": "IP/s", "ms_per_step": 1e3 * elapsed / args.steps, "kernel_ms": k_ms,
-            "tuning": best.as_dict()}
+            "tuning": best.as_dict(), "roofline": _alu_roofline(achieved, k_ms, slots, args)}
 
 
 def space_leg(args):

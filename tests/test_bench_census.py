@@ -64,3 +64,44 @@ def test_stride_sample_scales_to_the_bank():
     samp, cs = bench.scan_census(mc, t_c, g_tmid, g_rows, T, 8, 0.0, TSUN, stride=4)
     assert cs["pairs"] == pytest.approx(cf["pairs"], rel=0.05)
     assert samp == pytest.approx(full, rel=0.05)
+
+
+def test_fstat_census_adds_the_cross_norm():
+    mc, t_c, g_tmid, g_rows, T = _bank()
+    plain, c = bench.scan_census(mc, t_c, g_tmid, g_rows, T, 8, 0.0, TSUN, stride=1)
+    fs, cf = bench.scan_census(mc, t_c, g_tmid, g_rows, T, 8, 0.0, TSUN, stride=1, fstat=True)
+    use = (t_c[:, None] - g_tmid[None, :]) > 0
+    rows = float((use * g_rows[None, :]).sum())
+    assert cf == c
+    assert fs - plain == pytest.approx(rows * bench.OPS_FSTAT_ROW + c["pairs"] * bench.OPS_FSTAT_PAIR)
+
+
+def test_doppler_census_limits():
+    """A zero ephemeris is the one-row census plus the delay arithmetic; a constant delay r.n is
+    the one-row census of the bank with t_c - r.n; the rates move the frequency and the drift."""
+    mc, t_c, g_tmid, _, T = _bank()
+    ones = np.ones(g_tmid.size)
+    rng = np.random.default_rng(5)
+    sky = rng.normal(size=(mc.size, 3))
+    sky /= np.linalg.norm(sky, axis=1, keepdims=True)
+    base, c0 = bench.scan_census(mc, t_c, g_tmid, ones, T, 8, 0.0, TSUN, multi_row=False, stride=1)
+    eph = np.zeros((g_tmid.size, 9))
+    dop, c1 = bench.scan_census(mc, t_c, g_tmid, ones, T, 8, 0.0, TSUN, multi_row=False, stride=1,
+                                eph=eph, sky=sky)
+    assert c1 == c0
+    assert dop - base == pytest.approx(c0["pairs"] * bench.OPS_DOPPLER)
+    # a constant delay along x: t_c - r n_x for every template
+    r = 3.0
+    eph[:, 0] = r
+    dop, c2 = bench.scan_census(mc, t_c, g_tmid, ones, T, 8, 0.0, TSUN, multi_row=False, stride=1,
+                                eph=eph, sky=sky)
+    shifted, c3 = bench.scan_census(mc, t_c - r * sky[:, 0], g_tmid, ones, T, 8, 0.0, TSUN,
+                                    multi_row=False, stride=1)
+    assert c2 == c3
+    assert dop - shifted == pytest.approx(c3["pairs"] * bench.OPS_DOPPLER)
+    # a large v.n shifts every frequency: the classification of the bins changes
+    eph[:, 0] = 0.0
+    eph[:, 3] = 0.3
+    _, c4 = bench.scan_census(mc, t_c, g_tmid, ones, T, 8, 0.0, TSUN, multi_row=False, stride=1,
+                              eph=eph, sky=np.tile([1.0, 0.0, 0.0], (mc.size, 1)))
+    assert c4["pairs"] == c0["pairs"] and c4 != c0
