@@ -307,7 +307,7 @@ def main():
         best = sft.get_tuning(data)
         print("fixed tuning %s" % best.as_dict(), file=sys.stderr, flush=True)
     else:
-        best, best_ms = sft.autotune(data, bank, opts, out=out, reps=2)
+        best, best_ms = sft.autotune(data, bank, opts, out=out, reps=3)
         torch.cuda.synchronize()
         print("autotune %.1f s: %s -> %.3f ms" % (time.time() - t0, best.as_dict(), best_ms), file=sys.stderr,
               flush=True)
@@ -611,7 +611,7 @@ def space_leg(args):
         best = sft.get_tuning(data)
         print("fixed tuning %s" % best.as_dict(), file=sys.stderr, flush=True)
     else:
-        best, best_ms = sft.autotune(data, bank, opts, out=out, reps=2)
+        best, best_ms = sft.autotune(data, bank, opts, out=out, reps=3)
     for _ in range(args.warmup):
         sft.template_bank_scan(data, bank, opts, out=out)
     torch.cuda.synchronize()
