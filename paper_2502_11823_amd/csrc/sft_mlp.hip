@@ -294,16 +294,24 @@ __global__ void sum_parts_kernel(const double* __restrict__ part, int n, double 
   if (threadIdx.x == 0) out[0] = (float)(red[0] * scale);
 }
 
-// sum of `planes` planes of `count` values into dst (fixed order; the loop is unrolled so that
-// many planes' loads are in flight at once, the additions keep their order)
-__global__ void sum_planes_kernel(const float* __restrict__ src, int planes, int64_t count, float* __restrict__ dst)
+// Sum of the K-slice planes of a weight gradient, in a fixed order: a workgroup takes 64
+// consecutive elements, its four wavefronts a quarter of the planes each (summed in plane
+// order, their loads in flight together), then the four partial sums in wavefront order.
+__global__ __launch_bounds__(256) void sum_planes_kernel(const float* __restrict__ src, int planes, int64_t count,
+                                                         float* __restrict__ dst)
 {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const int p0 = wv * planes / 4, p1 = (wv + 1) * planes / 4;
   float s = 0.f;
+  if (i < count) {
 #pragma unroll 16
-  for (int p = 0; p < planes; ++p) s += src[(int64_t)p * count + i];
-  dst[i] = s;
+    for (int p = p0; p < p1; ++p) s += src[(int64_t)p * count + i];
+  }
+  part[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && i < count) dst[i] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
@@ -862,7 +870,8 @@ static hipError_t loss_grad(sft_surrogate* s, const float* U, const float* Tg, i
     if ((e = gemm_epi<true, false, kEpiColSum>(ly.n_in, ly.n_out, (int)B, Hl, ly.n_in, G, ly.n_out, t.plane,
                                                 ly.n_out, t.splits, pc, nullptr, nullptr, st)) != hipSuccess)
       return e;
-    hipLaunchKernelGGL(sum_planes_kernel, dim3(nblk(pc)), dim3(256), 0, st, t.plane, planes, pc, s->grad + ly.w_off);
+    hipLaunchKernelGGL(sum_planes_kernel, dim3((unsigned)((pc + 63) / 64)), dim3(256), 0, st, t.plane, planes, pc,
+                       s->grad + ly.w_off);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (l > 0) {
       // dL/dZ_{l-1} = (G W^T) * SiLU'(Z_{l-1})
