@@ -37,10 +37,11 @@ __device__ inline double2 cmul(double2 a, double2 b)
 // Median of each lane's block by a wavefront-wide sort: the 64 lanes of a wavefront take 64
 // consecutive band bins, whose blocks of 2w+1 periodogram values lie in a union of at most
 // 64 + 2w <= 128 bins.  The union's (value, bin) pairs are sorted once per wavefront by a
-// bitonic network in the wavefront's LDS slot (one compare-exchange per lane and stage, the
-// 28 stages unrolled and free of branches), then every lane walks the sorted list and stops at
-// the (w+1)-th entry that falls in its block: the block's middle element in (value, bin) order,
-// as a sort of the block itself gives.
+// bitonic network held in registers (two pairs per lane, the partner of each compare-exchange
+// fetched across lanes; the 28 stages unrolled and free of branches) and stored in the
+// wavefront's LDS slot, then every lane walks the sorted list and stops at the (w+1)-th entry
+// that falls in its block: the block's middle element in (value, bin) order, as a sort of the
+// block itself gives.
 constexpr int kSortN = 128;
 constexpr int kMaxSortW = (kSortN - 64) / 2;   // w <= 32
 // LDS bytes of the sort slots of a workgroup: kSortN values and kSortN bins (relative to the
@@ -57,6 +58,77 @@ __device__ inline void wave_sync()
 __device__ inline bool pair_less(double va, int ia, double vb, int ib)
 {
   return (va < vb) | ((va == vb) & (ia < ib));   // no short circuit: selects, not branches
+}
+
+// The 32-bit value of lane (lane ^ S) of the wavefront: quad permutes for S = 1, 2, a half-row
+// mirror then a quad reversal for S = 4 ((i ^ 7) ^ 3 = i ^ 4 within each 8 lanes), a rotation
+// by 8 within each row of 16 for S = 8 (all on the vector ALU); a swizzle in xor mode within 32
+// lanes for S = 16 and a backward permute for S = 32.
+template <int S>
+__device__ inline int lane_xor(int v, int lane)
+{
+  if constexpr (S == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  else if constexpr (S == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  else if constexpr (S == 4) {
+    const int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+    return __builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, false);           // quad_perm [3,2,1,0]
+  } else if constexpr (S == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);   // row_ror:8
+  else if constexpr (S == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);   // and 0x1f, xor 0x10
+  else return __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
+}
+
+template <int S>
+__device__ inline void xchg_pair(double v, int i, int lane, double& pv, int& pi)
+{
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_xor<S>((int)(b & 0xffffffffll), lane);
+  const int hi = lane_xor<S>((int)(b >> 32), lane);
+  pv = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+  pi = lane_xor<S>(i, lane);
+}
+
+// One compare-exchange stage of the bitonic network on kSortN = 128 (value, bin) pairs held two
+// per lane: element `lane` in (a, ia), element `lane + 64` in (b, ib).  Stride 64 pairs the two
+// elements of a lane; smaller strides pair an element with the same one of lane ^ STRIDE, and
+// the lower member of the pair keeps the smaller (up) or the larger (down) of the two.
+template <int SIZE, int STRIDE>
+__device__ inline void bitonic_stage(double& a, int& ia, double& b, int& ib, int lane)
+{
+  if constexpr (STRIDE == 64) {
+    // SIZE = 128: every pair ascending
+    const bool sw = pair_less(b, ib, a, ia);
+    const double ta = a;
+    const int tia = ia;
+    a = sw ? b : a;
+    ia = sw ? ib : ia;
+    b = sw ? ta : b;
+    ib = sw ? tia : ib;
+  } else {
+    const bool lower = (lane & STRIDE) == 0;
+    const int qlo = lane & ~STRIDE;
+    double pa, pb;
+    int pia, pib;
+    xchg_pair<STRIDE>(a, ia, lane, pa, pia);
+    xchg_pair<STRIDE>(b, ib, lane, pb, pib);
+    // keep the smaller of the pair when this lane holds the lower member of an ascending pair
+    // or the upper member of a descending one
+    const bool mina = lower == ((qlo & SIZE) == 0);
+    const bool minb = lower == (((qlo + 64) & SIZE) == 0);
+    const bool ta = mina ? pair_less(pa, pia, a, ia) : pair_less(a, ia, pa, pia);
+    const bool tb = minb ? pair_less(pb, pib, b, ib) : pair_less(b, ib, pb, pib);
+    a = ta ? pa : a;
+    ia = ta ? pia : ia;
+    b = tb ? pb : b;
+    ib = tb ? pib : ib;
+  }
+}
+
+template <int SIZE, int STRIDE>
+__device__ inline void bitonic_from(double& a, int& ia, double& b, int& ib, int lane)
+{
+  bitonic_stage<SIZE, STRIDE>(a, ia, b, ib, lane);
+  if constexpr (STRIDE > 1) bitonic_from<SIZE, STRIDE / 2>(a, ia, b, ib, lane);
+  else if constexpr (SIZE < kSortN) bitonic_from<SIZE * 2, SIZE>(a, ia, b, ib, lane);
 }
 
 // Transform of the M = 2^LOGM complex points in LDS (natural order in, digit-reversed out), as
@@ -326,32 +398,15 @@ __global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
       u1 = u1 < 0 ? 0 : u1;
       u1 = u1 + 2 * w > M ? M - 2 * w : u1;
       const int L = u1 + N - u0;                // <= 64 + 2w <= kSortN
-      for (int q = lane; q < kSortN; q += 64) {
-        sv[q] = q < L ? P(u0 + q) : INFINITY;
-        si[q] = q < L ? q : 0x7fffffff;
-      }
+      // the kSortN pairs sorted in registers (two per lane), then stored in sorted order
+      double a = lane < L ? P(u0 + lane) : INFINITY, b = lane + 64 < L ? P(u0 + lane + 64) : INFINITY;
+      int ia = lane < L ? lane : 0x7fffffff, ib = lane + 64 < L ? lane + 64 : 0x7fffffff;
+      bitonic_from<2, 1>(a, ia, b, ib, lane);
+      sv[lane] = a;
+      si[lane] = ia;
+      sv[lane + 64] = b;
+      si[lane + 64] = ib;
       wave_sync();
-      // bitonic sort of the kSortN pairs: lane l compare-exchanges one pair per stage.  The
-      // pairs of a stage are disjoint, so each lane writes both members back (exchanged or
-      // not) right after reading them; the sync orders the stage's writes before the next
-      // stage's reads.
-#pragma unroll
-      for (int size = 2; size <= kSortN; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-          const int q = 2 * lane - (lane & (stride - 1));   // lower index of lane's pair
-          const int r = q + stride;
-          const bool up = (q & size) == 0;
-          const double vq = sv[q], vr = sv[r];
-          const int iq = si[q], ir = si[r];
-          const bool swap = up ? pair_less(vr, ir, vq, iq) : pair_less(vq, iq, vr, ir);
-          sv[q] = swap ? vr : vq;
-          si[q] = swap ? ir : iq;
-          sv[r] = swap ? vq : vr;
-          si[r] = swap ? iq : ir;
-          wave_sync();
-        }
-      }
       // every lane counts, along the sorted list, the entries inside its own block; its median
       // is the entry at which that count reaches w + 1.  The bins are read as broadcasts, four
       // per read, in a wave-uniform loop without an early exit (the pads past L are in no
