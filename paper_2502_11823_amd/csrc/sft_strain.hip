@@ -39,14 +39,15 @@ __device__ inline double2 cmul(double2 a, double2 b)
 // 64 + 2w <= 128 bins.  The union's (value, bin) pairs are sorted once per wavefront by a
 // bitonic network held in registers (two pairs per lane, the partner of each compare-exchange
 // fetched across lanes; the 28 stages unrolled and free of branches) and stored in the
-// wavefront's LDS slot, then every lane walks the sorted list and stops at the (w+1)-th entry
-// that falls in its block: the block's middle element in (value, bin) order, as a sort of the
-// block itself gives.
+// wavefront's LDS slot; every lane then finds the (w+1)-th entry of the sorted list that falls in
+// its block (a binary search over prefix masks of the list's bins): the block's middle element in
+// (value, bin) order, as a sort of the block itself gives.
 constexpr int kSortN = 128;
 constexpr int kMaxSortW = (kSortN - 64) / 2;   // w <= 32
-// LDS bytes of the sort slots of a workgroup: kSortN values and kSortN bins (relative to the
-// union's first bin) per wavefront
-constexpr int kSortBytes = kStrainBlock / 64 * kSortN * (int)(sizeof(double) + sizeof(int));
+// LDS bytes of the sort slots of a workgroup: per wavefront the kSortN sorted values, then for
+// every position of the sorted list the 128-bit mask of the union bins (relative to the union's
+// first bin) that it and the entries before it hold
+constexpr int kSortBytes = kStrainBlock / 64 * kSortN * (int)(sizeof(double) + sizeof(uint4));
 
 __device__ inline void wave_sync()
 {
@@ -121,6 +122,20 @@ __device__ inline void bitonic_stage(double& a, int& ia, double& b, int& ib, int
     b = tb ? pb : b;
     ib = tb ? pib : ib;
   }
+}
+
+// Inclusive OR-scan of a 32-bit word over the 64 lanes: shifts by 1, 2, 4, 8 within each row of
+// 16 lanes (zero shifted in), then the last lane of rows 0 and 2 into rows 1 and 3, and lane 31
+// into rows 2 and 3.
+__device__ inline uint32_t wave_or_scan(uint32_t x)
+{
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);    // row_shr:1
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);    // row_shr:2
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);    // row_shr:4
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);    // row_shr:8
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);   // row_bcast:15
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);   // row_bcast:31
+  return x;
 }
 
 template <int SIZE, int STRIDE>
@@ -386,8 +401,8 @@ __global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
   } else if (w <= kMaxSortW) {
     const int lane = tid & 63, wv = tid >> 6;
     double* sv = reinterpret_cast<double*>(reinterpret_cast<char*>(buf) + sort_off) + wv * kSortN;
-    int* si = reinterpret_cast<int*>(reinterpret_cast<char*>(buf) + sort_off + (kStrainBlock / 64) * kSortN * 8) +
-              wv * kSortN;
+    uint4* pm = reinterpret_cast<uint4*>(reinterpret_cast<char*>(buf) + sort_off + (kStrainBlock / 64) * kSortN * 8) +
+                wv * kSortN;
     // every wavefront walks its chunks of 64 band bins (wave-uniform loop)
     for (int c0 = wv * 64; c0 < n_bins; c0 += blockDim.x) {
       const int kb = k_lo + c0;
@@ -402,36 +417,47 @@ __global__ __launch_bounds__(kStrainBlock) void strain_sft_kernel(
       double a = lane < L ? P(u0 + lane) : INFINITY, b = lane + 64 < L ? P(u0 + lane + 64) : INFINITY;
       int ia = lane < L ? lane : 0x7fffffff, ib = lane + 64 < L ? lane + 64 : 0x7fffffff;
       bitonic_from<2, 1>(a, ia, b, ib, lane);
+      // prefix masks of the sorted list: bit j of pm[q] is set when union bin j is one of the
+      // entries 0..q (an OR-scan of one-hot masks over the lanes, the second half of the list
+      // on top of the first; the pads set no bit)
+      uint32_t sa[4], sb[4];
+#pragma unroll
+      for (int wd = 0; wd < 4; ++wd) {
+        sa[wd] = wave_or_scan((ia >> 5) == wd ? 1u << (ia & 31) : 0u);
+        const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)sa[wd], 63);
+        sb[wd] = wave_or_scan((ib >> 5) == wd ? 1u << (ib & 31) : 0u) | t;
+      }
       sv[lane] = a;
-      si[lane] = ia;
       sv[lane + 64] = b;
-      si[lane + 64] = ib;
+      pm[lane] = make_uint4(sa[0], sa[1], sa[2], sa[3]);
+      pm[lane + 64] = make_uint4(sb[0], sb[1], sb[2], sb[3]);
       wave_sync();
-      // every lane counts, along the sorted list, the entries inside its own block; its median
-      // is the entry at which that count reaches w + 1.  The bins are read as broadcasts, four
-      // per read, in a wave-uniform loop without an early exit (the pads past L are in no
-      // block), and the lane keeps the list position of its median, whose value it reads last.
+      // The count of a lane's block entries among the sorted entries 0..q is the popcount of
+      // pm[q] under the block's mask and grows with q; the block's median is the entry at which
+      // it reaches w + 1: the smallest such q, by a binary search (7 steps over kSortN).
       const int i = c0 + lane;
       const int k = k_lo + i;
       int s0 = k - w;
       s0 = s0 < 0 ? 0 : s0;
       s0 = s0 + 2 * w > M ? M - 2 * w : s0;
-      const unsigned s0r = (unsigned)(s0 - u0);   // the block's first bin in the union
-      int cnt = 0, mq = 0;
-      const int4* si4 = reinterpret_cast<const int4*>(si);
-#pragma unroll 4
-      for (int q4 = 0; q4 < (L + 3) / 4; ++q4) {
-        const int4 j4 = si4[q4];
-        auto step = [&](int j, int q) {
-          const bool in = (unsigned)j - s0r < (unsigned)N;
-          mq = (in && cnt == w) ? q : mq;
-          cnt += in ? 1 : 0;
-        };
-        step(j4.x, 4 * q4);
-        step(j4.y, 4 * q4 + 1);
-        step(j4.z, 4 * q4 + 2);
-        step(j4.w, 4 * q4 + 3);
+      const int s0r = s0 - u0;   // the block's first bin in the union
+      uint32_t wm[4];
+#pragma unroll
+      for (int wd = 0; wd < 4; ++wd) {
+        const int lo = min(max(s0r - 32 * wd, 0), 32), hi = min(max(s0r + N - 32 * wd, 0), 32);
+        wm[wd] = (uint32_t)(((1ull << hi) - 1ull) & ~((1ull << lo) - 1ull));
       }
+      int qlo = 0, qhi = kSortN - 1;
+#pragma unroll
+      for (int it = 0; it < 7; ++it) {
+        const int mid = (qlo + qhi) >> 1;
+        const uint4 p = pm[mid];
+        const int c = __builtin_popcount(p.x & wm[0]) + __builtin_popcount(p.y & wm[1]) +
+                      __builtin_popcount(p.z & wm[2]) + __builtin_popcount(p.w & wm[3]);
+        if (c >= w + 1) qhi = mid;
+        else qlo = mid + 1;
+      }
+      const int mq = qlo;
       const double med = sv[mq];
       if (i < n_bins) po[i] = psd_scale * (dt * dt) * med;
       wave_sync();
