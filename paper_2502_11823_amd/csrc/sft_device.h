@@ -281,6 +281,10 @@ __device__ inline float2 fres_endpoint_asym(float p, float bq)
   }
 }
 
+// PRE: read the interval's coefficients before the Horner steps, so that their LDS reads are in
+// flight together (the one-row kernels, where the table bins are many; the multi-row kernels keep
+// the interleaved reads, which need fewer registers)
+template <bool PRE = false>
 __device__ inline float2 fres_endpoint2(float p, float bq, float sq2ob, float tsc, const float2* tab)
 {
   const float v = fabsf(p) * sq2ob;
@@ -290,11 +294,26 @@ __device__ inline float2 fres_endpoint2(float p, float bq, float sq2ob, float ts
   i = i > 0 ? i : 0;
   const float u = v - ((float)i + 0.5f) * SFT_G_WIDTH;
   const float2* cc = tab + i * (SFT_G_DEG + 1);
-  float gr = cc[SFT_G_DEG].x, gi = cc[SFT_G_DEG].y;
+  float gr, gi;
+  if constexpr (PRE) {
+    float2 c[SFT_G_DEG + 1];
 #pragma unroll
-  for (int k = SFT_G_DEG - 1; k >= 0; --k) {
-    gr = fmaf(gr, u, cc[k].x);
-    gi = fmaf(gi, u, cc[k].y);
+    for (int k = 0; k <= SFT_G_DEG; ++k) c[k] = cc[k];
+    gr = c[SFT_G_DEG].x;
+    gi = c[SFT_G_DEG].y;
+#pragma unroll
+    for (int k = SFT_G_DEG - 1; k >= 0; --k) {
+      gr = fmaf(gr, u, c[k].x);
+      gi = fmaf(gi, u, c[k].y);
+    }
+  } else {
+    gr = cc[SFT_G_DEG].x;
+    gi = cc[SFT_G_DEG].y;
+#pragma unroll
+    for (int k = SFT_G_DEG - 1; k >= 0; --k) {
+      gr = fmaf(gr, u, cc[k].x);
+      gi = fmaf(gi, u, cc[k].y);
+    }
   }
   const float sc = p < 0.0f ? -tsc : tsc;
   return make_float2(gr * sc, gi * sc);

@@ -592,8 +592,8 @@ __device__ __forceinline__ void scan_item(const ScanArgs& a, const int K, const 
             ep.y = -ep.y;
           }
         } else {
-          em = fres_endpoint2(pm, bq, sq2ob, tsc, tab);
-          ep = fres_endpoint2(pp, bq, sq2ob, tsc, tab);
+          em = fres_endpoint2<ND == 1>(pm, bq, sq2ob, tsc, tab);
+          ep = fres_endpoint2<ND == 1>(pp, bq, sq2ob, tsc, tab);
           if (NEG) {
             em.y = -em.y;
             ep.y = -ep.y;
