@@ -267,8 +267,8 @@ def copy_calibration():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (got --gpus %d); the scan would shard "
-              "templates across GPUs with no exchange, which is not built here" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only (got --gpus %d); the scan would shard "
+              "templates across GPUs with no exchange, which is not implemented here" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -1,6 +1,6 @@
 // sft_probe.hip -- issue-rate probe of the vector ALU.  The scan kernel's roofline counts FP32
 // lane-operation slots against the nominal FP32 vector peak, which assumes the packed FP32
-// instructions (two FP32 operations per lane and instruction); this build leaves those off, so
+// instructions (two FP32 operations per lane and instruction); this library leaves those off, so
 // the rate that plain wave64 instructions actually sustain on the part is the practical ceiling.
 // Each lane runs 16 independent chains of one instruction for a fixed number of iterations,
 // over a grid that fills every CU several times; the rate is in wave-instructions per second.
