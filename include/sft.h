@@ -385,8 +385,9 @@ sft_status sft_set_tuning(sft_data* data, const sft_tuning* tuning);
 /*
  * sft_autotune -- time candidate tunings (block 64/128/256, 1..64 chunks, plain and
  * persistent grids) on the given bank in its given order with HIP events on hip_stream,
- * reps timed runs each after one warm-up; then time the fastest with SFT_ORDER_TRACK (sort
- * included) and keep that order when it is faster.  Store the result in the handle and
+ * reps timed runs each after one warm-up; time the candidates within 2% of the fastest twice
+ * more, in turn, and take the best of those repeated times; then time the fastest with
+ * SFT_ORDER_TRACK (sort included) and keep that order when it is faster.  Store the result in the handle and
  * return it (best, best_ms may be NULL).  Writes the outputs like a scan.  Synchronises
  * hip_stream.
  * Errors: those of sft_template_bank_scan, SFT_E_RANGE (reps outside [1, 100]).
